@@ -1,0 +1,241 @@
+/* rt.h -- C ABI of the MI355X Riemannian ray tracer.
+ *
+ * The engine answers the question of the paper's "Riemannian shading"
+ * (Novello, da Silva, Velho, "Design and visualization of Riemannian
+ * metrics", Sec. 4): for every direction v of the observer field at a point
+ * p, follow the geodesic gamma with gamma(0) = p, gamma'(0) = v -- the
+ * exponential map of Sec. 3.4 -- and report what it hits.  The geodesic is
+ * the solution of the geodesic flow x' = y, y' = -Gamma(y, y) (Eq. 3.3),
+ * marched with a Runge-Kutta or Euler step (Sec. 4.1, Eq. 4.1), each step's
+ * segment tested against the scene (Sec. 4.1).  The hit point, the
+ * parameter t at the hit, the object id and the final direction are
+ * returned per pixel; colours are left to the caller (Sec. 4, last
+ * paragraph: pseudo-colour from the hit coordinates).
+ *
+ * Conventions shared by every entry point:
+ *  - All functions return rt_status (RT_OK = 0).  On any error nothing is
+ *    written to caller buffers and rt_last_error() explains.
+ *  - Host pointers (metric, scene, camera, rule structs and the arrays they
+ *    point to) are read during the call only; the context keeps copies.
+ *  - Device pointers (rt_outputs) are caller-owned device memory on the
+ *    context's device; the caller keeps them alive until the stream work
+ *    finishes.
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream); all
+ *    device work is enqueued on it asynchronously, in call order.
+ *  - A context is not thread-safe; use one context per host thread.  Calls
+ *    that enqueue work on one context must not overlap on two streams.
+ *  - Per-pixel outcomes are encoded in the id output, never in the status:
+ *    id >= 0 hit object, -1 miss (step budget or t_max reached),
+ *    -2 numerical failure (non-finite state, singular Jacobian, step size
+ *    below h_min).
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_ABI_VERSION 1
+
+typedef enum rt_status {
+    RT_OK = 0,
+    RT_EINVAL = -1,       /* bad argument (null pointer, bad size, non-finite value) */
+    RT_ENOMEM = -2,       /* device or host allocation failed */
+    RT_EDEVICE = -3,      /* HIP runtime error, no device, or an asynchronous fault */
+    RT_EUNSUPPORTED = -4, /* combination not implemented (kind x step rule) */
+    RT_ESTATE = -5        /* metric or scene not set, or host-only context */
+} rt_status;
+
+typedef struct rt_ctx rt_ctx;
+
+/* Library ABI version (RT_ABI_VERSION of the build). */
+int rt_abi_version(void);
+
+/* Create a context on HIP device `hip_device`.  hip_device = -1 creates a
+ * host-only context: every argument check runs, nothing is launched, and
+ * rt_trace returns RT_ESTATE after validation.  *out is set to NULL on
+ * failure; the message is then available from rt_last_error(NULL). */
+rt_status rt_create(int hip_device, rt_ctx **out);
+
+/* Release the context and its device memory (waits for its streams' work
+ * to finish first).  NULL is ignored. */
+void rt_destroy(rt_ctx *ctx);
+
+/* Human-readable message for the last failing call on ctx (NULL ctx: the
+ * last failing rt_create on this thread).  Empty string if none.  The
+ * pointer stays valid until the next call on the same context. */
+const char *rt_last_error(const rt_ctx *ctx);
+
+/* ------------------------------------------------------------------ metric
+ * RT_METRIC_EUCLID           flat R^3 (Gamma = 0).
+ * RT_METRIC_GRAPH_GAUSS      pull-back of the graph of f: R^3 -> R
+ *                            (Sec. 5.1): g = I + grad f grad f^T (Eq. 5.2),
+ *                            Gamma^m_ij = f_m f_ij / (1 + |grad f|^2)
+ *                            (Eq. 5.3), flow Eq. 5.4; f is a sum of
+ *                            isotropic Gaussians a exp(-|x-c|^2/(2 sigma^2))
+ *                            (Eq. 6.1 with equal spreads; sums as in
+ *                            Sec. 6.2, "Summing functions").
+ * RT_METRIC_PULLBACK_TWIST   pull-back g = J^T J (Eq. 5.6) of the radial
+ *                            twist phi(x) = x + amp tanh|x| R_z(theta) x,
+ *                            theta = theta0 exp(-|x|^2); Gamma from Thm 5.1
+ *                            (Eq. 5.7), flow Eq. 5.8.
+ * RT_METRIC_PULLBACK_ZTWIST  pull-back of the z-twist of Sec. 5.2,
+ *                            Phi(x,y,z) = (cos z x - sin z y,
+ *                                          sin z x + cos z y, z).
+ */
+typedef enum rt_metric_kind {
+    RT_METRIC_EUCLID = 0,
+    RT_METRIC_GRAPH_GAUSS = 1,
+    RT_METRIC_PULLBACK_TWIST = 2,
+    RT_METRIC_PULLBACK_ZTWIST = 3
+} rt_metric_kind;
+
+typedef struct rt_bump {
+    float a;          /* amplitude */
+    float cx, cy, cz; /* centre */
+    float sigma;      /* spread, > 0 */
+} rt_bump;
+
+typedef struct rt_metric {
+    int kind;            /* rt_metric_kind */
+    int n_sets;          /* independent parameter sets traced side by side, 1..64 */
+    int n_bumps;         /* bumps per set, 0..64 (GRAPH_GAUSS only) */
+    const rt_bump *bumps;/* host, [n_sets][n_bumps], row-major */
+    float twist_amp;     /* PULLBACK_TWIST amplitude (0.4 in the 4K workload), 0 <= amp <= 1 */
+    float twist_theta0;  /* PULLBACK_TWIST peak angle (1.2), |theta0| <= 1.5 */
+    float cull_sigmas;   /* a bump is ignored where |x - c| > cull_sigmas * sigma;
+                            >= 4, 6 recommended (exp(-18) is below FP32 resolution) */
+} rt_metric;
+
+/* Copy and validate the metric: finite values, sigma > 0, sizes in range.
+ * Replaces any previous metric. */
+rt_status rt_set_metric(rt_ctx *ctx, const rt_metric *metric);
+
+/* ------------------------------------------------------------------- scene
+ * Object ids: spheres 0..n_spheres-1, then planes, then tori.  Each object
+ * has an implicit function, > 0 outside, <= 0 inside:
+ *   sphere |x - c|^2 - r^2 ; plane n.x - d ; torus (axis a, |a| = 1) the
+ *   signed distance sqrt((|x_perp| - R)^2 + x_par^2) - r.                  */
+typedef struct rt_sphere { float cx, cy, cz, r; } rt_sphere;
+typedef struct rt_plane { float nx, ny, nz, d; } rt_plane;
+typedef struct rt_torus { float cx, cy, cz, ax, ay, az, R, r; } rt_torus;
+
+typedef struct rt_scene {
+    int n_spheres;             /* 0..256 */
+    const rt_sphere *spheres;  /* host */
+    int n_planes;              /* 0..8 */
+    const rt_plane *planes;    /* host; |n| = 1 */
+    int n_tori;                /* 0..8 */
+    const rt_torus *tori;      /* host; |a| = 1, 0 < r < R */
+} rt_scene;
+
+/* Copy and validate the scene.  Replaces any previous scene. */
+rt_status rt_set_scene(rt_ctx *ctx, const rt_scene *scene);
+
+/* ------------------------------------------------------------------ camera
+ * Pinhole at eye.  The paper leaves the observer field open (Sec. 4); this
+ * ABI uses: vertical field of view vfov_deg, pixel centres, column i to
+ * the right, row 0 at the top, right = up x forward.  The initial velocity
+ * is the pixel direction scaled to unit length in the metric g at the eye,
+ * so t is Riemannian arc length (exp_p(v) = gamma(|v|), Sec. 3.4). */
+typedef struct rt_camera {
+    float eye[3], forward[3], up[3];
+    float vfov_deg; /* (0, 180) */
+    int width, height; /* >= 1, width * height * n_sets <= 2^31 - 1 */
+} rt_camera;
+
+/* --------------------------------------------------------------- step rule
+ * RT_STEP_RK4    classical fixed-step Runge-Kutta, step h.
+ * RT_STEP_RK45   Dormand-Prince 5(4), first trial step h, error control on
+ *                the RMS of h*sum(b - bhat)k over the 6 state components
+ *                scaled by atol + rtol*max(|z|, |z_new|); step factor
+ *                clamp(0.9 err^(-1/5), 0.2, 5), h <= h_max, the last step
+ *                clipped to t_max; a step below h_min fails the ray (id -2).
+ * RT_STEP_EULER  the paper's explicit Euler march (Eq. 4.1), step h.
+ * A ray stops at the first accepted step whose segment meets the scene; the
+ * hit is then refined in double precision by bisection of the step fraction
+ * s on the sign of the object's implicit function along the partial step of
+ * the same integrator (bisect_iters halvings; a grazing sphere segment with
+ * no sign change keeps the segment's root).  Otherwise it stops after
+ * max_steps accepted steps or when t reaches t_max (miss). */
+typedef enum rt_step_kind { RT_STEP_RK4 = 0, RT_STEP_RK45 = 1, RT_STEP_EULER = 2 } rt_step_kind;
+
+typedef struct rt_step_rule {
+    int kind;          /* rt_step_kind */
+    float h;           /* step (RK4/Euler) or first trial step (RK45), > 0 */
+    float rtol, atol;  /* RK45 tolerances, > 0 */
+    float h_min, h_max;/* RK45 step bounds, 0 < h_min <= h_max */
+    float t_max;       /* > 0; RK4/Euler rays also stop at max_steps */
+    int cull_every;    /* K: steps between per-wave re-culls of bumps/objects, 1..256 (16) */
+    int pass_steps;    /* S: steps per launch before surviving rays are compacted, >= 16 (256) */
+    int bisect_iters;  /* FP64 bisection halvings for the hit, 0..60 (40) */
+    int flags;         /* RT_FLAG_* bits, 0 for a plain trace */
+} rt_step_rule;
+
+/* RT_FLAG_TIMING: record HIP events on the stream around every kernel of the
+ *   trace; rt_get_stats then reports their durations.
+ * RT_FLAG_COUNT_WORK: run the instrumented kernel variant that also counts,
+ *   per lane, the work the method needs (acceleration evaluations, bumps
+ *   inside their cut sphere, objects inside the lane's own window); same
+ *   outputs, slower.  Used to compute algorithmic FLOP counts. */
+#define RT_FLAG_TIMING 1
+#define RT_FLAG_COUNT_WORK 2
+
+/* ----------------------------------------------------------------- outputs
+ * Caller-owned device arrays, indexed [set][row][column] (pixel index
+ * p = (set*height + j)*width + i):
+ *   hit   float[.][3]  hit point (miss/failure: final position)
+ *   t     float[.]     geodesic parameter at the hit / at termination
+ *   id    int32[.]     object id, -1 miss, -2 numerical failure
+ *   dir   float[.][3]  unit Euclidean direction of the velocity there
+ *   steps int32[.]     accepted steps taken, including the hit step
+ *                      (optional: NULL skips it)                        */
+typedef struct rt_outputs {
+    float *hit;
+    float *t;
+    int32_t *id;
+    float *dir;
+    int32_t *steps;
+} rt_outputs;
+
+/* Trace every pixel of every parameter set.  Requires rt_set_metric and
+ * rt_set_scene.  Asynchronous on hip_stream; scratch memory sized for the
+ * largest frame seen so far is kept by the context.  max_steps in
+ * 1..1000000.  RT_EUNSUPPORTED if the step kind is unknown. */
+rt_status rt_trace(rt_ctx *ctx, const rt_camera *camera, const rt_step_rule *rule,
+                   int max_steps, const rt_outputs *out, void *hip_stream);
+
+/* Wait for the context's work on hip_stream and report any asynchronous
+ * device error as RT_EDEVICE. */
+rt_status rt_sync(rt_ctx *ctx, void *hip_stream);
+
+/* Counters of the last rt_trace (read after its work finished; this call
+ * waits for the context's last stream). */
+typedef struct rt_stats {
+    uint64_t rays;          /* rays launched */
+    uint64_t ray_steps;     /* accepted integration steps, all rays */
+    uint64_t attempts;      /* RK45 trial steps incl. rejected; = ray_steps otherwise */
+    uint64_t wave_iters;    /* wave-wide step iterations */
+    uint64_t lane_iters;    /* active lanes summed over wave iterations */
+    uint64_t bump_list_sum; /* culled bump-list length summed over wave iterations */
+    uint64_t obj_list_sum;  /* culled object-list length summed over wave iterations */
+    uint64_t refined;       /* hits refined in FP64 */
+    uint64_t acc_evals;     /* COUNT_WORK: lane acceleration evaluations */
+    uint64_t bump_evals;    /* COUNT_WORK: lane bump terms with |x - c| inside the cut */
+    uint64_t obj_tests;     /* COUNT_WORK: lane segment tests against objects in the lane's own window */
+    int passes;             /* kernel passes launched */
+    float pass_ms;          /* TIMING: summed duration of the integration passes */
+    float refine_ms;        /* TIMING: duration of the FP64 refinement kernel */
+    float total_ms;         /* TIMING: reset + passes + refinement */
+} rt_stats;
+
+rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_H */

@@ -1,0 +1,516 @@
+// C-ABI of the tracer: argument validation, device copies of the metric and
+// scene, the per-context workspace, launch sizing and statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+#include "rt_internal.hpp"
+
+namespace {
+thread_local std::string g_create_error;
+
+constexpr int MAX_BUMPS = 64, MAX_SETS = 64, MAX_SPHERES = 256, MAX_PLANES = 8, MAX_TORI = 8;
+}  // namespace
+
+struct rt_ctx {
+    int device = -1;
+    bool host_only = true;
+    std::string err;
+    int n_cu = 256;
+    // metric (host copy)
+    bool has_metric = false;
+    int kind = 0, n_sets = 1, n_bumps = 0;
+    float amp = 0.f, th0 = 0.f, cull = 6.f;
+    std::vector<rt_bump> bumps;
+    // scene (host copy)
+    bool has_scene = false;
+    std::vector<rt_sphere> sph;
+    std::vector<rt_plane> pln;
+    std::vector<rt_torus> tor;
+    // device copies
+    void *d_bump_f = nullptr, *d_bump_d = nullptr, *d_scene = nullptr;
+    size_t bump_f_bytes = 0, bump_d_bytes = 0, scene_bytes = 0;
+    rti::DeviceData dd{};
+    // workspace
+    float *d_q[2] = {nullptr, nullptr};
+    int64_t q_cap = 0;  // rays the workspace holds
+    float4 *d_rec = nullptr;
+    int *d_ctr = nullptr;
+    unsigned long long *d_stats = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool traced = false;
+    int last_passes = 0;
+    bool last_timed = false;
+    std::vector<hipEvent_t> ev;  // timing events of the last trace
+};
+
+static rt_status fail(rt_ctx *c, rt_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+static rt_status hip_fail(rt_ctx *c, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? RT_ENOMEM : RT_EDEVICE, m);
+}
+
+static bool finite(float v) { return std::isfinite(v); }
+
+extern "C" {
+
+int rt_abi_version(void) { return RT_ABI_VERSION; }
+
+rt_status rt_create(int hip_device, rt_ctx **out) {
+    if (!out) {
+        g_create_error = "rt_create: out is NULL";
+        return RT_EINVAL;
+    }
+    *out = nullptr;
+    g_create_error.clear();
+    if (hip_device < -1) {
+        g_create_error = "rt_create: device must be >= -1";
+        return RT_EINVAL;
+    }
+    rt_ctx *c = new (std::nothrow) rt_ctx();
+    if (!c) {
+        g_create_error = "rt_create: out of host memory";
+        return RT_ENOMEM;
+    }
+    if (hip_device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || hip_device >= n) {
+            g_create_error = std::string("rt_create: no HIP device ") + std::to_string(hip_device) + " (" +
+                             (e != hipSuccess ? hipGetErrorString(e) : "index out of range") + ")";
+            delete c;
+            return RT_EDEVICE;
+        }
+        hipDeviceProp_t prop;
+        if ((e = hipSetDevice(hip_device)) != hipSuccess || (e = hipGetDeviceProperties(&prop, hip_device)) != hipSuccess) {
+            g_create_error = std::string("rt_create: ") + hipGetErrorString(e);
+            delete c;
+            return RT_EDEVICE;
+        }
+        c->device = hip_device;
+        c->host_only = false;
+        c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        e = hipMalloc((void **)&c->d_stats, sizeof(unsigned long long) * rti::ST_N);
+        if (e != hipSuccess) {
+            g_create_error = std::string("rt_create: ") + hipGetErrorString(e);
+            delete c;
+            return RT_ENOMEM;
+        }
+        hipMemset(c->d_stats, 0, sizeof(unsigned long long) * rti::ST_N);
+    }
+    *out = c;
+    return RT_OK;
+}
+
+void rt_destroy(rt_ctx *c) {
+    if (!c) return;
+    if (!c->host_only) {
+        hipSetDevice(c->device);
+        hipDeviceSynchronize();
+        hipFree(c->d_bump_f);
+        hipFree(c->d_bump_d);
+        hipFree(c->d_scene);
+        hipFree(c->d_q[0]);
+        hipFree(c->d_q[1]);
+        hipFree(c->d_rec);
+        hipFree(c->d_ctr);
+        hipFree(c->d_stats);
+        for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    }
+    delete c;
+}
+
+const char *rt_last_error(const rt_ctx *c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+static rt_status sync_last(rt_ctx *c) {
+    if (c->host_only || !c->traced) return RT_OK;
+    hipError_t e = hipStreamSynchronize(c->last_stream);
+    if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+    return RT_OK;
+}
+
+static rt_status upload(rt_ctx *c, void **dst, size_t *cap, const void *src, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (*cap < bytes) {
+        hipFree(*dst);
+        *dst = nullptr;
+        *cap = 0;
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        *cap = bytes;
+    }
+    hipError_t e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy");
+    return RT_OK;
+}
+
+rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
+    if (!c) return RT_EINVAL;
+    if (!m) return fail(c, RT_EINVAL, "rt_set_metric: metric is NULL");
+    if (m->kind < RT_METRIC_EUCLID || m->kind > RT_METRIC_PULLBACK_ZTWIST)
+        return fail(c, RT_EUNSUPPORTED, "rt_set_metric: unknown metric kind " + std::to_string(m->kind));
+    if (m->n_sets < 1 || m->n_sets > MAX_SETS)
+        return fail(c, RT_EINVAL, "rt_set_metric: n_sets must be in 1..64");
+    int nb = m->kind == RT_METRIC_GRAPH_GAUSS ? m->n_bumps : 0;
+    if (nb < 0 || nb > MAX_BUMPS) return fail(c, RT_EINVAL, "rt_set_metric: n_bumps must be in 0..64");
+    if (nb > 0 && !m->bumps) return fail(c, RT_EINVAL, "rt_set_metric: bumps is NULL");
+    if (!finite(m->cull_sigmas) || m->cull_sigmas < 4.0f)
+        return fail(c, RT_EINVAL, "rt_set_metric: cull_sigmas must be finite and >= 4");
+    if (m->kind == RT_METRIC_PULLBACK_TWIST) {
+        if (!finite(m->twist_amp) || m->twist_amp < 0.f || m->twist_amp > 1.f)
+            return fail(c, RT_EINVAL, "rt_set_metric: twist_amp must be in [0, 1]");
+        if (!finite(m->twist_theta0) || std::fabs(m->twist_theta0) > 1.5f)
+            return fail(c, RT_EINVAL, "rt_set_metric: |twist_theta0| must be <= 1.5");
+    }
+    size_t n = (size_t)m->n_sets * nb;
+    for (size_t i = 0; i < n; ++i) {
+        const rt_bump &b = m->bumps[i];
+        if (!finite(b.a) || !finite(b.cx) || !finite(b.cy) || !finite(b.cz) || !finite(b.sigma))
+            return fail(c, RT_EINVAL, "rt_set_metric: non-finite bump parameter at " + std::to_string(i));
+        if (!(b.sigma > 0.f)) return fail(c, RT_EINVAL, "rt_set_metric: sigma must be > 0 at " + std::to_string(i));
+    }
+    std::vector<float> bf(std::max<size_t>(n, 1) * 8, 0.f);
+    std::vector<double> bd(std::max<size_t>(n, 1) * 8, 0.0);
+    const double log2e = 1.4426950408889634;
+    for (size_t i = 0; i < n; ++i) {
+        const rt_bump &b = m->bumps[i];
+        double s = b.sigma;
+        double cut = (double)m->cull_sigmas * s;
+        bf[8 * i + 0] = b.cx;
+        bf[8 * i + 1] = b.cy;
+        bf[8 * i + 2] = b.cz;
+        bf[8 * i + 3] = (float)(-log2e / (2.0 * s * s));
+        bf[8 * i + 4] = (float)((double)b.a / (s * s));
+        bf[8 * i + 5] = (float)(1.0 / (s * s));
+        bf[8 * i + 6] = (float)(cut * cut);
+        bd[8 * i + 0] = b.a;
+        bd[8 * i + 1] = b.cx;
+        bd[8 * i + 2] = b.cy;
+        bd[8 * i + 3] = b.cz;
+        bd[8 * i + 4] = b.sigma;
+        bd[8 * i + 5] = cut * cut;
+    }
+    if (!c->host_only) {
+        rt_status st = sync_last(c);
+        if (st != RT_OK) return st;
+        hipSetDevice(c->device);
+        if ((st = upload(c, &c->d_bump_f, &c->bump_f_bytes, bf.data(), bf.size() * sizeof(float))) != RT_OK) return st;
+        if ((st = upload(c, &c->d_bump_d, &c->bump_d_bytes, bd.data(), bd.size() * sizeof(double))) != RT_OK) return st;
+        c->dd.bump_f = (const float4 *)c->d_bump_f;
+        c->dd.bump_d = (const double *)c->d_bump_d;
+    }
+    c->kind = m->kind;
+    c->n_sets = m->n_sets;
+    c->n_bumps = nb;
+    c->amp = m->twist_amp;
+    c->th0 = m->twist_theta0;
+    c->cull = m->cull_sigmas;
+    c->bumps.assign(m->bumps, m->bumps + n);
+    c->has_metric = true;
+    c->err.clear();
+    return RT_OK;
+}
+
+rt_status rt_set_scene(rt_ctx *c, const rt_scene *s) {
+    if (!c) return RT_EINVAL;
+    if (!s) return fail(c, RT_EINVAL, "rt_set_scene: scene is NULL");
+    if (s->n_spheres < 0 || s->n_spheres > MAX_SPHERES) return fail(c, RT_EINVAL, "rt_set_scene: n_spheres must be in 0..256");
+    if (s->n_planes < 0 || s->n_planes > MAX_PLANES) return fail(c, RT_EINVAL, "rt_set_scene: n_planes must be in 0..8");
+    if (s->n_tori < 0 || s->n_tori > MAX_TORI) return fail(c, RT_EINVAL, "rt_set_scene: n_tori must be in 0..8");
+    if ((s->n_spheres && !s->spheres) || (s->n_planes && !s->planes) || (s->n_tori && !s->tori))
+        return fail(c, RT_EINVAL, "rt_set_scene: NULL object array");
+    for (int i = 0; i < s->n_spheres; ++i) {
+        const rt_sphere &o = s->spheres[i];
+        if (!finite(o.cx) || !finite(o.cy) || !finite(o.cz) || !finite(o.r) || !(o.r > 0.f))
+            return fail(c, RT_EINVAL, "rt_set_scene: bad sphere " + std::to_string(i));
+    }
+    for (int i = 0; i < s->n_planes; ++i) {
+        const rt_plane &o = s->planes[i];
+        float n2 = o.nx * o.nx + o.ny * o.ny + o.nz * o.nz;
+        if (!finite(o.nx) || !finite(o.ny) || !finite(o.nz) || !finite(o.d) || std::fabs(n2 - 1.f) > 1e-4f)
+            return fail(c, RT_EINVAL, "rt_set_scene: bad plane " + std::to_string(i) + " (need |n| = 1)");
+    }
+    for (int i = 0; i < s->n_tori; ++i) {
+        const rt_torus &o = s->tori[i];
+        float a2 = o.ax * o.ax + o.ay * o.ay + o.az * o.az;
+        bool ok = finite(o.cx) && finite(o.cy) && finite(o.cz) && finite(o.ax) && finite(o.ay) && finite(o.az) &&
+                  finite(o.R) && finite(o.r) && std::fabs(a2 - 1.f) <= 1e-4f && o.r > 0.f && o.R > o.r;
+        if (!ok) return fail(c, RT_EINVAL, "rt_set_scene: bad torus " + std::to_string(i));
+    }
+    if (!c->host_only) {
+        // one allocation: f32 spheres | f32 planes | f32 tori | f64 spheres | f64 planes | f64 tori
+        size_t ns = s->n_spheres, np = s->n_planes, nt = s->n_tori;
+        size_t off_pf = ns * 16, off_tf = off_pf + np * 16, end_f = off_tf + nt * 32;
+        size_t off_sd = (end_f + 255) & ~(size_t)255;
+        size_t off_pd = off_sd + ns * 32, off_td = off_pd + np * 32, total = off_td + nt * 64;
+        std::vector<char> buf(total + 16, 0);
+        float *f = (float *)buf.data();
+        for (size_t i = 0; i < ns; ++i) std::memcpy(f + 4 * i, &s->spheres[i], 16);
+        std::memcpy(buf.data() + off_pf, s->planes, np * 16);
+        std::memcpy(buf.data() + off_tf, s->tori, nt * 32);
+        double *sd = (double *)(buf.data() + off_sd);
+        for (size_t i = 0; i < ns; ++i) {
+            sd[4 * i + 0] = s->spheres[i].cx;
+            sd[4 * i + 1] = s->spheres[i].cy;
+            sd[4 * i + 2] = s->spheres[i].cz;
+            sd[4 * i + 3] = s->spheres[i].r;
+        }
+        double *pd = (double *)(buf.data() + off_pd);
+        for (size_t i = 0; i < np; ++i) {
+            pd[4 * i + 0] = s->planes[i].nx;
+            pd[4 * i + 1] = s->planes[i].ny;
+            pd[4 * i + 2] = s->planes[i].nz;
+            pd[4 * i + 3] = s->planes[i].d;
+        }
+        double *td = (double *)(buf.data() + off_td);
+        for (size_t i = 0; i < nt; ++i) {
+            const float *t = &s->tori[i].cx;
+            for (int k = 0; k < 8; ++k) td[8 * i + k] = t[k];
+        }
+        rt_status st = sync_last(c);
+        if (st != RT_OK) return st;
+        hipSetDevice(c->device);
+        if ((st = upload(c, &c->d_scene, &c->scene_bytes, buf.data(), buf.size())) != RT_OK) return st;
+        char *b = (char *)c->d_scene;
+        c->dd.sph_f = (const float4 *)b;
+        c->dd.pln_f = (const float4 *)(b + off_pf);
+        c->dd.tor_f = (const float *)(b + off_tf);
+        c->dd.sph_d = (const double *)(b + off_sd);
+        c->dd.pln_d = (const double *)(b + off_pd);
+        c->dd.tor_d = (const double *)(b + off_td);
+    }
+    c->sph.assign(s->spheres, s->spheres + s->n_spheres);
+    c->pln.assign(s->planes, s->planes + s->n_planes);
+    c->tor.assign(s->tori, s->tori + s->n_tori);
+    c->has_scene = true;
+    c->err.clear();
+    return RT_OK;
+}
+
+// Ray queues (2 x Q_NFIELDS floats per ray), refine records (REC_F4 float4
+// per ray) and the counter block, sized for `cap` rays; grow-only.
+static rt_status ensure_workspace(rt_ctx *c, int64_t cap) {
+    hipError_t e;
+    if (!c->d_ctr) {
+        e = hipMalloc((void **)&c->d_ctr, sizeof(int) * (rti::CTR_PASS0 + rti::MAX_PASSES_API * rti::CTR_PASS_WORDS));
+        if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (counters)");
+    }
+    if (c->q_cap >= cap) return RT_OK;
+    rt_status st = sync_last(c);
+    if (st != RT_OK) return st;
+    hipFree(c->d_q[0]);
+    hipFree(c->d_q[1]);
+    hipFree(c->d_rec);
+    c->d_q[0] = c->d_q[1] = nullptr;
+    c->d_rec = nullptr;
+    c->q_cap = 0;
+    size_t qb = (size_t)cap * rti::Q_NFIELDS * sizeof(float);
+    if ((e = hipMalloc((void **)&c->d_q[0], qb)) != hipSuccess || (e = hipMalloc((void **)&c->d_q[1], qb)) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_rec, (size_t)cap * rti::REC_F4 * sizeof(float4))) != hipSuccess) {
+        hipFree(c->d_q[0]);
+        hipFree(c->d_q[1]);
+        hipFree(c->d_rec);
+        c->d_q[0] = c->d_q[1] = nullptr;
+        c->d_rec = nullptr;
+        return hip_fail(c, e, "hipMalloc (workspace)");
+    }
+    c->q_cap = cap;
+    return RT_OK;
+}
+
+rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
+                   void *stream) {
+    if (!c) return RT_EINVAL;
+    if (!cam || !r || !o) return fail(c, RT_EINVAL, "rt_trace: NULL camera, rule or outputs");
+    if (!c->has_metric || !c->has_scene) return fail(c, RT_ESTATE, "rt_trace: set the metric and the scene first");
+    for (int k = 0; k < 3; ++k)
+        if (!finite(cam->eye[k]) || !finite(cam->forward[k]) || !finite(cam->up[k]))
+            return fail(c, RT_EINVAL, "rt_trace: non-finite camera vector");
+    if (!finite(cam->vfov_deg) || cam->vfov_deg <= 0.f || cam->vfov_deg >= 180.f)
+        return fail(c, RT_EINVAL, "rt_trace: vfov_deg must be in (0, 180)");
+    if (cam->width < 1 || cam->height < 1) return fail(c, RT_EINVAL, "rt_trace: width and height must be >= 1");
+    int64_t hw = (int64_t)cam->width * cam->height;
+    if (hw * c->n_sets > 2147483647LL) return fail(c, RT_EINVAL, "rt_trace: width*height*n_sets exceeds 2^31-1");
+    // camera basis: right = up x forward, up' = forward x right
+    double f[3] = {cam->forward[0], cam->forward[1], cam->forward[2]};
+    double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fn > 0)) return fail(c, RT_EINVAL, "rt_trace: zero forward vector");
+    for (double &v : f) v /= fn;
+    const float *u = cam->up;
+    double rt[3] = {u[1] * f[2] - u[2] * f[1], u[2] * f[0] - u[0] * f[2], u[0] * f[1] - u[1] * f[0]};
+    double rn = std::sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+    if (!(rn > 1e-12)) return fail(c, RT_EINVAL, "rt_trace: up is parallel to forward");
+    for (double &v : rt) v /= rn;
+    double up[3] = {f[1] * rt[2] - f[2] * rt[1], f[2] * rt[0] - f[0] * rt[2], f[0] * rt[1] - f[1] * rt[0]};
+
+    if (r->kind < RT_STEP_RK4 || r->kind > RT_STEP_EULER)
+        return fail(c, RT_EUNSUPPORTED, "rt_trace: unknown step kind " + std::to_string(r->kind));
+    if (!finite(r->h) || !(r->h > 0.f)) return fail(c, RT_EINVAL, "rt_trace: h must be finite and > 0");
+    if (!finite(r->t_max) || !(r->t_max > 0.f)) return fail(c, RT_EINVAL, "rt_trace: t_max must be finite and > 0");
+    if (r->kind == RT_STEP_RK45) {
+        if (!(r->rtol > 0.f) || !(r->atol > 0.f) || !finite(r->rtol) || !finite(r->atol))
+            return fail(c, RT_EINVAL, "rt_trace: rtol and atol must be finite and > 0");
+        if (!(r->h_min > 0.f) || !(r->h_max >= r->h_min) || !finite(r->h_max))
+            return fail(c, RT_EINVAL, "rt_trace: need 0 < h_min <= h_max");
+    }
+    if (r->cull_every < 1 || r->cull_every > 256) return fail(c, RT_EINVAL, "rt_trace: cull_every must be in 1..256");
+    if (r->pass_steps < 16) return fail(c, RT_EINVAL, "rt_trace: pass_steps must be >= 16");
+    if (r->bisect_iters < 0 || r->bisect_iters > 60) return fail(c, RT_EINVAL, "rt_trace: bisect_iters must be in 0..60");
+    if (r->flags & ~(RT_FLAG_TIMING | RT_FLAG_COUNT_WORK)) return fail(c, RT_EINVAL, "rt_trace: unknown flag bits");
+    if (max_steps < 1 || max_steps > 1000000) return fail(c, RT_EINVAL, "rt_trace: max_steps must be in 1..1000000");
+    int n_passes = (max_steps + r->pass_steps - 1) / r->pass_steps;
+    if (n_passes > rti::MAX_PASSES_API)
+        return fail(c, RT_EINVAL, "rt_trace: max_steps / pass_steps must be <= " + std::to_string(rti::MAX_PASSES_API));
+    if (!o->hit || !o->t || !o->id || !o->dir) return fail(c, RT_EINVAL, "rt_trace: NULL output pointer");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_trace: host-only context (created with device -1)");
+
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    int64_t cap = hw * c->n_sets;
+    rt_status st = ensure_workspace(c, cap);
+    if (st != RT_OK) return st;
+
+    rti::TraceArgs a{};
+    a.kind = c->kind;
+    a.n_sets = c->n_sets;
+    a.n_bumps = c->n_bumps;
+    a.twist_amp = c->amp;
+    a.twist_theta0 = c->th0;
+    a.n_spheres = (int)c->sph.size();
+    a.n_planes = (int)c->pln.size();
+    a.n_tori = (int)c->tor.size();
+    for (int k = 0; k < 3; ++k) {
+        a.eye[k] = cam->eye[k];
+        a.right[k] = (float)rt[k];
+        a.up[k] = (float)up[k];
+        a.fwd[k] = (float)f[k];
+    }
+    a.tan_half = (float)std::tan(0.5 * (double)cam->vfov_deg * M_PI / 180.0);
+    a.aspect = (float)((double)cam->width / (double)cam->height);
+    a.width = cam->width;
+    a.height = cam->height;
+    a.tiles_x = (cam->width + 7) / 8;
+    a.tiles_y = (cam->height + 7) / 8;
+    a.step_kind = r->kind;
+    a.h = r->h;
+    a.rtol = r->rtol;
+    a.atol = r->atol;
+    a.h_min = r->h_min;
+    a.h_max = r->kind == RT_STEP_RK45 ? r->h_max : r->h;
+    a.t_max = r->t_max;
+    a.max_steps = max_steps;
+    a.K = r->cull_every;
+    a.S = r->pass_steps;
+    a.bisect_iters = r->bisect_iters;
+    a.count = (r->flags & RT_FLAG_COUNT_WORK) ? 1 : 0;
+    // Culling window: before the next re-cull a lane moves at most K+1 steps
+    // of Euclidean length <= h_max * vmax.  A g-unit velocity has Euclidean
+    // speed <= 1 wherever g >= I: always for the graph metric
+    // (g = I + grad f grad f^T), and for the twist, whose Jacobian has
+    // smallest singular value >= 1 (vmax carries a 5% safety factor there).
+    // The z-twist has g < I away from its axis and is not culled.
+    float vmax = c->kind == RT_METRIC_PULLBACK_TWIST ? 1.05f : 1.0f;
+    a.cull_margin = c->kind == RT_METRIC_PULLBACK_ZTWIST ? -1.0f
+                                                         : (float)((r->cull_every + 1) * (double)a.h_max * vmax * 1.02 + 1e-4);
+    a.q[0] = c->d_q[0];
+    a.q[1] = c->d_q[1];
+    a.cap = cap;
+    a.ctr = c->d_ctr;
+    a.stats = c->d_stats;
+    a.rec = c->d_rec;
+    a.out_hit = o->hit;
+    a.out_t = o->t;
+    a.out_dir = o->dir;
+    a.out_id = o->id;
+    a.out_steps = o->steps;
+
+    int bpc = rti::trace_blocks_per_cu(a.kind, a.step_kind);
+    int64_t chunks = cap / 64 + 1;
+    int64_t grid = (int64_t)c->n_cu * bpc;
+    if (grid * 4 > chunks) grid = (chunks + 3) / 4;
+    if (grid < 1) grid = 1;
+    int rgrid = (int)std::min<int64_t>((cap + 255) / 256, (int64_t)c->n_cu * 8);
+    if (rgrid < 1) rgrid = 1;
+    if (const char *g = std::getenv("RT_GRID_BLOCKS")) {
+        int v = std::atoi(g);
+        if (v >= 1) grid = v;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    bool timed = (r->flags & RT_FLAG_TIMING) != 0;
+    if (timed) {
+        while ((int)c->ev.size() < n_passes + 3) {
+            hipEvent_t ev;
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+            c->ev.push_back(ev);
+        }
+    }
+    e = rti::launch_trace(a, c->dd, n_passes, (int)grid, rgrid, s, timed ? c->ev.data() : nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    c->last_stream = s;
+    c->traced = true;
+    c->last_passes = n_passes;
+    c->last_timed = timed;
+    c->err.clear();
+    return RT_OK;
+}
+
+rt_status rt_sync(rt_ctx *c, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (c->host_only) return RT_OK;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "rt_sync");
+    return RT_OK;
+}
+
+rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
+    if (!c || !out) return c ? fail(c, RT_EINVAL, "rt_get_stats: out is NULL") : RT_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    if (c->host_only || !c->traced) return RT_OK;
+    rt_status st = sync_last(c);
+    if (st != RT_OK) return st;
+    unsigned long long v[rti::ST_N];
+    hipError_t e = hipMemcpy(v, c->d_stats, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "rt_get_stats");
+    out->rays = v[rti::ST_RAYS];
+    out->ray_steps = v[rti::ST_STEPS];
+    out->attempts = v[rti::ST_ATTEMPTS];
+    out->wave_iters = v[rti::ST_WAVE_ITERS];
+    out->lane_iters = v[rti::ST_LANE_ITERS];
+    out->bump_list_sum = v[rti::ST_BUMP_LIST];
+    out->obj_list_sum = v[rti::ST_OBJ_LIST];
+    out->refined = v[rti::ST_REFINED];
+    out->acc_evals = v[rti::ST_ACC_EVALS];
+    out->bump_evals = v[rti::ST_BUMP_EVALS];
+    out->obj_tests = v[rti::ST_OBJ_TESTS];
+    out->passes = c->last_passes;
+    if (c->last_timed) {
+        float ms = 0.f, pass = 0.f;
+        int np = c->last_passes;
+        for (int p = 0; p < np; ++p) {
+            if ((e = hipEventElapsedTime(&ms, c->ev[1 + p], c->ev[2 + p])) != hipSuccess) return hip_fail(c, e, "timing");
+            pass += ms;
+        }
+        out->pass_ms = pass;
+        if ((e = hipEventElapsedTime(&ms, c->ev[1 + np], c->ev[2 + np])) != hipSuccess) return hip_fail(c, e, "timing");
+        out->refine_ms = ms;
+        if ((e = hipEventElapsedTime(&ms, c->ev[0], c->ev[2 + np])) != hipSuccess) return hip_fail(c, e, "timing");
+        out->total_ms = ms;
+    }
+    return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+// Device building blocks of the geodesic tracer for gfx950 (CDNA4, wave64).
+//
+// One lane integrates one ray.  Per-wave state that is the same for all
+// lanes (culled bump and object lists, set index) lives in scalar registers:
+// the bump list is a 64-bit mask walked with s_ff1 and the bump parameters
+// are fetched with scalar loads, so the vector ALU consumes them directly as
+// SGPR operands.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtd {
+
+enum { KIND_EUCLID = 0, KIND_GRAPH = 1, KIND_TWIST = 2, KIND_ZTWIST = 3 };
+enum { STEP_RK4 = 0, STEP_RK45 = 1, STEP_EULER = 2 };
+
+constexpr int MAX_BUMPS = 64;
+constexpr int MAX_SETS = 64;
+constexpr int MAX_SPHERES = 256;
+constexpr int MAX_PLANES = 8;
+constexpr int MAX_TORI = 8;
+constexpr int MAX_PASSES = 512;
+constexpr int N_XCD = 8;
+
+// ------------------------------------------------------------------ vectors
+template <class T> struct V3 {
+    T x, y, z;
+};
+template <class T> __device__ __forceinline__ V3<T> mk(T x, T y, T z) { return V3<T>{x, y, z}; }
+template <class T> __device__ __forceinline__ V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T> __device__ __forceinline__ V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T> __device__ __forceinline__ V3<T> operator*(T s, V3<T> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class T> __device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+// a + s*b
+template <class T> __device__ __forceinline__ V3<T> axpy(T s, V3<T> b, V3<T> a) { return {a.x + s * b.x, a.y + s * b.y, a.z + s * b.z}; }
+
+// --------------------------------------------------------------- math shims
+// Single precision uses the hardware transcendental units (v_exp_f32,
+// v_rcp_f32, v_sqrt_f32, v_sin/cos_f32); double uses the device libm.
+__device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double exp2_(double x) { return exp2(x); }
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ void sincos_(float x, float *s, float *c) { *s = __sinf(x); *c = __cosf(x); }
+__device__ __forceinline__ void sincos_(double x, double *s, double *c) { sincos(x, s, c); }
+template <class T> __device__ __forceinline__ T log2e_() { return T(1.4426950408889634); }
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int u = __shfl_up(v, o);
+        if (l >= o) v += u;
+    }
+    return v;
+}
+// rank of this lane among the set bits of m below it
+__device__ __forceinline__ int mbcnt64(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+// ------------------------------------------------------ metric parameters
+// Graph metric, one bump, packed for single precision (two float4):
+//   B0 = (cx, cy, cz, nk)   nk = -log2(e) / (2 sigma^2)  so exp(-r^2/2s^2) = exp2(nk r^2)
+//   B1 = (as, s, cut2, 0)   as = a / sigma^2, s = 1 / sigma^2, cut2 = (cull sigma)^2
+// and in double: (a, cx, cy, cz, sigma, cut2, 0, 0).
+struct MetricArgs {
+    int kind, n_sets, n_bumps;
+    float twist_amp, twist_theta0;
+};
+
+// Graph metric acceleration (Eq. 5.4 regrouped):
+//   grad f = -sum_b w_b d_b,           d_b = x - c_b, w_b = (a_b/s_b^2) e_b
+//   y^T H y = sum_b w_b (s_b (d_b.y)^2 - |y|^2)
+//   y' = - grad f (y^T H y) / (1 + |grad f|^2)
+// A bump contributes only where |d_b|^2 <= cut2 (per lane), which keeps each
+// lane's result independent of which superset list its wave walked.
+struct GraphAccum {
+    float gx, gy, gz, q;
+};
+
+__device__ __forceinline__ void graph_bump_f32(const float4 b0, const float4 b1, V3<float> p, V3<float> y,
+                                               float yy, GraphAccum &A) {
+    float dx = p.x - b0.x, dy = p.y - b0.y, dz = p.z - b0.z;
+    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    float e = exp2_(b0.w * r2);
+    float w = (r2 <= b1.z) ? b1.x * e : 0.0f;
+    A.gx = fmaf(-w, dx, A.gx);
+    A.gy = fmaf(-w, dy, A.gy);
+    A.gz = fmaf(-w, dz, A.gz);
+    float dv = fmaf(dz, y.z, fmaf(dy, y.y, dx * y.x));
+    A.q = fmaf(w, fmaf(b1.y, dv * dv, -yy), A.q);
+}
+
+__device__ __forceinline__ V3<float> graph_finish(const GraphAccum &A) {
+    float den = fmaf(A.gz, A.gz, fmaf(A.gy, A.gy, fmaf(A.gx, A.gx, 1.0f)));
+    float c = -A.q * rcp_(den);
+    return {c * A.gx, c * A.gy, c * A.gz};
+}
+
+// Walk a wave-uniform bump mask; bump data by scalar loads.  COUNT adds the
+// number of bumps inside their cut sphere at p to *n_in.
+template <bool COUNT = false>
+__device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
+                                                     V3<float> y, unsigned *n_in = nullptr) {
+    GraphAccum A{0.f, 0.f, 0.f, 0.f};
+    float yy = dot(y, y);
+    unsigned n = 0;
+    while (mask) {
+        int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        float4 b0 = B[2 * b], b1 = B[2 * b + 1];
+        graph_bump_f32(b0, b1, p, y, yy, A);
+        if (COUNT) {
+            float dx = p.x - b0.x, dy = p.y - b0.y, dz = p.z - b0.z;
+            n += (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= b1.z) ? 1u : 0u;
+        }
+    }
+    if (COUNT) *n_in += n;
+    return graph_finish(A);
+}
+
+// Double precision version over a (per-lane) mask, same regrouping.
+__device__ __forceinline__ V3<double> graph_accel_f64(const double *__restrict__ B, uint64_t mask, V3<double> p,
+                                                      V3<double> y) {
+    double gx = 0, gy = 0, gz = 0, q = 0;
+    double yy = dot(y, y);
+    while (mask) {
+        int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const double *pb = B + 8 * b;
+        double s = 1.0 / (pb[4] * pb[4]);
+        double dx = p.x - pb[1], dy = p.y - pb[2], dz = p.z - pb[3];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 > pb[5]) continue;
+        double w = pb[0] * s * exp(-0.5 * r2 * s);
+        gx -= w * dx;
+        gy -= w * dy;
+        gz -= w * dz;
+        double dv = dx * y.x + dy * y.y + dz * y.z;
+        q += w * (s * dv * dv - yy);
+    }
+    double den = 1.0 + gx * gx + gy * gy + gz * gz;
+    double c = -q / den;
+    return {c * gx, c * gy, c * gz};
+}
+
+// Twist pull-back, phi(x) = x + A(rho) R_z(theta(rho)) x, A = amp tanh rho,
+// theta = theta0 exp(-rho^2), rho = |x|.  With u = x/rho:
+//   J = I + A R + v u^T,        v = A' R x + A theta' R' x
+//   w = D^2 phi[y,y] = (A'' rho'^2) R x + A' P R u + 2 A' rho' R y
+//       + (2 A' theta' rho'^2 + A theta'' rho'^2) R' x + A theta' P R' u
+//       + 2 A theta' rho' R' y + A theta'^2 rho'^2 R'' x
+// where rho' = u.y and P = |y|^2 - rho'^2 (so rho'' x = P u: bounded at the
+// origin, where phi is only C^1).  The flow is y' = -J^-1 w (Eq. 5.8),
+// solved with Sherman-Morrison on M = I + A R (a scaled rotation in the
+// xy-plane, 1 + A along z).  Returns false when the solve is singular.
+template <class T>
+__device__ __forceinline__ bool twist_accel(T amp, T th0, V3<T> x, V3<T> y, V3<T> &acc) {
+    T r2 = dot(x, x);
+    T rho = sqrt_(r2);
+    T tiny = T(1e-30);
+    T inv_rho = rho > tiny ? rcp_(rho) : T(0);
+    V3<T> u = inv_rho * x;
+    // tanh(rho) = (1 - e)/(1 + e), e = exp(-2 rho) (rho >= 0)
+    T e = exp2_(T(-2) * log2e_<T>() * rho);
+    T th = (T(1) - e) * rcp_(T(1) + e);
+    T sech2 = T(1) - th * th;
+    T A = amp * th, A1 = amp * sech2, A2 = T(-2) * th * A1;
+    T ang = th0 * exp2_(-log2e_<T>() * r2);
+    T t1 = T(-2) * rho * ang, t2 = (T(4) * r2 - T(2)) * ang;
+    T s, c;
+    sincos_(ang, &s, &c);
+    auto R = [&](V3<T> a) { return mk(c * a.x - s * a.y, s * a.x + c * a.y, a.z); };
+    auto Rp = [&](V3<T> a) { return mk(-s * a.x - c * a.y, c * a.x - s * a.y, T(0)); };
+    auto Rpp = [&](V3<T> a) { return mk(-c * a.x + s * a.y, -s * a.x - c * a.y, T(0)); };
+    T rp = dot(u, y);
+    T P = dot(y, y) - rp * rp;
+    V3<T> Rx = R(x), Rpx = Rp(x);
+    V3<T> v = axpy(A * t1, Rpx, A1 * Rx);
+    T rp2 = rp * rp;
+    V3<T> w = (A2 * rp2) * Rx;
+    w = axpy(A1 * P, R(u), w);
+    w = axpy(T(2) * A1 * rp, R(y), w);
+    w = axpy((T(2) * A1 * t1 + A * t2) * rp2, Rpx, w);
+    w = axpy(A * t1 * P, Rp(u), w);
+    w = axpy(T(2) * A * t1 * rp, Rp(y), w);
+    w = axpy(A * t1 * t1 * rp2, Rpp(x), w);
+    // M^-1 for M = I + A R:  xy block [[1+Ac, -As],[As, 1+Ac]], z: 1 + A
+    T m = T(1) + A * c, n = A * s;
+    T idet = rcp_(m * m + n * n), iz = rcp_(T(1) + A);
+    auto Minv = [&](V3<T> a) { return mk(idet * (m * a.x + n * a.y), idet * (-n * a.x + m * a.y), iz * a.z); };
+    V3<T> Mw = Minv(w), Mv = Minv(v);
+    T den = T(1) + dot(u, Mv);
+    if (!(den > T(1e-12))) return false;
+    T coef = dot(u, Mw) * rcp_(den);
+    // a = -J^-1 w = -(M^-1 w - M^-1 v (u.M^-1 w)/(1 + u.M^-1 v))
+    acc = mk(-(Mw.x - coef * Mv.x), -(Mw.y - coef * Mv.y), -(Mw.z - coef * Mv.z));
+    return true;
+}
+
+// |J d|^2 for the twist (initial speed normalisation).
+template <class T> __device__ __forceinline__ T twist_gdd(T amp, T th0, V3<T> x, V3<T> d) {
+    T r2 = dot(x, x);
+    T rho = sqrt_(r2);
+    T inv_rho = rho > T(1e-30) ? rcp_(rho) : T(0);
+    V3<T> u = inv_rho * x;
+    T e = exp2_(T(-2) * log2e_<T>() * rho);
+    T th = (T(1) - e) * rcp_(T(1) + e);
+    T A = amp * th, A1 = amp * (T(1) - th * th);
+    T ang = th0 * exp2_(-log2e_<T>() * r2);
+    T t1 = T(-2) * rho * ang;
+    T s, c;
+    sincos_(ang, &s, &c);
+    V3<T> Rx = mk(c * x.x - s * x.y, s * x.x + c * x.y, x.z);
+    V3<T> Rpx = mk(-s * x.x - c * x.y, c * x.x - s * x.y, T(0));
+    V3<T> Rd = mk(c * d.x - s * d.y, s * d.x + c * d.y, d.z);
+    V3<T> v = axpy(A * t1, Rpx, A1 * Rx);
+    V3<T> Jd = axpy(dot(u, d), v, axpy(A, Rd, d));
+    return dot(Jd, Jd);
+}
+
+// z-twist of Sec. 5.2: Phi = (cos z x - sin z y, sin z x + cos z y, z).
+//   J = [[c, -s, -s x - c y], [s, c, c x - s y], [0, 0, 1]]
+//   D^2 Phi[v,v] = (-v3^2 (c x - s y) - 2 v3 (s v1 + c v2),
+//                   -v3^2 (s x + c y) + 2 v3 (c v1 - s v2), 0)
+//   J a = -w  =>  a3 = 0, (a1, a2) = -R(z)^T (w1, w2).
+template <class T> __device__ __forceinline__ V3<T> ztwist_accel(V3<T> x, V3<T> v) {
+    T s, c;
+    sincos_(x.z, &s, &c);
+    T v3 = v.z;
+    T w1 = -v3 * v3 * (c * x.x - s * x.y) - T(2) * v3 * (s * v.x + c * v.y);
+    T w2 = -v3 * v3 * (s * x.x + c * x.y) + T(2) * v3 * (c * v.x - s * v.y);
+    return mk(-(c * w1 + s * w2), -(-s * w1 + c * w2), T(0));
+}
+template <class T> __device__ __forceinline__ T ztwist_gdd(V3<T> x, V3<T> d) {
+    T s, c;
+    sincos_(x.z, &s, &c);
+    T j1 = c * d.x - s * d.y + (-s * x.x - c * x.y) * d.z;
+    T j2 = s * d.x + c * d.y + (c * x.x - s * x.y) * d.z;
+    return j1 * j1 + j2 * j2 + d.z * d.z;
+}
+
+// ------------------------------------------------------------------- scene
+// Segment-vs-object tests on the chord [x0, x0 + D] in single precision.
+// Return the crossing parameter s in [0,1], or 2 for none.
+__device__ __forceinline__ float sphere_chord(float4 sp, V3<float> o, V3<float> D, float DD) {
+    // o = x0 - c
+    float B = dot(D, o);
+    float Cq = fmaf(-sp.w, sp.w, dot(o, o));
+    float disc = fmaf(B, B, -DD * Cq);
+    if (!(disc >= 0.0f)) return 2.0f;
+    float q = sqrt_(disc);
+    float inv = rcp_(DD);
+    float s1 = (-B - q) * inv, s2 = (-B + q) * inv;
+    if (s1 >= 0.0f && s1 <= 1.0f) return s1;
+    if (s2 >= 0.0f && s2 <= 1.0f) return s2;
+    return 2.0f;
+}
+
+template <class T> __device__ __forceinline__ T torus_sdf(const T *tp, V3<T> x) {
+    V3<T> q = mk(x.x - tp[0], x.y - tp[1], x.z - tp[2]);
+    V3<T> a = mk(tp[3], tp[4], tp[5]);
+    T ax = dot(q, a);
+    V3<T> rad = axpy(-ax, a, q);
+    T e = sqrt_(dot(rad, rad)) - tp[6];
+    return sqrt_(e * e + ax * ax) - tp[7];
+}
+
+}  // namespace rtd

@@ -1,0 +1,220 @@
+"""ctypes binding of librt.so (the C ABI declared in include/rt.h).
+
+Argument marshalling only: every step of the trace runs in the HIP kernels of
+librt.so.  There is no fallback: if the library is missing, importing this
+module raises.  PyTorch supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("paper_2005_05386_amd: %s is not built; run `python -c 'import __graft_entry__ as g; "
+                      "g.build()'` (hipcc for gfx950)" % LIB_PATH)
+
+_lib = C.CDLL(LIB_PATH)
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED, RT_ESTATE = 0, -1, -2, -3, -4, -5
+EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST = 0, 1, 2, 3
+RK4, RK45, EULER = 0, 1, 2
+FLAG_TIMING, FLAG_COUNT_WORK = 1, 2
+
+EXPORTS = ["rt_abi_version", "rt_create", "rt_destroy", "rt_last_error", "rt_set_metric", "rt_set_scene",
+           "rt_trace", "rt_sync", "rt_get_stats"]
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("rt status %d: %s" % (status, msg))
+        self.status = status
+
+
+class rt_bump(C.Structure):
+    _fields_ = [("a", C.c_float), ("cx", C.c_float), ("cy", C.c_float), ("cz", C.c_float), ("sigma", C.c_float)]
+
+
+class rt_metric(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n_sets", C.c_int), ("n_bumps", C.c_int), ("bumps", C.c_void_p),
+                ("twist_amp", C.c_float), ("twist_theta0", C.c_float), ("cull_sigmas", C.c_float)]
+
+
+class rt_scene(C.Structure):
+    _fields_ = [("n_spheres", C.c_int), ("spheres", C.c_void_p), ("n_planes", C.c_int), ("planes", C.c_void_p),
+                ("n_tori", C.c_int), ("tori", C.c_void_p)]
+
+
+class rt_camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("forward", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float), ("width", C.c_int), ("height", C.c_int)]
+
+
+class rt_step_rule(C.Structure):
+    _fields_ = [("kind", C.c_int), ("h", C.c_float), ("rtol", C.c_float), ("atol", C.c_float),
+                ("h_min", C.c_float), ("h_max", C.c_float), ("t_max", C.c_float), ("cull_every", C.c_int),
+                ("pass_steps", C.c_int), ("bisect_iters", C.c_int), ("flags", C.c_int)]
+
+
+class rt_outputs(C.Structure):
+    _fields_ = [("hit", C.c_void_p), ("t", C.c_void_p), ("id", C.c_void_p), ("dir", C.c_void_p),
+                ("steps", C.c_void_p)]
+
+
+class rt_stats(C.Structure):
+    _fields_ = [("rays", C.c_uint64), ("ray_steps", C.c_uint64), ("attempts", C.c_uint64),
+                ("wave_iters", C.c_uint64), ("lane_iters", C.c_uint64), ("bump_list_sum", C.c_uint64),
+                ("obj_list_sum", C.c_uint64), ("refined", C.c_uint64), ("acc_evals", C.c_uint64),
+                ("bump_evals", C.c_uint64), ("obj_tests", C.c_uint64), ("passes", C.c_int), ("pass_ms", C.c_float),
+                ("refine_ms", C.c_float), ("total_ms", C.c_float)]
+
+
+_P = C.c_void_p
+_lib.rt_abi_version.restype = C.c_int
+_lib.rt_create.argtypes = [C.c_int, C.POINTER(_P)]
+_lib.rt_create.restype = C.c_int
+_lib.rt_destroy.argtypes = [_P]
+_lib.rt_destroy.restype = None
+_lib.rt_last_error.argtypes = [_P]
+_lib.rt_last_error.restype = C.c_char_p
+_lib.rt_set_metric.argtypes = [_P, C.POINTER(rt_metric)]
+_lib.rt_set_metric.restype = C.c_int
+_lib.rt_set_scene.argtypes = [_P, C.POINTER(rt_scene)]
+_lib.rt_set_scene.restype = C.c_int
+_lib.rt_trace.argtypes = [_P, C.POINTER(rt_camera), C.POINTER(rt_step_rule), C.c_int, C.POINTER(rt_outputs), _P]
+_lib.rt_trace.restype = C.c_int
+_lib.rt_sync.argtypes = [_P, _P]
+_lib.rt_sync.restype = C.c_int
+_lib.rt_get_stats.argtypes = [_P, C.POINTER(rt_stats)]
+_lib.rt_get_stats.restype = C.c_int
+
+
+def lib():
+    return _lib
+
+
+def abi_version():
+    return _lib.rt_abi_version()
+
+
+def camera_struct(cam):
+    f3 = lambda v: (C.c_float * 3)(*[float(x) for x in v])
+    return rt_camera(f3(cam["eye"]), f3(cam["forward"]), f3(cam["up"]), float(cam["vfov_deg"]),
+                     int(cam["width"]), int(cam["height"]))
+
+
+def rule_struct(r):
+    return rt_step_rule(int(r["kind"]), float(r["h"]), float(r.get("rtol", 1e-6)), float(r.get("atol", 1e-6)),
+                        float(r.get("h_min", 1e-6)), float(r.get("h_max", r["h"])), float(r["t_max"]),
+                        int(r.get("cull_every", 16)), int(r.get("pass_steps", 256)), int(r.get("bisect_iters", 40)),
+                        int(r.get("flags", 0)))
+
+
+class Tracer:
+    """One rt_ctx on a HIP device (device=-1: host-only, validation only)."""
+
+    def __init__(self, device=0):
+        h = _P()
+        st = _lib.rt_create(int(device), C.byref(h))
+        if st != RT_OK:
+            raise RtError(st, _lib.rt_last_error(None).decode())
+        self._h = h
+        self.device = device
+        self.n_sets = 1
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != RT_OK:
+            raise RtError(st, _lib.rt_last_error(self._h).decode())
+
+    def set_metric(self, metric):
+        b = np.ascontiguousarray(np.asarray(metric["bumps"], np.float32))
+        if b.ndim == 2:
+            b = b[None]
+        n_sets, n_bumps = b.shape[0], b.shape[1]
+        m = rt_metric(int(metric["kind"]), int(n_sets), int(n_bumps), b.ctypes.data if b.size else None,
+                      float(metric.get("twist_amp", 0.4)), float(metric.get("twist_theta0", 1.2)),
+                      float(metric.get("cull_sigmas", 6.0)))
+        self._check(_lib.rt_set_metric(self._h, C.byref(m)))
+        self.n_sets = n_sets
+
+    def set_scene(self, scene):
+        sp = np.ascontiguousarray(np.asarray(scene["spheres"], np.float32).reshape(-1, 4))
+        pl = np.ascontiguousarray(np.asarray(scene["planes"], np.float32).reshape(-1, 4))
+        to = np.ascontiguousarray(np.asarray(scene["tori"], np.float32).reshape(-1, 8))
+        s = rt_scene(sp.shape[0], sp.ctypes.data if sp.size else None, pl.shape[0],
+                     pl.ctypes.data if pl.size else None, to.shape[0], to.ctypes.data if to.size else None)
+        self._check(_lib.rt_set_scene(self._h, C.byref(s)))
+
+    def alloc_outputs(self, camera, with_steps=True):
+        import torch
+        n = self.n_sets * camera["height"] * camera["width"]
+        dev = torch.device("cuda", self.device)
+        return dict(hit=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                    t=torch.empty(n, dtype=torch.float32, device=dev),
+                    id=torch.empty(n, dtype=torch.int32, device=dev),
+                    dir=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                    steps=torch.empty(n, dtype=torch.int32, device=dev) if with_steps else None)
+
+    def trace_into(self, camera, rule, max_steps, out, stream=None):
+        """Enqueue a trace writing into the tensors of `out` (see
+        alloc_outputs); asynchronous on `stream` (torch stream or None for
+        torch's current stream)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        n = self.n_sets * camera["height"] * camera["width"]
+        for k, shape, dt in (("hit", (n, 3), torch.float32), ("t", (n,), torch.float32),
+                             ("id", (n,), torch.int32), ("dir", (n, 3), torch.float32)):
+            tns = out[k]
+            if tuple(tns.shape) != shape or tns.dtype != dt or not tns.is_cuda or not tns.is_contiguous():
+                raise ValueError("output %s must be a contiguous %s cuda tensor of shape %s" % (k, dt, shape))
+        steps = out.get("steps")
+        if steps is not None and (tuple(steps.shape) != (n,) or steps.dtype != torch.int32):
+            raise ValueError("output steps must be an int32 tensor of shape (%d,)" % n)
+        o = rt_outputs(out["hit"].data_ptr(), out["t"].data_ptr(), out["id"].data_ptr(), out["dir"].data_ptr(),
+                       steps.data_ptr() if steps is not None else None)
+        cam = camera_struct(camera)
+        r = rule_struct(rule)
+        self._check(_lib.rt_trace(self._h, C.byref(cam), C.byref(r), int(max_steps), C.byref(o),
+                                  C.c_void_p(stream.cuda_stream)))
+        return out
+
+    def trace(self, camera, rule, max_steps=None, with_steps=True):
+        if max_steps is None:
+            max_steps = rule["max_steps"]
+        out = self.alloc_outputs(camera, with_steps)
+        return self.trace_into(camera, rule, max_steps, out)
+
+    def trace_raw(self, camera, rule, max_steps, out_ptrs, stream_handle):
+        """Enqueue with raw device pointers (hit, t, id, dir, steps-or-0)."""
+        o = rt_outputs(*[p if p else None for p in out_ptrs])
+        self._check(_lib.rt_trace(self._h, C.byref(camera_struct(camera)), C.byref(rule_struct(rule)),
+                                  int(max_steps), C.byref(o), C.c_void_p(stream_handle)))
+
+    def sync(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_sync(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def stats(self):
+        s = rt_stats()
+        self._check(_lib.rt_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in rt_stats._fields_}
+
+
+def to_numpy(out):
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}

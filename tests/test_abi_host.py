@@ -1,0 +1,125 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/rt.h declares, and the host-side validation returns the documented
+status codes (host-only context, device -1)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rt():
+    from paper_2005_05386_amd import rt
+    return rt
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rt.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:rt_status|void|int|const char \*)\s*\*?\s*(rt_\w+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    rt = _rt()
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(rt.lib(), n), n
+    assert sorted(rt.EXPORTS) == names
+    assert rt.abi_version() == 1
+
+
+def test_host_only_context_validates():
+    rt = _rt()
+    tr = rt.Tracer(-1)
+    wl = W.get("bumps16_1080p")
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    cam, rule = wl["camera"], wl["rule"]
+    # a valid trace on a host-only context stops after validation
+    with pytest.raises(rt.RtError) as e:
+        tr.trace_raw(cam, rule, rule["max_steps"], (16, 16, 16, 16, 0), 0)
+    assert e.value.status == rt.RT_ESTATE
+    bad = [
+        (dict(cam, width=0), rule, 10, rt.RT_EINVAL),
+        (dict(cam, vfov_deg=180.0), rule, 10, rt.RT_EINVAL),
+        (dict(cam, up=[0, 0, 1.0]), rule, 10, rt.RT_EINVAL),
+        (cam, dict(rule, h=0.0), 10, rt.RT_EINVAL),
+        (cam, dict(rule, h=float("nan")), 10, rt.RT_EINVAL),
+        (cam, dict(rule, kind=7), 10, rt.RT_EUNSUPPORTED),
+        (cam, dict(rule, cull_every=0), 10, rt.RT_EINVAL),
+        (cam, dict(rule, pass_steps=4), 10, rt.RT_EINVAL),
+        (cam, dict(rule, bisect_iters=61), 10, rt.RT_EINVAL),
+        (cam, dict(rule, kind=W.RK45, rtol=0.0), 10, rt.RT_EINVAL),
+        (cam, rule, 0, rt.RT_EINVAL),
+        (cam, rule, 2000000, rt.RT_EINVAL),
+    ]
+    for c_, r_, ms, want in bad:
+        with pytest.raises(rt.RtError) as e:
+            tr.trace_raw(c_, r_, ms, (16, 16, 16, 16, 0), 0)
+        assert e.value.status == want, (c_, r_, ms, e.value)
+        assert rt.lib().rt_last_error(tr._h)
+    with pytest.raises(rt.RtError) as e:
+        tr.trace_raw(cam, rule, 10, (0, 16, 16, 16, 0), 0)
+    assert e.value.status == rt.RT_EINVAL
+
+
+def test_metric_and_scene_validation():
+    rt = _rt()
+    tr = rt.Tracer(-1)
+    b = W.random_bumps(4, 0)
+    for mod, want in [(lambda x: x.__setitem__((0, 4), 0.0), rt.RT_EINVAL),
+                      (lambda x: x.__setitem__((1, 4), -1.0), rt.RT_EINVAL),
+                      (lambda x: x.__setitem__((2, 0), np.nan), rt.RT_EINVAL),
+                      (lambda x: x.__setitem__((3, 1), np.inf), rt.RT_EINVAL)]:
+        bb = b.copy()
+        mod(bb)
+        with pytest.raises(rt.RtError) as e:
+            tr.set_metric(W.metric(W.GRAPH_GAUSS, bb))
+        assert e.value.status == want
+    with pytest.raises(rt.RtError) as e:
+        tr.set_metric(W.metric(W.GRAPH_GAUSS, W.random_bumps(65, 0)))
+    assert e.value.status == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        tr.set_metric(dict(W.metric(W.GRAPH_GAUSS, b), kind=9))
+    assert e.value.status == rt.RT_EUNSUPPORTED
+    with pytest.raises(rt.RtError) as e:
+        tr.set_metric(dict(W.metric(W.PULLBACK_TWIST), twist_amp=2.0))
+    assert e.value.status == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        tr.set_metric(dict(W.metric(W.GRAPH_GAUSS, b), cull_sigmas=2.0))
+    assert e.value.status == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        tr.set_scene(W.scene(spheres=W.random_spheres(257, 1)))
+    assert e.value.status == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        tr.set_scene(W.scene(planes=[[0.0, 2.0, 0.0, -1.0]]))
+    assert e.value.status == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        tr.set_scene(W.scene(tori=[[0, 0, 0, 0, 0, 1, 0.1, 0.2]]))
+    assert e.value.status == rt.RT_EINVAL
+    sp = W.random_spheres(3, 1)
+    sp[1, 3] = -0.1
+    with pytest.raises(rt.RtError) as e:
+        tr.set_scene(W.scene(spheres=sp))
+    assert e.value.status == rt.RT_EINVAL
+    # trace before a scene is set
+    tr2 = rt.Tracer(-1)
+    tr2.set_metric(W.metric(W.GRAPH_GAUSS, b))
+    wl = W.get("single_bump_64")
+    with pytest.raises(rt.RtError) as e:
+        tr2.trace_raw(wl["camera"], wl["rule"], 10, (16, 16, 16, 16, 0), 0)
+    assert e.value.status == rt.RT_ESTATE
+
+
+def test_create_errors():
+    rt = _rt()
+    h = C.c_void_p()
+    assert rt.lib().rt_create(-2, C.byref(h)) == rt.RT_EINVAL
+    assert rt.lib().rt_last_error(None)
+    assert not h.value
+    rt.lib().rt_destroy(None)

@@ -1,0 +1,243 @@
+"""GPU parity of the HIP trace path against the FP64 oracle, through the
+C ABI.  Every test names its case on stdout before touching the GPU."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import exact
+from tests.parity import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_05386_amd import rt as _rt
+    return _rt
+
+
+def gpu_trace(rt, wl, rule=None, max_steps=None, tracer=None):
+    rule = rule or wl["rule"]
+    tr = tracer or rt.Tracer(0)
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    out = tr.trace(wl["camera"], rule, max_steps or rule["max_steps"])
+    tr.sync()
+    res = rt.to_numpy(out)
+    res["_stats"] = tr.stats()
+    return res
+
+
+def oracle_trace(wl, pixels=None, rule=None, set_index=0):
+    return oracle.Oracle(wl["metric"], wl["scene"], set_index).trace(wl["camera"], rule or wl["rule"], pixels)
+
+
+def test_single_bump_full_frame(rt):
+    say("single_bump_64 full frame 64x64 RK4 h=0.01")
+    wl = W.get("single_bump_64")
+    g = gpu_trace(rt, wl)
+    ref = oracle_trace(wl)
+    rep = compare(g, ref)
+    say(rep)
+    assert_parity(rep)
+    assert rep["max_t_err"] < 1e-3
+    st = g["_stats"]
+    assert st["rays"] == 64 * 64
+    assert st["ray_steps"] == int(g["steps"].sum())
+    assert np.array_equal(g["steps"], ref["steps"]) or (g["steps"] != ref["steps"]).mean() < 0.002
+
+
+def test_single_bump_matches_quadrature(rt):
+    """GPU against the exact continuous single-bump geodesics (tighter than
+    the parity tolerance: RK4 truncation + FP32 rounding)."""
+    say("single_bump_64 vs quadrature")
+    wl = W.get("single_bump_64")
+    g = gpu_trace(rt, wl)
+    pix = W.pixel_sample(64, 64, 300, seed=21)
+    d = exact.camera_dirs(wl["camera"], pix)
+    b = np.linalg.norm(np.cross(np.float64(wl["camera"]["eye"]), d), axis=1)
+    pix = pix[(b > 0.02) & (b < 1.2) & (g["id"][pix] >= 0)][:25]
+    d = exact.camera_dirs(wl["camera"], pix)
+    bump = wl["metric"]["bumps"][0, 0].astype(np.float64)
+    sph = np.float64(wl["scene"]["spheres"][0])
+    pl = np.float64(wl["scene"]["planes"][0])
+    objs = [lambda x: (x - sph[:3]) @ (x - sph[:3]) - sph[3] ** 2, lambda x: pl[:3] @ x - pl[3]]
+    worst = 0.0
+    for q, p in enumerate(pix):
+        ray = exact.SingleBumpRay(bump[0], bump[1:4], bump[4], np.float64(wl["camera"]["eye"]), d[q]).tabulate(10.0)
+        t, oid, x = ray.first_hit(objs, 10.0)
+        assert g["id"][p] == oid
+        worst = max(worst, np.abs(g["hit"][p] - x).max())
+    say("worst hit error vs quadrature", worst)
+    assert worst < 2e-4
+
+
+def test_flat_space_is_straight(rt):
+    say("flat space (EUCLID) bumps16 scene 96x54")
+    wl = W.with_size(W.get("bumps16_1080p"), 96, 54)
+    wl["metric"] = W.metric(W.EUCLID)
+    rule = dict(wl["rule"], max_steps=2000)
+    g = gpu_trace(rt, wl, rule=rule)
+    pix = np.arange(96 * 54)
+    d = exact.camera_dirs(wl["camera"], pix)
+    t, ids = exact.line_hits(np.float64(wl["camera"]["eye"]), d, wl["scene"], 2000 * np.float64(np.float32(0.005)))
+    same = g["id"] == ids
+    assert same.mean() >= 0.999
+    hit = same & (ids >= 0)
+    exp_hit = np.float64(wl["camera"]["eye"]) + t[hit, None] * d[hit]
+    say("max flat hit err", np.abs(g["hit"][hit] - exp_hit).max())
+    assert np.abs(g["hit"][hit] - exp_hit).max() < 2e-5
+
+
+def test_bumps16_small_full_frame(rt):
+    say("bumps16 192x108 full frame RK4 h=0.005 4000 steps")
+    wl = W.with_size(W.get("bumps16_1080p"), 192, 108)
+    g = gpu_trace(rt, wl)
+    ref = oracle_trace(wl)
+    rep = compare(g, ref)
+    say(rep)
+    assert_parity(rep)
+
+
+def test_bumps16_1080p_sampled(rt):
+    """Full 1080p frame in the benchmark's launch configuration; a seeded
+    sample of pixels recomputed one by one by the oracle."""
+    say("bumps16_1080p full frame, 3000 sampled pixels vs oracle")
+    wl = W.get("bumps16_1080p")
+    g = gpu_trace(rt, wl)
+    pix = W.pixel_sample(1920, 1080, 3000, seed=7)
+    ref = oracle_trace(wl, pix)
+    rep = compare(g, ref, pix)
+    say(rep, g["_stats"])
+    assert_parity(rep)
+    assert g["_stats"]["rays"] == 1920 * 1080
+    assert (g["id"] >= -1).all()
+
+
+def test_rk45_small(rt):
+    say("bumps16 RK45 tol 1e-6, 96x54")
+    wl = W.with_size(W.get("bumps16_1080p_rk45"), 96, 54)
+    g = gpu_trace(rt, wl)
+    ref = oracle_trace(wl)
+    rep = compare(g, ref)
+    say(rep, g["_stats"])
+    assert_parity(rep)
+
+
+def test_rk45_1080p_sampled(rt):
+    say("bumps16 RK45 1080p, 1500 sampled pixels")
+    wl = W.get("bumps16_1080p_rk45")
+    g = gpu_trace(rt, wl)
+    pix = W.pixel_sample(1920, 1080, 1500, seed=8)
+    rep = compare(g, oracle_trace(wl, pix), pix)
+    say(rep, g["_stats"])
+    assert_parity(rep)
+
+
+def test_euler_single_bump(rt):
+    say("single_bump Euler h=0.01")
+    wl = W.get("single_bump_64")
+    rule = dict(wl["rule"], kind=W.EULER)
+    g = gpu_trace(rt, wl, rule=rule)
+    rep = compare(g, oracle_trace(wl, rule=rule))
+    say(rep)
+    assert_parity(rep)
+
+
+def test_sign_invariance_bitwise(rt):
+    say("f -> -f bitwise, bumps16 96x54")
+    wl = W.with_size(W.get("bumps16_1080p"), 96, 54)
+    g1 = gpu_trace(rt, wl)
+    wl2 = dict(wl)
+    wl2["metric"] = dict(wl["metric"], bumps=wl["metric"]["bumps"] * np.array([-1, 1, 1, 1, 1], np.float32))
+    g2 = gpu_trace(rt, wl2)
+    for k in ("hit", "t", "id", "dir", "steps"):
+        assert np.array_equal(g1[k], g2[k]), k
+
+
+@pytest.mark.parametrize("grid,K,S", [("1", 16, 256), ("7", 4, 64), ("", 64, 16)])
+def test_deterministic_across_launch_shapes(rt, grid, K, S):
+    """Per-lane 6-sigma selection and ordered bump walks make every ray's
+    arithmetic independent of the grid size, the culling period K and the
+    pass length S: outputs must be bitwise identical."""
+    say("determinism grid=%s K=%d S=%d" % (grid or "default", K, S))
+    wl = W.with_size(W.get("bumps16_1080p"), 64, 40)
+    ref = gpu_trace(rt, wl)
+    old = os.environ.get("RT_GRID_BLOCKS")
+    try:
+        if grid:
+            os.environ["RT_GRID_BLOCKS"] = grid
+        g = gpu_trace(rt, wl, rule=dict(wl["rule"], cull_every=K, pass_steps=S))
+    finally:
+        if old is None:
+            os.environ.pop("RT_GRID_BLOCKS", None)
+        else:
+            os.environ["RT_GRID_BLOCKS"] = old
+    for k in ("hit", "t", "id", "dir", "steps"):
+        assert np.array_equal(ref[k], g[k]), k
+
+
+def test_ragged_and_tiny_frames(rt):
+    for (w, h) in [(61, 37), (1, 1), (9, 3)]:
+        say("ragged frame %dx%d" % (w, h))
+        wl = W.with_size(W.get("single_bump_64"), w, h)
+        g = gpu_trace(rt, wl)
+        rep = compare(g, oracle_trace(wl))
+        assert rep["frac_ok"] == 1.0 or (w * h > 1000 and rep["frac_ok"] >= 0.999), rep
+        assert g["_stats"]["rays"] == w * h
+
+
+def test_multi_set_equals_single_sets(rt):
+    say("3 parameter sets in one launch vs one by one")
+    wl = W.with_size(W.get("adjoint_64x512", n_sets=3), 40, 32)
+    g = gpu_trace(rt, wl)
+    n = 40 * 32
+    for s in range(3):
+        one = dict(wl)
+        one["metric"] = dict(wl["metric"], bumps=wl["metric"]["bumps"][s:s + 1])
+        gs = gpu_trace(rt, one)
+        for k in ("hit", "t", "id", "dir", "steps"):
+            assert np.array_equal(g[k][s * n:(s + 1) * n], gs[k]), (s, k)
+    ref = oracle_trace(wl, set_index=2)
+    assert_parity(compare({k: v[2 * n:] for k, v in g.items() if k != "_stats"}, ref))
+
+
+def test_twist_small_full_frame(rt):
+    say("twist pullback 128x72 full frame")
+    wl = W.with_size(W.get("twist_4k"), 128, 72)
+    g = gpu_trace(rt, wl)
+    rep = compare(g, oracle_trace(wl))
+    say(rep)
+    assert_parity(rep)
+
+
+def test_twist_4k_sampled(rt):
+    say("twist_4k full frame, 1200 sampled pixels")
+    wl = W.get("twist_4k")
+    g = gpu_trace(rt, wl)
+    pix = W.pixel_sample(3840, 2160, 1200, seed=3)
+    rep = compare(g, oracle_trace(wl, pix), pix)
+    say(rep, g["_stats"])
+    assert_parity(rep)
+
+
+def test_ztwist_small(rt):
+    say("paper z-twist 64x48")
+    wl = W.with_size(W.get("single_bump_64"), 64, 48)
+    wl["metric"] = W.metric(W.PULLBACK_ZTWIST)
+    wl["scene"] = W.scene(spheres=W.random_spheres(32, 1), planes=W.PLANE_Y_MINUS_1)
+    rule = dict(wl["rule"], h=0.005, max_steps=2000, t_max=10.0)
+    g = gpu_trace(rt, wl, rule=rule)
+    rep = compare(g, oracle_trace(wl, rule=rule))
+    say(rep)
+    assert_parity(rep)
