@@ -126,7 +126,7 @@ def main():
     timed_rule = dict(rule, flags=rt.FLAG_TIMING)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    pass_ms = refine_ms = 0.0
+    pass_ms = refine_ms = compact_ms = 0.0
     n_pass_launches = 0
     torch.cuda.synchronize()
     ev0.record(stream)
@@ -135,6 +135,7 @@ def main():
         st = tr.stats()  # waits for this trace; reads its kernel times
         pass_ms += st["pass_ms"]
         refine_ms += st["refine_ms"]
+        compact_ms += st["compact_ms"]
         n_pass_launches += st["passes"]
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -159,11 +160,13 @@ def main():
                      "kernel": "k_trace_pass", "flops_per_trace": flops,
                      "kernel_ms_per_launch": pass_ms / max(1, n_pass_launches),
                      "frac_of_nonpacked_peak": achieved / FP32_PEAK_NONPACKED},
-        "kernel_ms": {"passes": pass_ms / args.steps, "refine": refine_ms / args.steps},
+        "kernel_ms": {"passes": pass_ms / args.steps, "refine": refine_ms / args.steps,
+                      "compaction": compact_ms / args.steps},
         "work": {"ray_steps": work["ray_steps"], "acc_evals": work["acc_evals"],
                  "bump_evals": work["bump_evals"], "obj_tests": work["obj_tests"],
                  "mean_active_bumps_per_eval": work["bump_evals"] / max(1, work["acc_evals"]),
                  "wave_list_bumps_per_iter": work["bump_list_sum"] / max(1, work["wave_iters"]),
+                 "wave_list_objects_per_iter": work["obj_list_sum"] / max(1, work["wave_iters"]),
                  "lane_occupancy": work["lane_iters"] / max(1, 64 * work["wave_iters"]),
                  "refined": work["refined"], "passes": work["passes"]},
     }

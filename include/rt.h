@@ -172,7 +172,7 @@ typedef struct rt_step_rule {
     float t_max;       /* > 0; RK4/Euler rays also stop at max_steps */
     int cull_every;    /* K: steps between per-wave re-culls of bumps/objects, 1..256 (16) */
     int pass_steps;    /* S: steps per launch before surviving rays are compacted, >= 16 (256) */
-    int bisect_iters;  /* FP64 bisection halvings for the hit, 0..60 (40) */
+    int bisect_iters;  /* FP64 bisection halvings for the hit, 0..60 (32) */
     int flags;         /* RT_FLAG_* bits, 0 for a plain trace */
 } rt_step_rule;
 
@@ -230,10 +230,55 @@ typedef struct rt_stats {
     int passes;             /* kernel passes launched */
     float pass_ms;          /* TIMING: summed duration of the integration passes */
     float refine_ms;        /* TIMING: duration of the FP64 refinement kernel */
+    float compact_ms;       /* TIMING: summed duration of the survivor compaction between passes */
     float total_ms;         /* TIMING: reset + passes + refinement */
 } rt_stats;
 
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
+
+/* ------------------------------------------------------- differentiation
+ * Gradients of a loss on the hit map with respect to every bump parameter
+ * (a, cx, cy, cz, sigma) of every set: the discrete adjoint of the RK4
+ * trace of the graph metric (RT_METRIC_GRAPH_GAUSS, 1..16 bumps per set,
+ * RT_STEP_RK4).  For a hitting pixel, the hit is the position of the
+ * partial RK4 step of fraction s* from the last state before the hit,
+ * where s* zeroes the object's implicit function; its derivative follows
+ * the implicit function theorem.  Pixels that miss carry no gradient.
+ *
+ * Tape: caller-owned device memory of rt_tape_bytes() bytes holding the
+ * state (x_hi, x_lo, y) every ckpt_every accepted steps of every ray and,
+ * per pixel, the state before the hit step with s*, the step index and the
+ * object.  rt_trace_bwd recomputes each ckpt_every-step segment from its
+ * checkpoint into context-owned scratch, then runs the per-step
+ * vector-Jacobian products backwards.  Gradient sums are reduced in a fixed
+ * order: results are bitwise reproducible for a given input.            */
+
+/* Bytes of tape for a trace of n_sets sets of the camera's frame
+ * (0 on invalid arguments). */
+size_t rt_tape_bytes(const rt_camera *camera, int n_sets, int max_steps, int ckpt_every);
+
+/* rt_trace plus the tape.  ckpt_every in 1..max_steps.  RT_EUNSUPPORTED
+ * unless the metric is GRAPH_GAUSS with 1..16 bumps and the rule is RK4;
+ * RT_EINVAL if tape_bytes < rt_tape_bytes(...).  The context remembers the
+ * call (camera, rule, tape) for rt_trace_bwd. */
+rt_status rt_trace_fwd_ckpt(rt_ctx *ctx, const rt_camera *camera, const rt_step_rule *rule, int max_steps,
+                            int ckpt_every, const rt_outputs *out, void *tape, size_t tape_bytes,
+                            void *hip_stream);
+
+/* Masked L2 loss per set, loss[set] = sum_p m_p |hit_p - target_p|^2 with
+ * m_p = (id_p >= 0) && (id_p == target_id_p) && (mask == NULL || mask[p]),
+ * and grad_hit_p = 2 m_p (hit_p - target_p) (grad_hit may be NULL).  All
+ * arrays are device arrays indexed like rt_outputs ([set][row][column]);
+ * loss has n_sets floats. */
+rt_status rt_loss_l2(rt_ctx *ctx, const rt_camera *camera, const float *hit, const int32_t *id,
+                     const float *target_hit, const int32_t *target_id, const uint8_t *mask, float *loss,
+                     float *grad_hit, void *hip_stream);
+
+/* Gradient of sum_p grad_hit_p . hit_p with respect to the bump parameters,
+ * written to grad_params [n_sets][n_bumps][5] (device).  tape must be the
+ * tape of the last rt_trace_fwd_ckpt on this context, with the metric
+ * unchanged since (RT_ESTATE otherwise). */
+rt_status rt_trace_bwd(rt_ctx *ctx, const void *tape, const float *grad_hit, float *grad_params, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -106,11 +106,17 @@ def _dptr(a):
 class Oracle:
     """Holds FP64 copies of one metric (one parameter set) and one scene."""
 
-    def __init__(self, metric, scene, set_index=0):
-        b = np.asarray(metric["bumps"], np.float32)
-        if b.ndim == 3:
-            b = b[set_index]
-        self._bumps = np.ascontiguousarray(b.astype(np.float64).reshape(-1, 5))
+    def __init__(self, metric, scene, set_index=0, bumps64=None):
+        """bumps64: optional float64 [n_bumps, 5] parameters used as given
+        (finite-difference perturbations must not be rounded to float32)."""
+        if bumps64 is not None:
+            b = np.asarray(bumps64, np.float64)
+        else:
+            b = np.asarray(metric["bumps"], np.float32)
+            if b.ndim == 3:
+                b = b[set_index]
+            b = b.astype(np.float64)
+        self._bumps = np.ascontiguousarray(b.reshape(-1, 5))
         self.m = _Metric(int(metric["kind"]), int(self._bumps.shape[0]), _dptr(self._bumps),
                          float(metric.get("twist_amp", 0.4)), float(metric.get("twist_theta0", 1.2)))
         self._sp = np.ascontiguousarray(np.asarray(scene["spheres"], np.float32).astype(np.float64).reshape(-1, 4))
@@ -187,3 +193,52 @@ def _rule(r):
     g = lambda k: float(np.float32(r[k]))
     return _Rule(int(r["kind"]), g("h"), g("rtol"), g("atol"), g("h_min"), g("h_max"),
                  g("t_max"), int(r["max_steps"]), 60)
+
+
+# --------------------------------------------------------------------------
+# Differentiation reference: the masked L2 loss between a hit map and a
+# target map, and its central finite-difference gradient with respect to
+# every bump parameter (a, cx, cy, cz, sigma).  This is the definition of
+# the derivative the GPU adjoint must reproduce; it uses nothing but the
+# traced hit points above.
+def l2_loss(hit, target_hit, mask):
+    """L = sum over masked pixels of |hit - target|^2 (FP64)."""
+    d = (np.asarray(hit, np.float64) - np.asarray(target_hit, np.float64))[mask]
+    return float((d * d).sum())
+
+
+def fd_gradient(metric, scene, camera, rule, pixels, target_hit, target_id, set_index=0, eps=1e-4,
+                nthreads=0):
+    """Central differences (L(theta + eps e_i) - L(theta - eps e_i)) / (2 eps)
+    over all n_bumps x 5 parameters of one set.
+
+    Pixels count only where the traced id equals the target id at theta and
+    at every perturbed theta (a common mask: FD across a change of the hit
+    object is meaningless).  Returns (grad [n_bumps, 5], loss at theta,
+    mask)."""
+    b0 = np.asarray(metric["bumps"], np.float32)
+    if b0.ndim == 3:
+        b0 = b0[set_index]
+    base = b0.astype(np.float64)
+    nb = base.shape[0]
+
+    def run(bumps64):
+        return Oracle(metric, scene, bumps64=bumps64).trace(camera, rule, pixels, nthreads=nthreads)
+
+    r0 = run(base)
+    target_id = np.asarray(target_id)
+    mask = (r0["id"] == target_id) & (r0["id"] >= 0)
+    plus, minus = {}, {}
+    for i in range(nb):
+        for j in range(5):
+            bp = base.copy()
+            bp[i, j] += eps
+            bm = base.copy()
+            bm[i, j] -= eps
+            plus[i, j] = run(bp)
+            minus[i, j] = run(bm)
+            mask &= (plus[i, j]["id"] == r0["id"]) & (minus[i, j]["id"] == r0["id"])
+    grad = np.zeros((nb, 5))
+    for (i, j), rp in plus.items():
+        grad[i, j] = (l2_loss(rp["hit"], target_hit, mask) - l2_loss(minus[i, j]["hit"], target_hit, mask)) / (2 * eps)
+    return grad, l2_loss(r0["hit"], target_hit, mask), mask

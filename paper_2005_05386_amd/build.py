@@ -8,10 +8,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt.so")
-SOURCES = ["rt_trace.hip", "rt_api.cpp"]
+SOURCES = ["rt_trace.hip", "rt_adjoint.hip", "rt_api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # contraction decided per source expression, so every kernel that shares
+    # an inline step function performs the same rounding
+    "-ffp-contract=on",
     # packed FP32 (v_pk_*_f32) disabled on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

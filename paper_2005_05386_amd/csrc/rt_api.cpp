@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rt.h"
+#include "rt.h"
 #include "rt_internal.hpp"
 
 namespace {
@@ -38,10 +38,13 @@ struct rt_ctx {
     void *d_bump_f = nullptr, *d_bump_d = nullptr, *d_scene = nullptr;
     size_t bump_f_bytes = 0, bump_d_bytes = 0, scene_bytes = 0;
     rti::DeviceData dd{};
-    // workspace
-    float *d_q[2] = {nullptr, nullptr};
-    int64_t q_cap = 0;  // rays the workspace holds
-    float4 *d_rec = nullptr;
+    // workspace (grow-only)
+    float *d_st = nullptr;             // ray state, Q_NFIELDS x ws_cap
+    int *d_ids[2] = {nullptr, nullptr};  // survivor lists, ws_cap + 64 * MAX_SETS each
+    unsigned long long *d_cmask = nullptr;
+    int *d_cscan = nullptr, *d_bscan = nullptr;
+    float4 *d_rec = nullptr;           // refine records, ws_cap
+    int64_t ws_cap = 0;                // ray ids the workspace holds
     int *d_ctr = nullptr;
     unsigned long long *d_stats = nullptr;
     hipStream_t last_stream = nullptr;
@@ -49,6 +52,12 @@ struct rt_ctx {
     int last_passes = 0;
     bool last_timed = false;
     std::vector<hipEvent_t> ev;  // timing events of the last trace
+    // differentiation
+    bool adj_valid = false;
+    const void *adj_tape = nullptr;
+    rti::TraceArgs adj_args{};
+    float *d_adj_scr = nullptr, *d_adj_part = nullptr, *d_loss_blk = nullptr;
+    int64_t adj_scr_cap = 0, adj_part_cap = 0, loss_cap = 0;
 };
 
 static rt_status fail(rt_ctx *c, rt_status s, const std::string &msg) {
@@ -121,11 +130,18 @@ void rt_destroy(rt_ctx *c) {
         hipFree(c->d_bump_f);
         hipFree(c->d_bump_d);
         hipFree(c->d_scene);
-        hipFree(c->d_q[0]);
-        hipFree(c->d_q[1]);
+        hipFree(c->d_st);
+        hipFree(c->d_ids[0]);
+        hipFree(c->d_ids[1]);
+        hipFree(c->d_cmask);
+        hipFree(c->d_cscan);
+        hipFree(c->d_bscan);
         hipFree(c->d_rec);
         hipFree(c->d_ctr);
         hipFree(c->d_stats);
+        hipFree(c->d_adj_scr);
+        hipFree(c->d_adj_part);
+        hipFree(c->d_loss_blk);
         for (hipEvent_t e : c->ev) hipEventDestroy(e);
     }
     delete c;
@@ -197,6 +213,7 @@ rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
         bf[8 * i + 4] = (float)((double)b.a / (s * s));
         bf[8 * i + 5] = (float)(1.0 / (s * s));
         bf[8 * i + 6] = (float)(cut * cut);
+        bf[8 * i + 7] = b.sigma;
         bd[8 * i + 0] = b.a;
         bd[8 * i + 1] = b.cx;
         bd[8 * i + 2] = b.cy;
@@ -221,6 +238,7 @@ rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
     c->cull = m->cull_sigmas;
     c->bumps.assign(m->bumps, m->bumps + n);
     c->has_metric = true;
+    c->adj_valid = false;
     c->err.clear();
     return RT_OK;
 }
@@ -301,39 +319,57 @@ rt_status rt_set_scene(rt_ctx *c, const rt_scene *s) {
     return RT_OK;
 }
 
-// Ray queues (2 x Q_NFIELDS floats per ray), refine records (REC_F4 float4
-// per ray) and the counter block, sized for `cap` rays; grow-only.
+// Chunks of one pass: every set's survivor list is padded to whole chunks.
+static int64_t max_chunks_for(int64_t cap) { return cap / 64 + MAX_SETS; }
+
+static void free_workspace(rt_ctx *c) {
+    hipFree(c->d_st);
+    hipFree(c->d_ids[0]);
+    hipFree(c->d_ids[1]);
+    hipFree(c->d_cmask);
+    hipFree(c->d_cscan);
+    hipFree(c->d_bscan);
+    hipFree(c->d_rec);
+    c->d_st = nullptr;
+    c->d_ids[0] = c->d_ids[1] = nullptr;
+    c->d_cmask = nullptr;
+    c->d_cscan = c->d_bscan = nullptr;
+    c->d_rec = nullptr;
+    c->ws_cap = 0;
+}
+
+// Ray state (Q_NFIELDS floats per ray id), two sorted survivor lists, the
+// per-chunk compaction arrays, refine records (REC_F4 float4 per ray) and
+// the counter block, sized for `cap` ray ids; grow-only.
 static rt_status ensure_workspace(rt_ctx *c, int64_t cap) {
     hipError_t e;
     if (!c->d_ctr) {
         e = hipMalloc((void **)&c->d_ctr, sizeof(int) * (rti::CTR_PASS0 + rti::MAX_PASSES_API * rti::CTR_PASS_WORDS));
         if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (counters)");
     }
-    if (c->q_cap >= cap) return RT_OK;
+    if (c->ws_cap >= cap) return RT_OK;
     rt_status st = sync_last(c);
     if (st != RT_OK) return st;
-    hipFree(c->d_q[0]);
-    hipFree(c->d_q[1]);
-    hipFree(c->d_rec);
-    c->d_q[0] = c->d_q[1] = nullptr;
-    c->d_rec = nullptr;
-    c->q_cap = 0;
-    size_t qb = (size_t)cap * rti::Q_NFIELDS * sizeof(float);
-    if ((e = hipMalloc((void **)&c->d_q[0], qb)) != hipSuccess || (e = hipMalloc((void **)&c->d_q[1], qb)) != hipSuccess ||
+    free_workspace(c);
+    int64_t mch = max_chunks_for(cap);
+    size_t list = (size_t)(cap + 64 * MAX_SETS);
+    if ((e = hipMalloc((void **)&c->d_st, (size_t)cap * rti::Q_NFIELDS * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_ids[0], list * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_ids[1], list * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_cmask, (size_t)mch * sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_cscan, (size_t)mch * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void **)&c->d_bscan, (size_t)(mch / rti::SCAN_BLOCK + 2) * sizeof(int))) != hipSuccess ||
         (e = hipMalloc((void **)&c->d_rec, (size_t)cap * rti::REC_F4 * sizeof(float4))) != hipSuccess) {
-        hipFree(c->d_q[0]);
-        hipFree(c->d_q[1]);
-        hipFree(c->d_rec);
-        c->d_q[0] = c->d_q[1] = nullptr;
-        c->d_rec = nullptr;
+        free_workspace(c);
         return hip_fail(c, e, "hipMalloc (workspace)");
     }
-    c->q_cap = cap;
+    c->ws_cap = cap;
     return RT_OK;
 }
 
-rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
-                   void *stream) {
+// Shared body of rt_trace and rt_trace_fwd_ckpt (tape != NULL).
+static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
+                            void *stream, void *tape, size_t tape_bytes, int ckpt_every) {
     if (!c) return RT_EINVAL;
     if (!cam || !r || !o) return fail(c, RT_EINVAL, "rt_trace: NULL camera, rule or outputs");
     if (!c->has_metric || !c->has_scene) return fail(c, RT_ESTATE, "rt_trace: set the metric and the scene first");
@@ -380,7 +416,10 @@ rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int m
 
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    int64_t cap = hw * c->n_sets;
+    const int tiles_x = (cam->width + 7) / 8, tiles_y = (cam->height + 7) / 8;
+    const int64_t T = (int64_t)tiles_x * tiles_y * 64;
+    int64_t cap = T * c->n_sets;
+    if (cap > 2147483647LL - 4096) return fail(c, RT_EINVAL, "rt_trace: frame too large");
     rt_status st = ensure_workspace(c, cap);
     if (st != RT_OK) return st;
 
@@ -403,8 +442,9 @@ rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int m
     a.aspect = (float)((double)cam->width / (double)cam->height);
     a.width = cam->width;
     a.height = cam->height;
-    a.tiles_x = (cam->width + 7) / 8;
-    a.tiles_y = (cam->height + 7) / 8;
+    a.tiles_x = tiles_x;
+    a.tiles_y = tiles_y;
+    a.T = (int)T;
     a.step_kind = r->kind;
     a.h = r->h;
     a.rtol = r->rtol;
@@ -426,8 +466,13 @@ rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int m
     float vmax = c->kind == RT_METRIC_PULLBACK_TWIST ? 1.05f : 1.0f;
     a.cull_margin = c->kind == RT_METRIC_PULLBACK_ZTWIST ? -1.0f
                                                          : (float)((r->cull_every + 1) * (double)a.h_max * vmax * 1.02 + 1e-4);
-    a.q[0] = c->d_q[0];
-    a.q[1] = c->d_q[1];
+    a.st = c->d_st;
+    a.ids[0] = c->d_ids[0];
+    a.ids[1] = c->d_ids[1];
+    a.cmask = c->d_cmask;
+    a.cscan = c->d_cscan;
+    a.bscan = c->d_bscan;
+    a.max_chunks = (int)max_chunks_for(cap);
     a.cap = cap;
     a.ctr = c->d_ctr;
     a.stats = c->d_stats;
@@ -437,6 +482,20 @@ rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int m
     a.out_dir = o->dir;
     a.out_id = o->id;
     a.out_steps = o->steps;
+    a.tape_ck = nullptr;
+    a.tape_hit = nullptr;
+    a.ckpt_every = 1;
+    a.n_ckpt = 1;
+    if (tape) {
+        size_t need = rt_tape_bytes(cam, c->n_sets, max_steps, ckpt_every);
+        if (tape_bytes < need)
+            return fail(c, RT_EINVAL, "rt_trace_fwd_ckpt: tape_bytes " + std::to_string(tape_bytes) + " < " +
+                                          std::to_string(need));
+        a.ckpt_every = ckpt_every;
+        a.n_ckpt = (max_steps + ckpt_every - 1) / ckpt_every;
+        a.tape_ck = (float *)tape;
+        a.tape_hit = (float *)tape + (size_t)cap * a.n_ckpt * 9;
+    }
 
     int bpc = rti::trace_blocks_per_cu(a.kind, a.step_kind);
     int64_t chunks = cap / 64 + 1;
@@ -452,7 +511,7 @@ rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int m
     hipStream_t s = (hipStream_t)stream;
     bool timed = (r->flags & RT_FLAG_TIMING) != 0;
     if (timed) {
-        while ((int)c->ev.size() < n_passes + 3) {
+        while ((int)c->ev.size() < 3 * n_passes + 3) {
             hipEvent_t ev;
             if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(c, e, "hipEventCreate");
             c->ev.push_back(ev);
@@ -464,7 +523,102 @@ rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int m
     c->traced = true;
     c->last_passes = n_passes;
     c->last_timed = timed;
+    if (tape) {
+        c->adj_args = a;
+        c->adj_tape = tape;
+        c->adj_valid = true;
+    }
     c->err.clear();
+    return RT_OK;
+}
+
+rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
+                   void *stream) {
+    return trace_impl(c, cam, r, max_steps, o, stream, nullptr, 0, 0);
+}
+
+size_t rt_tape_bytes(const rt_camera *cam, int n_sets, int max_steps, int ckpt_every) {
+    if (!cam || cam->width < 1 || cam->height < 1 || n_sets < 1 || max_steps < 1 || ckpt_every < 1) return 0;
+    size_t tiles = (size_t)((cam->width + 7) / 8) * ((cam->height + 7) / 8);
+    size_t cap = tiles * 64 * (size_t)n_sets;
+    size_t n_ckpt = ((size_t)max_steps + ckpt_every - 1) / ckpt_every;
+    return (cap * n_ckpt * 9 + (size_t)n_sets * cam->width * cam->height * rti::TAPE_REC) * sizeof(float);
+}
+
+rt_status rt_trace_fwd_ckpt(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, int ckpt_every,
+                            const rt_outputs *o, void *tape, size_t tape_bytes, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (!tape) return fail(c, RT_EINVAL, "rt_trace_fwd_ckpt: tape is NULL");
+    if (ckpt_every < 1 || ckpt_every > max_steps)
+        return fail(c, RT_EINVAL, "rt_trace_fwd_ckpt: ckpt_every must be in 1..max_steps");
+    if (!c->has_metric || c->kind != RT_METRIC_GRAPH_GAUSS)
+        return fail(c, RT_EUNSUPPORTED, "rt_trace_fwd_ckpt: differentiation needs the graph metric");
+    if (c->n_bumps < 1 || c->n_bumps > rti::adjoint_max_bumps())
+        return fail(c, RT_EUNSUPPORTED, "rt_trace_fwd_ckpt: differentiation supports 1..16 bumps per set");
+    if (r && r->kind != RT_STEP_RK4) return fail(c, RT_EUNSUPPORTED, "rt_trace_fwd_ckpt: the adjoint is RK4 only");
+    c->adj_valid = false;
+    return trace_impl(c, cam, r, max_steps, o, stream, tape, tape_bytes, ckpt_every);
+}
+
+rt_status rt_loss_l2(rt_ctx *c, const rt_camera *cam, const float *hit, const int32_t *id, const float *target_hit,
+                     const int32_t *target_id, const uint8_t *mask, float *loss, float *grad_hit, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (!cam || !hit || !id || !target_hit || !target_id || !loss)
+        return fail(c, RT_EINVAL, "rt_loss_l2: NULL argument");
+    if (cam->width < 1 || cam->height < 1) return fail(c, RT_EINVAL, "rt_loss_l2: bad frame size");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_loss_l2: host-only context");
+    int HW = cam->width * cam->height;
+    int64_t nblk = ((int64_t)HW + 255) / 256;
+    int64_t need = nblk * c->n_sets;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if (c->loss_cap < need) {
+        rt_status st = sync_last(c);
+        if (st != RT_OK) return st;
+        hipFree(c->d_loss_blk);
+        c->d_loss_blk = nullptr;
+        c->loss_cap = 0;
+        if ((e = hipMalloc((void **)&c->d_loss_blk, need * sizeof(float))) != hipSuccess)
+            return hip_fail(c, e, "hipMalloc (loss)");
+        c->loss_cap = need;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    e = rti::launch_loss(hit, id, target_hit, target_id, mask, c->n_sets, HW, grad_hit, c->d_loss_blk, loss, s);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (loss)");
+    c->last_stream = s;
+    c->traced = true;
+    return RT_OK;
+}
+
+rt_status rt_trace_bwd(rt_ctx *c, const void *tape, const float *grad_hit, float *grad_params, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (!tape || !grad_hit || !grad_params) return fail(c, RT_EINVAL, "rt_trace_bwd: NULL argument");
+    if (!c->adj_valid || c->adj_tape != tape)
+        return fail(c, RT_ESTATE, "rt_trace_bwd: no rt_trace_fwd_ckpt recorded this tape on this context");
+    rti::TraceArgs a = c->adj_args;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    int64_t chunks = (int64_t)a.n_sets * a.tiles_x * a.tiles_y;
+    int blocks = (int)std::min<int64_t>(chunks, (int64_t)c->n_cu * 16);
+    int64_t scr = (int64_t)blocks * a.ckpt_every * 9 * 64;
+    int64_t part = chunks * a.n_bumps * 5;
+    if (c->adj_scr_cap < scr || c->adj_part_cap < part) {
+        rt_status st = sync_last(c);
+        if (st != RT_OK) return st;
+        hipFree(c->d_adj_scr);
+        hipFree(c->d_adj_part);
+        c->d_adj_scr = c->d_adj_part = nullptr;
+        c->adj_scr_cap = c->adj_part_cap = 0;
+        if ((e = hipMalloc((void **)&c->d_adj_scr, scr * sizeof(float))) != hipSuccess ||
+            (e = hipMalloc((void **)&c->d_adj_part, part * sizeof(float))) != hipSuccess)
+            return hip_fail(c, e, "hipMalloc (adjoint scratch)");
+        c->adj_scr_cap = scr;
+        c->adj_part_cap = part;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    e = rti::launch_adjoint(a, c->dd, grad_hit, c->d_adj_part, grad_params, c->d_adj_scr, blocks, s);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (adjoint)");
+    c->last_stream = s;
     return RT_OK;
 }
 
@@ -498,13 +652,21 @@ rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
     out->obj_tests = v[rti::ST_OBJ_TESTS];
     out->passes = c->last_passes;
     if (c->last_timed) {
-        float ms = 0.f, pass = 0.f;
+        // events: 0 before reset, 1 after reset, 2+p after pass p, 2+np after
+        // refine, 2np+2+p after the compaction that precedes pass p (p >= 1)
+        float ms = 0.f, pass = 0.f, comp = 0.f;
         int np = c->last_passes;
         for (int p = 0; p < np; ++p) {
-            if ((e = hipEventElapsedTime(&ms, c->ev[1 + p], c->ev[2 + p])) != hipSuccess) return hip_fail(c, e, "timing");
+            hipEvent_t start = p == 0 ? c->ev[1] : c->ev[2 * np + 2 + p];
+            if ((e = hipEventElapsedTime(&ms, start, c->ev[2 + p])) != hipSuccess) return hip_fail(c, e, "timing");
             pass += ms;
+            if (p > 0) {
+                if ((e = hipEventElapsedTime(&ms, c->ev[1 + p], start)) != hipSuccess) return hip_fail(c, e, "timing");
+                comp += ms;
+            }
         }
         out->pass_ms = pass;
+        out->compact_ms = comp;
         if ((e = hipEventElapsedTime(&ms, c->ev[1 + np], c->ev[2 + np])) != hipSuccess) return hip_fail(c, e, "timing");
         out->refine_ms = ms;
         if ((e = hipEventElapsedTime(&ms, c->ev[0], c->ev[2 + np])) != hipSuccess) return hip_fail(c, e, "timing");

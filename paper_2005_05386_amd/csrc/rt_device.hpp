@@ -54,15 +54,30 @@ template <class T> __device__ __forceinline__ T log2e_() { return T(1.4426950408
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// DPP lane movement within the wave (GFX9 encodings): quad permutations
+// xor-1 and xor-2, row half-mirror, row mirror, and the row broadcasts of
+// lane 15 / lane 31 into the following rows.
+template <int CTRL, int ROW_MASK = 0xF> __device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+// Wave-wide min / max (all 64 lanes must be active); result is uniform.
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
+    v = fminf(v, dpp<0xB1>(v));
+    v = fminf(v, dpp<0x4E>(v));
+    v = fminf(v, dpp<0x141>(v));
+    v = fminf(v, dpp<0x140>(v));
+    v = fminf(v, dpp<0x142, 0xA>(v));
+    v = fminf(v, dpp<0x143, 0xC>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    v = fmaxf(v, dpp<0xB1>(v));
+    v = fmaxf(v, dpp<0x4E>(v));
+    v = fmaxf(v, dpp<0x141>(v));
+    v = fmaxf(v, dpp<0x140>(v));
+    v = fmaxf(v, dpp<0x142, 0xA>(v));
+    v = fmaxf(v, dpp<0x143, 0xC>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 // inclusive prefix sum over the 64 lanes
 __device__ __forceinline__ int wave_incl_scan(int v) {
@@ -118,22 +133,34 @@ __device__ __forceinline__ V3<float> graph_finish(const GraphAccum &A) {
     return {c * A.gx, c * A.gy, c * A.gz};
 }
 
-// Walk a wave-uniform bump mask; bump data by scalar loads.  COUNT adds the
-// number of bumps inside their cut sphere at p to *n_in.
+// Walk a wave-uniform bump mask; bump data by scalar loads, two bumps per
+// iteration so that both bumps' loads are in flight before the first wait.
+// The accumulation order (increasing bump index) is unchanged.  COUNT adds
+// the number of bumps inside their cut sphere at p to *n_in.
 template <bool COUNT = false>
 __device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
                                                      V3<float> y, unsigned *n_in = nullptr) {
     GraphAccum A{0.f, 0.f, 0.f, 0.f};
     float yy = dot(y, y);
     unsigned n = 0;
+    auto in_cut = [&](float4 b0, float4 b1) {
+        float dx = p.x - b0.x, dy = p.y - b0.y, dz = p.z - b0.z;
+        return (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= b1.z) ? 1u : 0u;
+    };
     while (mask) {
-        int b = __builtin_ctzll(mask);
+        const int b = __builtin_ctzll(mask);
         mask &= mask - 1;
-        float4 b0 = B[2 * b], b1 = B[2 * b + 1];
-        graph_bump_f32(b0, b1, p, y, yy, A);
-        if (COUNT) {
-            float dx = p.x - b0.x, dy = p.y - b0.y, dz = p.z - b0.z;
-            n += (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= b1.z) ? 1u : 0u;
+        if (mask) {
+            const int c = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const float4 b0 = B[2 * b], b1 = B[2 * b + 1], c0 = B[2 * c], c1 = B[2 * c + 1];
+            graph_bump_f32(b0, b1, p, y, yy, A);
+            graph_bump_f32(c0, c1, p, y, yy, A);
+            if (COUNT) n += in_cut(b0, b1) + in_cut(c0, c1);
+        } else {
+            const float4 b0 = B[2 * b], b1 = B[2 * b + 1];
+            graph_bump_f32(b0, b1, p, y, yy, A);
+            if (COUNT) n += in_cut(b0, b1);
         }
     }
     if (COUNT) *n_in += n;

@@ -1,0 +1,175 @@
+// Integration steps shared by the trace and the adjoint kernels, so that
+// the adjoint's recomputation of a trajectory repeats the forward
+// arithmetic exactly.
+#pragma once
+
+#include "rt_device.hpp"
+
+namespace rtd {
+
+// ------------------------------------------------ Dormand-Prince 5(4) table
+// Coefficients of Dormand & Prince (1980).  The flow is second order
+// (x' = y, y' = a(x, y)), so with A_l = a(X_l, Y_l) the stage states are
+//   Y_i = y + h sum_l a_il A_l,  X_i = x + h c_i y + h^2 sum_l (a a)_il A_l
+// and the step and its error estimate need only the A_l.
+constexpr double DPA[7][7] = {
+    {0, 0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0}};
+constexpr double DPB[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+constexpr double DPBH[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+
+constexpr double dp_c(int i) {
+    double s = 0;
+    for (int j = 0; j < 7; ++j) s += DPA[i][j];
+    return s;
+}
+constexpr double dp_aa(int i, int l) {
+    double s = 0;
+    for (int j = 0; j < 7; ++j) s += DPA[i][j] * DPA[j][l];
+    return s;
+}
+constexpr double dp_ba(int l) {
+    double s = 0;
+    for (int i = 0; i < 7; ++i) s += DPB[i] * DPA[i][l];
+    return s;
+}
+constexpr double dp_ea(int l) {
+    double s = 0;
+    for (int i = 0; i < 7; ++i) s += (DPB[i] - DPBH[i]) * DPA[i][l];
+    return s;
+}
+
+// --------------------------------------------------------------- steppers
+// Each stepper returns the increments (dx, dv) of one step of size h from
+// (p, y); acc(p, y, a) evaluates the acceleration and reports failure.
+template <class T, class F>
+__device__ __forceinline__ bool step_euler(F &acc, V3<T> p, V3<T> y, T h, V3<T> &dx, V3<T> &dv,
+                                           const V3<T> *k1 = nullptr) {
+    V3<T> a;
+    bool ok = true;
+    if (k1)
+        a = *k1;
+    else
+        ok = acc(p, y, a);
+    dx = h * y;
+    dv = h * a;
+    return ok;
+}
+
+template <class T, class F>
+__device__ __forceinline__ bool step_rk4(F &acc, V3<T> p, V3<T> y, T h, V3<T> &dx, V3<T> &dv,
+                                         const V3<T> *k1 = nullptr) {
+    // Classical RK4 on (x, y): stage s evaluates k_s = a(P_s, Y_s) with
+    // (P_0, Y_0) = (p, y) and (P_s, Y_s) = (p + c_s Y_{s-1}, y + c_s k_{s-1}),
+    // c = (h/2, h/2, h); the stage sums with weights (1, 2, 2, 1) are
+    // accumulated as the stages are produced.  The stage loop is kept rolled
+    // so that the acceleration (the bump walk) is emitted once.
+    const T hh = T(0.5) * h;
+    V3<T> P = p, Y = y;
+    V3<T> sx = mk(T(0), T(0), T(0)), sv = mk(T(0), T(0), T(0));
+    bool ok = true;
+#pragma unroll 1
+    for (int st = 0; st < 4; ++st) {
+        V3<T> k;
+        if (st == 0 && k1)
+            k = *k1;  // first stage supplied by the caller
+        else
+            ok &= acc(P, Y, k);
+        const T w = (st == 0 || st == 3) ? T(1) : T(2);
+        sx = axpy(w, Y, sx);
+        sv = axpy(w, k, sv);
+        const T c = st < 2 ? hh : h;
+        P = axpy(c, Y, p);
+        Y = axpy(c, k, y);
+    }
+    const T h6 = h * T(1.0 / 6.0);
+    dx = h6 * sx;
+    dv = h6 * sv;
+    return ok;
+}
+
+// Dormand-Prince 5(4).  On entry A0 = a(p, y); on exit A0 = a at the new
+// state (first-same-as-last).  ex, ev: embedded error h*sum(b - bhat)k.
+template <class T, class F>
+__device__ __forceinline__ bool step_dp5(F &acc, V3<T> p, V3<T> y, T h, V3<T> &A0, V3<T> &dx, V3<T> &dv,
+                                         V3<T> &ex, V3<T> &ev) {
+    V3<T> Ak[7];
+    Ak[0] = A0;
+    bool ok = true;
+    T h2 = h * h;
+#pragma unroll
+    for (int i = 1; i < 7; ++i) {
+        V3<T> X = axpy(h * T(dp_c(i)), y, p);
+        V3<T> Y = y;
+#pragma unroll
+        for (int l = 0; l < i; ++l) {
+            if (DPA[i][l] != 0.0) Y = axpy(h * T(DPA[i][l]), Ak[l], Y);
+            if (dp_aa(i, l) != 0.0) X = axpy(h2 * T(dp_aa(i, l)), Ak[l], X);
+        }
+        ok &= acc(X, Y, Ak[i]);
+    }
+    dx = h * y;
+    dv = mk(T(0), T(0), T(0));
+    ex = mk(T(0), T(0), T(0));
+    ev = mk(T(0), T(0), T(0));
+#pragma unroll
+    for (int l = 0; l < 7; ++l) {
+        if (dp_ba(l) != 0.0) dx = axpy(h2 * T(dp_ba(l)), Ak[l], dx);
+        if (DPB[l] != 0.0) dv = axpy(h * T(DPB[l]), Ak[l], dv);
+        if (dp_ea(l) != 0.0) ex = axpy(h2 * T(dp_ea(l)), Ak[l], ex);
+        if (DPB[l] - DPBH[l] != 0.0) ev = axpy(h * T(DPB[l] - DPBH[l]), Ak[l], ev);
+    }
+    A0 = Ak[6];
+    return ok;
+}
+
+// Knuth's TwoSum followed by a fast renormalisation: (hi, lo) += d.
+__device__ __forceinline__ void two_sum_add(float &hi, float &lo, float d) {
+    float s = hi + d;
+    float bp = s - hi;
+    float e = (hi - (s - bp)) + (d - bp);
+    float l = lo + e;
+    float hn = s + l;
+    lo = l - (hn - s);
+    hi = hn;
+}
+
+__device__ __forceinline__ float box_dist2(float cx, float cy, float cz, const float lo[3], const float hi[3]) {
+    float dx = fmaxf(fmaxf(lo[0] - cx, cx - hi[0]), 0.0f);
+    float dy = fmaxf(fmaxf(lo[1] - cy, cy - hi[1]), 0.0f);
+    float dz = fmaxf(fmaxf(lo[2] - cz, cz - hi[2]), 0.0f);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ __forceinline__ bool finite3(V3<float> v) {
+    return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z);
+}
+
+template <int KIND, bool COUNT> struct Acc32 {
+    const float4 *__restrict__ B;
+    uint64_t mask;
+    float amp, th0;
+    unsigned *n_eval, *n_bump;  // COUNT only
+    __device__ __forceinline__ bool operator()(V3<float> p, V3<float> y, V3<float> &a) const {
+        if (COUNT) *n_eval += 1;
+        if constexpr (KIND == KIND_GRAPH) {
+            a = graph_accel_f32<COUNT>(B, mask, p, y, n_bump);
+            return true;
+        } else if constexpr (KIND == KIND_TWIST) {
+            return twist_accel<float>(amp, th0, p, y, a);
+        } else if constexpr (KIND == KIND_ZTWIST) {
+            a = ztwist_accel<float>(p, y);
+            return true;
+        } else {
+            a = mk(0.f, 0.f, 0.f);
+            return true;
+        }
+    }
+};
+
+}  // namespace rtd

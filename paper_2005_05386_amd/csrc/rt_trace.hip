@@ -19,160 +19,18 @@
 // cull_sigmas*sigma) and objects against it: lane i tests bump i / sphere
 // 64w+i and a ballot turns the answers into wave-uniform masks.  Bump
 // parameters for the masked bumps are then read with scalar loads.
+#include <algorithm>
+
 #include "rt_device.hpp"
 #include "rt_internal.hpp"
+#include "rt_step.hpp"
 
 using namespace rtd;
 using rti::TraceArgs;
 
 namespace {
 
-// ------------------------------------------------ Dormand-Prince 5(4) table
-// Coefficients of Dormand & Prince (1980).  The flow is second order
-// (x' = y, y' = a(x, y)), so with A_l = a(X_l, Y_l) the stage states are
-//   Y_i = y + h sum_l a_il A_l,  X_i = x + h c_i y + h^2 sum_l (a a)_il A_l
-// and the step and its error estimate need only the A_l.
-constexpr double DPA[7][7] = {
-    {0, 0, 0, 0, 0, 0, 0},
-    {1.0 / 5, 0, 0, 0, 0, 0, 0},
-    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0, 0},
-    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0, 0},
-    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0, 0},
-    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0, 0},
-    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0}};
-constexpr double DPB[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
-constexpr double DPBH[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
-
-constexpr double dp_c(int i) {
-    double s = 0;
-    for (int j = 0; j < 7; ++j) s += DPA[i][j];
-    return s;
-}
-constexpr double dp_aa(int i, int l) {
-    double s = 0;
-    for (int j = 0; j < 7; ++j) s += DPA[i][j] * DPA[j][l];
-    return s;
-}
-constexpr double dp_ba(int l) {
-    double s = 0;
-    for (int i = 0; i < 7; ++i) s += DPB[i] * DPA[i][l];
-    return s;
-}
-constexpr double dp_ea(int l) {
-    double s = 0;
-    for (int i = 0; i < 7; ++i) s += (DPB[i] - DPBH[i]) * DPA[i][l];
-    return s;
-}
-
-// --------------------------------------------------------------- steppers
-// Each stepper returns the increments (dx, dv) of one step of size h from
-// (p, y); acc(p, y, a) evaluates the acceleration and reports failure.
-template <class T, class F>
-__device__ __forceinline__ bool step_euler(F &acc, V3<T> p, V3<T> y, T h, V3<T> &dx, V3<T> &dv) {
-    V3<T> a;
-    bool ok = acc(p, y, a);
-    dx = h * y;
-    dv = h * a;
-    return ok;
-}
-
-template <class T, class F>
-__device__ __forceinline__ bool step_rk4(F &acc, V3<T> p, V3<T> y, T h, V3<T> &dx, V3<T> &dv) {
-    V3<T> k1, k2, k3, k4;
-    T hh = T(0.5) * h;
-    bool ok = acc(p, y, k1);
-    V3<T> y2 = axpy(hh, k1, y);
-    ok &= acc(axpy(hh, y, p), y2, k2);
-    V3<T> y3 = axpy(hh, k2, y);
-    ok &= acc(axpy(hh, y2, p), y3, k3);
-    V3<T> y4 = axpy(h, k3, y);
-    ok &= acc(axpy(h, y3, p), y4, k4);
-    T h6 = h * T(1.0 / 6.0);
-    dx = h6 * (y + T(2) * (y2 + y3) + y4);
-    dv = h6 * (k1 + T(2) * (k2 + k3) + k4);
-    return ok;
-}
-
-// Dormand-Prince 5(4).  On entry A0 = a(p, y); on exit A0 = a at the new
-// state (first-same-as-last).  ex, ev: embedded error h*sum(b - bhat)k.
-template <class T, class F>
-__device__ __forceinline__ bool step_dp5(F &acc, V3<T> p, V3<T> y, T h, V3<T> &A0, V3<T> &dx, V3<T> &dv,
-                                         V3<T> &ex, V3<T> &ev) {
-    V3<T> Ak[7];
-    Ak[0] = A0;
-    bool ok = true;
-    T h2 = h * h;
-#pragma unroll
-    for (int i = 1; i < 7; ++i) {
-        V3<T> X = axpy(h * T(dp_c(i)), y, p);
-        V3<T> Y = y;
-#pragma unroll
-        for (int l = 0; l < i; ++l) {
-            if (DPA[i][l] != 0.0) Y = axpy(h * T(DPA[i][l]), Ak[l], Y);
-            if (dp_aa(i, l) != 0.0) X = axpy(h2 * T(dp_aa(i, l)), Ak[l], X);
-        }
-        ok &= acc(X, Y, Ak[i]);
-    }
-    dx = h * y;
-    dv = mk(T(0), T(0), T(0));
-    ex = mk(T(0), T(0), T(0));
-    ev = mk(T(0), T(0), T(0));
-#pragma unroll
-    for (int l = 0; l < 7; ++l) {
-        if (dp_ba(l) != 0.0) dx = axpy(h2 * T(dp_ba(l)), Ak[l], dx);
-        if (DPB[l] != 0.0) dv = axpy(h * T(DPB[l]), Ak[l], dv);
-        if (dp_ea(l) != 0.0) ex = axpy(h2 * T(dp_ea(l)), Ak[l], ex);
-        if (DPB[l] - DPBH[l] != 0.0) ev = axpy(h * T(DPB[l] - DPBH[l]), Ak[l], ev);
-    }
-    A0 = Ak[6];
-    return ok;
-}
-
-// Knuth's TwoSum followed by a fast renormalisation: (hi, lo) += d.
-__device__ __forceinline__ void two_sum_add(float &hi, float &lo, float d) {
-    float s = hi + d;
-    float bp = s - hi;
-    float e = (hi - (s - bp)) + (d - bp);
-    float l = lo + e;
-    float hn = s + l;
-    lo = l - (hn - s);
-    hi = hn;
-}
-
-__device__ __forceinline__ float box_dist2(float cx, float cy, float cz, const float lo[3], const float hi[3]) {
-    float dx = fmaxf(fmaxf(lo[0] - cx, cx - hi[0]), 0.0f);
-    float dy = fmaxf(fmaxf(lo[1] - cy, cy - hi[1]), 0.0f);
-    float dz = fmaxf(fmaxf(lo[2] - cz, cz - hi[2]), 0.0f);
-    return dx * dx + dy * dy + dz * dz;
-}
-
-__device__ __forceinline__ bool finite3(V3<float> v) {
-    return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z);
-}
-
-template <int KIND, bool COUNT> struct Acc32 {
-    const float4 *__restrict__ B;
-    uint64_t mask;
-    float amp, th0;
-    unsigned *n_eval, *n_bump;  // COUNT only
-    __device__ __forceinline__ bool operator()(V3<float> p, V3<float> y, V3<float> &a) const {
-        if (COUNT) *n_eval += 1;
-        if constexpr (KIND == KIND_GRAPH) {
-            a = graph_accel_f32<COUNT>(B, mask, p, y, n_bump);
-            return true;
-        } else if constexpr (KIND == KIND_TWIST) {
-            return twist_accel<float>(amp, th0, p, y, a);
-        } else if constexpr (KIND == KIND_ZTWIST) {
-            a = ztwist_accel<float>(p, y);
-            return true;
-        } else {
-            a = mk(0.f, 0.f, 0.f);
-            return true;
-        }
-    }
-};
-
-__device__ __forceinline__ void write_out(const TraceArgs &A, int64_t oi, V3<float> x, float t, V3<float> y, int id,
+__device__ __forceinline__ void write_out(const TraceArgs &A, unsigned oi, V3<float> x, float t, V3<float> y, int id,
                                           int steps) {
     A.out_hit[3 * oi + 0] = x.x;
     A.out_hit[3 * oi + 1] = x.y;
@@ -184,6 +42,59 @@ __device__ __forceinline__ void write_out(const TraceArgs &A, int64_t oi, V3<flo
     A.out_dir[3 * oi + 1] = y.y * n;
     A.out_dir[3 * oi + 2] = y.z * n;
     if (A.out_steps) A.out_steps[oi] = steps;
+}
+
+// ========================================================= ray generation
+// Initial state of every ray: x = eye, y = the pixel direction d scaled to
+// unit length in the metric at the eye (y = d / sqrt(g(d, d))).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restrict__ BF) {
+    const int64_t n = A.cap;
+    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n; id += (int64_t)gridDim.x * blockDim.x) {
+        const int set = (int)(id / A.T);
+        const int r = (int)(id - (int64_t)set * A.T);
+        const int tile = r >> 6, ln = r & 63;
+        const int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
+        const int pi = tx * 8 + (ln & 7), pj = ty * 8 + (ln >> 3);
+        if (pi >= A.width || pj >= A.height) continue;
+        const float4 *__restrict__ Bs = BF + (int64_t)set * A.n_bumps * 2;
+        float su = (2.0f * ((float)pi + 0.5f) / (float)A.width - 1.0f) * A.tan_half * A.aspect;
+        float sv = (1.0f - 2.0f * ((float)pj + 0.5f) / (float)A.height) * A.tan_half;
+        V3<float> d = mk(su * A.right[0] + sv * A.up[0] + A.fwd[0], su * A.right[1] + sv * A.up[1] + A.fwd[1],
+                         su * A.right[2] + sv * A.up[2] + A.fwd[2]);
+        d = rsqrt_(dot(d, d)) * d;
+        V3<float> e = mk(A.eye[0], A.eye[1], A.eye[2]);
+        float gdd;
+        if constexpr (KIND == KIND_GRAPH) {
+            GraphAccum G{0.f, 0.f, 0.f, 0.f};
+            for (int b = 0; b < A.n_bumps; ++b) graph_bump_f32(Bs[2 * b], Bs[2 * b + 1], e, d, 1.0f, G);
+            float gd = G.gx * d.x + G.gy * d.y + G.gz * d.z;
+            gdd = dot(d, d) + gd * gd;
+        } else if constexpr (KIND == KIND_TWIST) {
+            gdd = twist_gdd<float>(A.twist_amp, A.twist_theta0, e, d);
+        } else if constexpr (KIND == KIND_ZTWIST) {
+            gdd = ztwist_gdd<float>(e, d);
+        } else {
+            gdd = dot(d, d);
+        }
+        V3<float> y = rsqrt_(gdd) * d;
+        float *__restrict__ dst = A.st + ((id >> 6) * rti::Q_NFIELDS * 64 + (id & 63));
+        auto P = [&](int f, float v) { dst[f * 64] = v; };
+        P(rti::Q_XH, e.x);
+        P(rti::Q_XH + 1, e.y);
+        P(rti::Q_XH + 2, e.z);
+        P(rti::Q_XL, 0.f);
+        P(rti::Q_XL + 1, 0.f);
+        P(rti::Q_XL + 2, 0.f);
+        P(rti::Q_Y, y.x);
+        P(rti::Q_Y + 1, y.y);
+        P(rti::Q_Y + 2, y.z);
+        P(rti::Q_TH, 0.f);
+        P(rti::Q_TL, 0.f);
+        P(rti::Q_H, A.h);
+        P(rti::Q_STEPS, __int_as_float(0));
+        P(rti::Q_ATT, __int_as_float(0));
+    }
 }
 
 // ================================================================ the pass
@@ -200,7 +111,8 @@ __global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const
     const int n_bumps = A.n_bumps, ns = A.n_spheres, np = A.n_planes, nt = A.n_tori;
     const int nsw = (ns + 63) >> 6;
 
-    // chunk table of this pass
+    // chunk table of this pass: pass 0 walks every tile of every set; pass
+    // p > 0 walks the sorted survivor list, each set padded to whole chunks
     int total_chunks, pre = 0, cnt = 0;
     if (pass == 0) {
         total_chunks = A.n_sets * tiles;
@@ -210,8 +122,9 @@ __global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const
         pre = wave_incl_scan((cnt + 63) >> 6);
         total_chunks = uniform_i(__shfl(pre, 63));
     }
-    const float *__restrict__ qin = A.q[(pass + 1) & 1];
-    float *__restrict__ qout = A.q[pass & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) pass_ctr[rti::CTR_NCH] = total_chunks;
+    const int *__restrict__ ids_in = A.ids[pass & 1];
+    float *__restrict__ st = A.st;
     const int64_t cap = A.cap;
 
     unsigned long long st_wave = 0, st_lane = 0, st_bl = 0, st_ol = 0, st_steps = 0, st_rays = 0;
@@ -227,64 +140,45 @@ __global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const
             const int chunk = k * N_XCD + xp;
             if (chunk >= total_chunks) break;
 
-            // ---- resolve the set and this lane's ray
-            int set, slot = 0, pix = 0;
+            // ---- resolve the set and this lane's ray id
+            int set, id;
             bool valid;
             if (pass == 0) {
                 set = chunk / tiles;
-                int tile = chunk - set * tiles;
-                int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
-                int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
-                valid = i < A.width && j < A.height;
-                pix = j * A.width + i;
+                id = chunk * 64 + lane;
+                valid = true;
             } else {
                 set = __popcll(ballot(pre <= chunk));
                 int base_chunk = set > 0 ? __shfl(pre, set - 1) : 0;
                 int cnt_s = __shfl(cnt, set);
-                slot = (chunk - base_chunk) * 64 + lane;
-                valid = slot < cnt_s;
+                valid = (chunk - base_chunk) * 64 + lane < cnt_s;
+                id = valid ? ids_in[chunk * 64 + lane] : 0;
             }
             set = uniform_i(set);
+            // pixel of the ray: id = (set * tiles + tile) * 64 + lane-in-tile
+            const int r = id - set * A.T;
+            const int tile = r >> 6, tl_lane = r & 63;
+            const int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
+            const int pi = tx * 8 + (tl_lane & 7), pj = ty * 8 + (tl_lane >> 3);
+            if (pass == 0) valid = pi < A.width && pj < A.height;
+            const int pix = pj * A.width + pi;
             const float4 *__restrict__ Bs = BF + (int64_t)set * n_bumps * 2;
-            const int64_t qbase = (int64_t)set * HW;
+            const unsigned qbase = (unsigned)set * (unsigned)HW;
 
             V3<float> xh, xl, y;
             float th = 0.f, tl = 0.f, hc = A.h;
             int steps = 0, att = 0;
-            if (pass == 0) {
-                int i = pix % A.width, j = pix / A.width;
-                float su = (2.0f * ((float)i + 0.5f) / (float)A.width - 1.0f) * A.tan_half * A.aspect;
-                float sv = (1.0f - 2.0f * ((float)j + 0.5f) / (float)A.height) * A.tan_half;
-                V3<float> d = mk(su * A.right[0] + sv * A.up[0] + A.fwd[0], su * A.right[1] + sv * A.up[1] + A.fwd[1],
-                                 su * A.right[2] + sv * A.up[2] + A.fwd[2]);
-                d = rsqrt_(dot(d, d)) * d;
-                xh = mk(A.eye[0], A.eye[1], A.eye[2]);
-                xl = mk(0.f, 0.f, 0.f);
-                float gdd;
-                if constexpr (KIND == KIND_GRAPH) {
-                    GraphAccum G{0.f, 0.f, 0.f, 0.f};
-                    for (int b = 0; b < n_bumps; ++b) graph_bump_f32(Bs[2 * b], Bs[2 * b + 1], xh, d, 1.0f, G);
-                    float gd = G.gx * d.x + G.gy * d.y + G.gz * d.z;
-                    gdd = dot(d, d) + gd * gd;
-                } else if constexpr (KIND == KIND_TWIST) {
-                    gdd = twist_gdd<float>(A.twist_amp, A.twist_theta0, xh, d);
-                } else if constexpr (KIND == KIND_ZTWIST) {
-                    gdd = ztwist_gdd<float>(xh, d);
-                } else {
-                    gdd = dot(d, d);
-                }
-                y = rsqrt_(gdd) * d;
-            } else if (valid) {
-                const float *src = qin + qbase + slot;
-                xh = mk(src[rti::Q_XH * cap], src[(rti::Q_XH + 1) * cap], src[(rti::Q_XH + 2) * cap]);
-                xl = mk(src[rti::Q_XL * cap], src[(rti::Q_XL + 1) * cap], src[(rti::Q_XL + 2) * cap]);
-                y = mk(src[rti::Q_Y * cap], src[(rti::Q_Y + 1) * cap], src[(rti::Q_Y + 2) * cap]);
-                th = src[rti::Q_TH * cap];
-                tl = src[rti::Q_TL * cap];
-                hc = src[rti::Q_H * cap];
-                steps = __float_as_int(src[rti::Q_STEPS * cap]);
-                pix = __float_as_int(src[rti::Q_PIX * cap]);
-                att = __float_as_int(src[rti::Q_ATT * cap]);
+            if (valid) {
+                const float *__restrict__ src = st + ((int64_t)(id >> 6) * rti::Q_NFIELDS * 64 + (id & 63));
+                auto F = [&](int f) { return src[f * 64]; };
+                xh = mk(F(rti::Q_XH), F(rti::Q_XH + 1), F(rti::Q_XH + 2));
+                xl = mk(F(rti::Q_XL), F(rti::Q_XL + 1), F(rti::Q_XL + 2));
+                y = mk(F(rti::Q_Y), F(rti::Q_Y + 1), F(rti::Q_Y + 2));
+                th = F(rti::Q_TH);
+                tl = F(rti::Q_TL);
+                hc = F(rti::Q_H);
+                steps = __float_as_int(F(rti::Q_STEPS));
+                att = __float_as_int(F(rti::Q_ATT));
             } else {
                 xh = xl = y = mk(0.f, 0.f, 0.f);
             }
@@ -381,13 +275,25 @@ __global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const
                 st_bl += __popcll(bmask);
                 st_ol += __popcll(sm[0]) + __popcll(sm[1]) + __popcll(sm[2]) + __popcll(sm[3]) + __popcll(omask);
 
+                if (A.tape_ck && act && steps % A.ckpt_every == 0) {
+                    float *ck = A.tape_ck + ((((int64_t)(id >> 6) * A.n_ckpt + steps / A.ckpt_every) * 9) * 64 + (id & 63));
+                    ck[0 * 64] = xh.x;
+                    ck[1 * 64] = xh.y;
+                    ck[2 * 64] = xh.z;
+                    ck[3 * 64] = xl.x;
+                    ck[4 * 64] = xl.y;
+                    ck[5 * 64] = xl.z;
+                    ck[6 * 64] = y.x;
+                    ck[7 * 64] = y.y;
+                    ck[8 * 64] = y.z;
+                }
                 Acc32<KIND, COUNT> acc{Bs, bmask, A.twist_amp, A.twist_theta0, &c_eval, &c_bump};
-                bool hit = false, done_miss = false, done_fail = false;
+                // The step is computed, its chord tested against the scene on
+                // the state before the step, and only then committed: a hit
+                // records that pre-step state without keeping copies of it.
+                bool hit = false;
                 int hit_id = -1;
                 float hit_s = 2.f, hstep = A.h;
-                V3<float> xh0 = xh, xl0 = xl, y0 = y;
-                float th0 = th, tl0 = tl;
-                int steps0 = steps;
                 if (act) {
                     V3<float> p = xh + xl;
                     V3<float> dx, dv;
@@ -427,84 +333,80 @@ __global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const
                     } else {
                         ok = step_euler<float>(acc, p, y, A.h, dx, dv);
                     }
-                    if (!ok) {
-                        done_fail = true;
-                    } else if (accepted) {
+                    bool done_fail = !ok || !finite3(dx) || !finite3(dv);
+                    bool done_miss = false;
+                    if (!done_fail && accepted) {
                         if (COUNT) c_obj += lane_objs;
-                        two_sum_add(xh.x, xl.x, dx.x);
-                        two_sum_add(xh.y, xl.y, dx.y);
-                        two_sum_add(xh.z, xl.z, dx.z);
-                        y = y + dv;
-                        steps++;
-                        acc_pass++;
-                        if (STEP == STEP_RK45) two_sum_add(th, tl, hstep);
-                        if (!finite3(xh) || !finite3(y)) {
-                            done_fail = true;
-                        } else {
-                            // ---- segment versus scene
-                            float DD = dot(dx, dx);
+                        // ---- segment versus scene, chord [x, x + dx]
+                        float DD = dot(dx, dx);
 #pragma unroll
-                            for (int w = 0; w < 4; ++w) {
-                                uint64_t m = sm[w];
-                                while (m) {
-                                    int b = __builtin_ctzll(m);
-                                    m &= m - 1;
-                                    int idx = 64 * w + b;
-                                    float4 s = SPH[idx];
-                                    V3<float> o = mk((xh0.x - s.x) + xl0.x, (xh0.y - s.y) + xl0.y, (xh0.z - s.z) + xl0.z);
-                                    float sc = sphere_chord(s, o, dx, DD);
-                                    if (sc < hit_s) {
-                                        hit_s = sc;
-                                        hit_id = idx;
-                                    }
-                                }
-                            }
-                            uint64_t m = omask;
+                        for (int w = 0; w < 4; ++w) {
+                            uint64_t m = sm[w];
                             while (m) {
                                 int b = __builtin_ctzll(m);
                                 m &= m - 1;
-                                float F0, F1;
-                                int id;
-                                V3<float> x0 = xh0 + xl0;
-                                if (b < 8) {
-                                    float4 pl = PLN[b];
-                                    F0 = pl.x * x0.x + pl.y * x0.y + pl.z * x0.z - pl.w;
-                                    F1 = F0 + (pl.x * dx.x + pl.y * dx.y + pl.z * dx.z);
-                                    id = ns + b;
-                                } else {
-                                    const float *tp = TOR + 8 * (b - 8);
-                                    F0 = torus_sdf<float>(tp, x0);
-                                    F1 = torus_sdf<float>(tp, x0 + dx);
-                                    id = ns + np + (b - 8);
+                                int idx = 64 * w + b;
+                                float4 s = SPH[idx];
+                                V3<float> o = mk((xh.x - s.x) + xl.x, (xh.y - s.y) + xl.y, (xh.z - s.z) + xl.z);
+                                float sc = sphere_chord(s, o, dx, DD);
+                                if (sc < hit_s) {
+                                    hit_s = sc;
+                                    hit_id = idx;
                                 }
-                                if ((F0 > 0.f) != (F1 > 0.f)) {
-                                    float sc = fminf(fmaxf(F0 / (F0 - F1), 0.f), 1.f);
-                                    if (sc < hit_s) {
-                                        hit_s = sc;
-                                        hit_id = id;
-                                    }
-                                }
-                            }
-                            if (hit_id >= 0) {
-                                hit = true;
-                            } else {
-                                // RK45 lands on t_max up to float rounding of the clipped last step
-                                float t = (STEP == STEP_RK45) ? th + tl : (float)steps * A.h;
-                                float t_end = (STEP == STEP_RK45) ? A.t_max * (1.0f - 1e-6f) : A.t_max;
-                                if (steps >= A.max_steps || t >= t_end) done_miss = true;
                             }
                         }
+                        uint64_t m = omask;
+                        while (m) {
+                            int b = __builtin_ctzll(m);
+                            m &= m - 1;
+                            float F0, F1;
+                            int oid;
+                            if (b < 8) {
+                                float4 pl = PLN[b];
+                                F0 = pl.x * p.x + pl.y * p.y + pl.z * p.z - pl.w;
+                                F1 = F0 + (pl.x * dx.x + pl.y * dx.y + pl.z * dx.z);
+                                oid = ns + b;
+                            } else {
+                                const float *tp = TOR + 8 * (b - 8);
+                                F0 = torus_sdf<float>(tp, p);
+                                F1 = torus_sdf<float>(tp, p + dx);
+                                oid = ns + np + (b - 8);
+                            }
+                            if ((F0 > 0.f) != (F1 > 0.f)) {
+                                float sc = fminf(fmaxf(F0 / (F0 - F1), 0.f), 1.f);
+                                if (sc < hit_s) {
+                                    hit_s = sc;
+                                    hit_id = oid;
+                                }
+                            }
+                        }
+                        if (hit_id >= 0) {
+                            hit = true;
+                            acc_pass++;  // the hit step was integrated: count it
+                        } else {
+                            // commit the step
+                            two_sum_add(xh.x, xl.x, dx.x);
+                            two_sum_add(xh.y, xl.y, dx.y);
+                            two_sum_add(xh.z, xl.z, dx.z);
+                            y = y + dv;
+                            steps++;
+                            acc_pass++;
+                            if (STEP == STEP_RK45) two_sum_add(th, tl, hstep);
+                            // RK45 lands on t_max up to float rounding of the clipped last step
+                            float t = (STEP == STEP_RK45) ? th + tl : (float)steps * A.h;
+                            float t_end = (STEP == STEP_RK45) ? A.t_max * (1.0f - 1e-6f) : A.t_max;
+                            done_miss = steps >= A.max_steps || t >= t_end;
+                        }
                     }
-                    if (done_fail) {
-                        write_out(A, qbase + pix, xh0 + xl0,
-                                  STEP == STEP_RK45 ? th0 + tl0 : (float)steps0 * A.h, y0, -2, steps0);
-                    } else if (done_miss) {
-                        write_out(A, qbase + pix, xh + xl, STEP == STEP_RK45 ? th + tl : (float)steps * A.h, y, -1,
-                                  steps);
+                    if (done_fail || done_miss) {
+                        write_out(A, qbase + pix, xh + xl, STEP == STEP_RK45 ? th + tl : (float)steps * A.h, y,
+                                  done_fail ? -2 : -1, steps);
+                        if (A.tape_hit) A.tape_hit[(int64_t)(qbase + pix) * rti::TAPE_REC + 11] = __int_as_float(-1);
                     }
                     if (done_fail || done_miss || hit) alive = false;
                 }
-                // ---- push chord hits to the refine queue (wave-aggregated)
+                // ---- push chord hits to the refine queue (wave-aggregated);
+                // the lane's registers still hold the state before the step
                 uint64_t hm = ballot(hit);
                 if (hm) {
                     int base = 0;
@@ -513,11 +415,11 @@ __global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const
                     if (hit) {
                         int64_t r = base + mbcnt64(hm);
                         float4 *rec = A.rec + rti::REC_F4 * r;
-                        rec[0] = make_float4(xh0.x, xh0.y, xh0.z, xl0.x);
-                        rec[1] = make_float4(xl0.y, xl0.z, y0.x, y0.y);
-                        rec[2] = make_float4(y0.z, th0, hstep, hit_s);
+                        rec[0] = make_float4(xh.x, xh.y, xh.z, xl.x);
+                        rec[1] = make_float4(xl.y, xl.z, y.x, y.y);
+                        rec[2] = make_float4(y.z, th, hstep, hit_s);
                         rec[3] = make_float4(__int_as_float(hit_id), __int_as_float((int)(qbase + pix)),
-                                             __int_as_float(steps0), tl0);
+                                             __int_as_float(steps), tl);
                         rec[4] = make_float4(__int_as_float((int)(uint32_t)bmask), __int_as_float((int)(bmask >> 32)),
                                              0.f, 0.f);
                     }
@@ -525,29 +427,29 @@ __global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const
                 it++;
             }
 
-            // ---- compact survivors into the next queue
+            // ---- survivors keep their state in place; the chunk's alive mask
+            // and the per-set counts feed the ordered compaction after the pass
             uint64_t sv = ballot(alive);
+            if (lane == 0) A.cmask[chunk] = sv;
             if (sv) {
-                int base = 0;
-                if (lane == 0) base = atomicAdd(pass_ctr + rti::CTR_SURV + set, __popcll(sv));
-                base = uniform_i(__shfl(base, 0));
+                if (lane == 0) atomicAdd(pass_ctr + rti::CTR_SURV + set, __popcll(sv));
                 if (alive) {
-                    float *dst = qout + qbase + base + mbcnt64(sv);
-                    dst[rti::Q_XH * cap] = xh.x;
-                    dst[(rti::Q_XH + 1) * cap] = xh.y;
-                    dst[(rti::Q_XH + 2) * cap] = xh.z;
-                    dst[rti::Q_XL * cap] = xl.x;
-                    dst[(rti::Q_XL + 1) * cap] = xl.y;
-                    dst[(rti::Q_XL + 2) * cap] = xl.z;
-                    dst[rti::Q_Y * cap] = y.x;
-                    dst[(rti::Q_Y + 1) * cap] = y.y;
-                    dst[(rti::Q_Y + 2) * cap] = y.z;
-                    dst[rti::Q_TH * cap] = th;
-                    dst[rti::Q_TL * cap] = tl;
-                    dst[rti::Q_H * cap] = hc;
-                    dst[rti::Q_STEPS * cap] = __int_as_float(steps);
-                    dst[rti::Q_PIX * cap] = __int_as_float(pix);
-                    dst[rti::Q_ATT * cap] = __int_as_float(att);
+                    float *__restrict__ dst = st + ((int64_t)(id >> 6) * rti::Q_NFIELDS * 64 + (id & 63));
+                    auto P = [&](int f, float v) { dst[f * 64] = v; };
+                    P(rti::Q_XH, xh.x);
+                    P(rti::Q_XH + 1, xh.y);
+                    P(rti::Q_XH + 2, xh.z);
+                    P(rti::Q_XL, xl.x);
+                    P(rti::Q_XL + 1, xl.y);
+                    P(rti::Q_XL + 2, xl.z);
+                    P(rti::Q_Y, y.x);
+                    P(rti::Q_Y + 1, y.y);
+                    P(rti::Q_Y + 2, y.z);
+                    P(rti::Q_TH, th);
+                    P(rti::Q_TL, tl);
+                    P(rti::Q_H, hc);
+                    P(rti::Q_STEPS, __int_as_float(steps));
+                    P(rti::Q_ATT, __int_as_float(att));
                 }
             }
             // accepted steps of this chunk
@@ -635,17 +537,19 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
                 return true;
             }
         };
+        // every probe of the bisection restarts from the same state, so the
+        // first stage a(x_k, y_k) is evaluated once
         V3<double> a0;
-        if (STEP == STEP_RK45) acc(x, y, a0);
+        acc(x, y, a0);
         auto step = [&](double hs, V3<double> &xo, V3<double> &yo) {
             V3<double> dx, dv;
             if constexpr (STEP == STEP_RK45) {
                 V3<double> A1 = a0, ex, ev;
                 step_dp5<double>(acc, x, y, hs, A1, dx, dv, ex, ev);
             } else if constexpr (STEP == STEP_RK4) {
-                step_rk4<double>(acc, x, y, hs, dx, dv);
+                step_rk4<double>(acc, x, y, hs, dx, dv, &a0);
             } else {
-                step_euler<double>(acc, x, y, hs, dx, dv);
+                step_euler<double>(acc, x, y, hs, dx, dv, &a0);
             }
             xo = x + dx;
             yo = y + dv;
@@ -679,8 +583,101 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
         A.out_dir[3 * (int64_t)oi + 1] = (float)(ys.y * nrm);
         A.out_dir[3 * (int64_t)oi + 2] = (float)(ys.z * nrm);
         if (A.out_steps) A.out_steps[oi] = k + 1;
+        if (A.tape_hit) {
+            float *tr = A.tape_hit + (int64_t)oi * rti::TAPE_REC;
+            tr[0] = r0.x;
+            tr[1] = r0.y;
+            tr[2] = r0.z;
+            tr[3] = r0.w;
+            tr[4] = r1.x;
+            tr[5] = r1.y;
+            tr[6] = r1.z;
+            tr[7] = r1.w;
+            tr[8] = r2.x;
+            tr[9] = (float)s;
+            tr[10] = __int_as_float(k);
+            tr[11] = __int_as_float(obj);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(A.stats + rti::ST_REFINED, (unsigned long long)n);
+}
+
+// ====================================================== ordered compaction
+// After pass p: survivors of chunk c (alive mask cmask[c]) move to the
+// sorted list of pass p+1 at
+//   pad_base[set] + (survivors in chunks < c) + (rank in chunk) - (survivors in sets < set)
+// where pad_base[set] rounds every earlier set up to whole chunks.  Sorted
+// ids keep 64 consecutive survivors spatially close (same or adjacent
+// tiles), which keeps the per-wave culling windows tight.
+__global__ __launch_bounds__(1024) void k_chunk_scan(TraceArgs A, int pass) {
+    __shared__ int sh[1024];
+    const int nch = A.ctr[rti::CTR_PASS0 + pass * rti::CTR_PASS_WORDS + rti::CTR_NCH];
+    const int nblk = (nch + rti::SCAN_BLOCK - 1) / rti::SCAN_BLOCK;
+    for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+        int c = b * rti::SCAN_BLOCK + threadIdx.x;
+        int v = c < nch ? __popcll(A.cmask[c]) : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            int u = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += u;
+            __syncthreads();
+        }
+        if (c < nch) A.cscan[c] = sh[threadIdx.x] - v;
+        if (threadIdx.x == 1023) A.bscan[b] = sh[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_block_scan(TraceArgs A, int pass) {
+    __shared__ int sh[1024];
+    __shared__ int carry;
+    const int nch = A.ctr[rti::CTR_PASS0 + pass * rti::CTR_PASS_WORDS + rti::CTR_NCH];
+    const int nblk = (nch + rti::SCAN_BLOCK - 1) / rti::SCAN_BLOCK;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblk; base += 1024) {
+        int i = base + threadIdx.x;
+        int v = i < nblk ? A.bscan[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            int u = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += u;
+            __syncthreads();
+        }
+        if (i < nblk) A.bscan[i] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(TraceArgs A, int pass) {
+    const int lane = lane_id();
+    const int *pc = A.ctr + rti::CTR_PASS0 + pass * rti::CTR_PASS_WORDS;
+    const int nch = pc[rti::CTR_NCH];
+    // per-set survivor counts of this pass: unpadded and chunk-padded prefixes
+    int cnt = lane < A.n_sets ? pc[rti::CTR_SURV + lane] : 0;
+    int excl = wave_incl_scan(cnt) - cnt;
+    int pad = (cnt + 63) & ~63;
+    int pexcl = wave_incl_scan(pad) - pad;
+    const int *__restrict__ ids_in = A.ids[pass & 1];
+    int *__restrict__ ids_out = A.ids[(pass + 1) & 1];
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int c = wave; c < nch; c += nwaves) {
+        uint64_t m = A.cmask[c];
+        if (!m) continue;
+        bool alive = (m >> lane) & 1ull;
+        int id = alive ? (pass == 0 ? c * 64 + lane : ids_in[c * 64 + lane]) : 0;
+        int s = id / A.T;
+        int rank = A.bscan[c / rti::SCAN_BLOCK] + A.cscan[c] + mbcnt64(m);
+        int pos = __shfl(pexcl, s) + rank - __shfl(excl, s);
+        if (alive) ids_out[pos] = id;
+    }
 }
 
 __global__ void k_reset(int *ctr, int n_words, unsigned long long *stats) {
@@ -691,7 +688,20 @@ __global__ void k_reset(int *ctr, int n_words, unsigned long long *stats) {
 template <int KIND, int STEP>
 hipError_t launch_kind_step(const TraceArgs &a, const rti::DeviceData &d, int n_passes, int grid, int rgrid,
                             hipStream_t s, hipEvent_t *ev) {
+    const int scan_blocks = std::min((a.max_chunks + rti::SCAN_BLOCK - 1) / rti::SCAN_BLOCK, 1024);
+    const int scatter_blocks = std::max(1, std::min((a.max_chunks + 3) / 4, 4096));
+    {
+        int gblocks = (int)std::min<int64_t>((a.cap + 255) / 256, 8192);
+        hipLaunchKernelGGL((k_gen<KIND>), dim3(gblocks), dim3(256), 0, s, a, d.bump_f);
+    }
     for (int p = 0; p < n_passes; ++p) {
+        if (p > 0) {
+            // ordered compaction of the survivors of pass p-1 (not timed as a pass)
+            hipLaunchKernelGGL(k_chunk_scan, dim3(scan_blocks), dim3(1024), 0, s, a, p - 1);
+            hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(1024), 0, s, a, p - 1);
+            hipLaunchKernelGGL(k_scatter, dim3(scatter_blocks), dim3(256), 0, s, a, p - 1);
+            if (ev) (void)hipEventRecord(ev[2 * n_passes + 2 + p], s);
+        }
         if (a.count)
             hipLaunchKernelGGL((k_trace_pass<KIND, STEP, true>), dim3(grid), dim3(256), 0, s, a, p, d.bump_f, d.sph_f,
                                d.pln_f, d.tor_f);
@@ -700,11 +710,11 @@ hipError_t launch_kind_step(const TraceArgs &a, const rti::DeviceData &d, int n_
                                d.sph_f, d.pln_f, d.tor_f);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (ev) hipEventRecord(ev[2 + p], s);
+        if (ev) (void)hipEventRecord(ev[2 + p], s);
     }
     hipLaunchKernelGGL((k_refine<KIND, STEP>), dim3(rgrid), dim3(256), 0, s, a, d.bump_d, d.sph_d, d.pln_d, d.tor_d);
     hipError_t e = hipGetLastError();
-    if (ev) hipEventRecord(ev[2 + n_passes], s);
+    if (ev) (void)hipEventRecord(ev[2 + n_passes], s);
     return e;
 }
 
@@ -742,11 +752,11 @@ int trace_blocks_per_cu(int kind, int step) {
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid, int rgrid, hipStream_t s,
                         hipEvent_t *ev) {
     int words = CTR_PASS0 + n_passes * CTR_PASS_WORDS;
-    if (ev) hipEventRecord(ev[0], s);
+    if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_reset, dim3(64), dim3(256), 0, s, a.ctr, words, a.stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (ev) hipEventRecord(ev[1], s);
+    if (ev) (void)hipEventRecord(ev[1], s);
     const int step = a.step_kind;
     switch (a.kind) {
     case KIND_EUCLID: RT_DISPATCH(KIND_EUCLID, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev)

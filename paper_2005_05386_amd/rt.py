@@ -26,7 +26,8 @@ RK4, RK45, EULER = 0, 1, 2
 FLAG_TIMING, FLAG_COUNT_WORK = 1, 2
 
 EXPORTS = ["rt_abi_version", "rt_create", "rt_destroy", "rt_last_error", "rt_set_metric", "rt_set_scene",
-           "rt_trace", "rt_sync", "rt_get_stats"]
+           "rt_trace", "rt_sync", "rt_get_stats", "rt_tape_bytes", "rt_trace_fwd_ckpt", "rt_loss_l2",
+           "rt_trace_bwd"]
 
 
 class RtError(RuntimeError):
@@ -70,7 +71,7 @@ class rt_stats(C.Structure):
                 ("wave_iters", C.c_uint64), ("lane_iters", C.c_uint64), ("bump_list_sum", C.c_uint64),
                 ("obj_list_sum", C.c_uint64), ("refined", C.c_uint64), ("acc_evals", C.c_uint64),
                 ("bump_evals", C.c_uint64), ("obj_tests", C.c_uint64), ("passes", C.c_int), ("pass_ms", C.c_float),
-                ("refine_ms", C.c_float), ("total_ms", C.c_float)]
+                ("refine_ms", C.c_float), ("compact_ms", C.c_float), ("total_ms", C.c_float)]
 
 
 _P = C.c_void_p
@@ -91,6 +92,15 @@ _lib.rt_sync.argtypes = [_P, _P]
 _lib.rt_sync.restype = C.c_int
 _lib.rt_get_stats.argtypes = [_P, C.POINTER(rt_stats)]
 _lib.rt_get_stats.restype = C.c_int
+_lib.rt_tape_bytes.argtypes = [C.POINTER(rt_camera), C.c_int, C.c_int, C.c_int]
+_lib.rt_tape_bytes.restype = C.c_size_t
+_lib.rt_trace_fwd_ckpt.argtypes = [_P, C.POINTER(rt_camera), C.POINTER(rt_step_rule), C.c_int, C.c_int,
+                                   C.POINTER(rt_outputs), _P, C.c_size_t, _P]
+_lib.rt_trace_fwd_ckpt.restype = C.c_int
+_lib.rt_loss_l2.argtypes = [_P, C.POINTER(rt_camera), _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.rt_loss_l2.restype = C.c_int
+_lib.rt_trace_bwd.argtypes = [_P, _P, _P, _P, _P]
+_lib.rt_trace_bwd.restype = C.c_int
 
 
 def lib():
@@ -110,7 +120,7 @@ def camera_struct(cam):
 def rule_struct(r):
     return rt_step_rule(int(r["kind"]), float(r["h"]), float(r.get("rtol", 1e-6)), float(r.get("atol", 1e-6)),
                         float(r.get("h_min", 1e-6)), float(r.get("h_max", r["h"])), float(r["t_max"]),
-                        int(r.get("cull_every", 16)), int(r.get("pass_steps", 256)), int(r.get("bisect_iters", 40)),
+                        int(r.get("cull_every", 16)), int(r.get("pass_steps", 256)), int(r.get("bisect_iters", 32)),
                         int(r.get("flags", 0)))
 
 
@@ -204,6 +214,55 @@ class Tracer:
         self._check(_lib.rt_trace(self._h, C.byref(camera_struct(camera)), C.byref(rule_struct(rule)),
                                   int(max_steps), C.byref(o), C.c_void_p(stream_handle)))
 
+    # ---- differentiation (graph metric, RK4)
+    def tape_bytes(self, camera, max_steps, ckpt_every):
+        return int(_lib.rt_tape_bytes(C.byref(camera_struct(camera)), int(self.n_sets), int(max_steps),
+                                      int(ckpt_every)))
+
+    def trace_fwd_ckpt(self, camera, rule, max_steps, ckpt_every, out=None, tape=None):
+        """Trace with the adjoint tape; returns (outputs, tape tensor)."""
+        import torch
+        stream = torch.cuda.current_stream(self.device)
+        if out is None:
+            out = self.alloc_outputs(camera)
+        nbytes = self.tape_bytes(camera, max_steps, ckpt_every)
+        if tape is None or tape.numel() * tape.element_size() < nbytes:
+            tape = torch.empty(nbytes // 4 + 1, dtype=torch.float32, device=torch.device("cuda", self.device))
+        steps = out.get("steps")
+        o = rt_outputs(out["hit"].data_ptr(), out["t"].data_ptr(), out["id"].data_ptr(), out["dir"].data_ptr(),
+                       steps.data_ptr() if steps is not None else None)
+        self._check(_lib.rt_trace_fwd_ckpt(self._h, C.byref(camera_struct(camera)), C.byref(rule_struct(rule)),
+                                           int(max_steps), int(ckpt_every), C.byref(o), C.c_void_p(tape.data_ptr()),
+                                           C.c_size_t(tape.numel() * tape.element_size()),
+                                           C.c_void_p(stream.cuda_stream)))
+        return out, tape
+
+    def loss_l2(self, camera, hit, ids, target_hit, target_id, mask=None, want_grad=True):
+        """Masked L2 loss per set (device) and its gradient on the hit map."""
+        import torch
+        stream = torch.cuda.current_stream(self.device)
+        dev = hit.device
+        loss = torch.empty(self.n_sets, dtype=torch.float32, device=dev)
+        grad = torch.empty_like(hit) if want_grad else None
+        m = None
+        if mask is not None:
+            m = mask.to(device=dev, dtype=torch.uint8).contiguous()
+        self._check(_lib.rt_loss_l2(self._h, C.byref(camera_struct(camera)), C.c_void_p(hit.data_ptr()),
+                                    C.c_void_p(ids.data_ptr()), C.c_void_p(target_hit.data_ptr()),
+                                    C.c_void_p(target_id.data_ptr()), C.c_void_p(m.data_ptr() if m is not None else 0),
+                                    C.c_void_p(loss.data_ptr()), C.c_void_p(grad.data_ptr() if grad is not None else 0),
+                                    C.c_void_p(stream.cuda_stream)))
+        return loss, grad
+
+    def trace_bwd(self, tape, grad_hit, n_bumps):
+        import torch
+        stream = torch.cuda.current_stream(self.device)
+        g = torch.empty((self.n_sets, n_bumps, 5), dtype=torch.float32, device=grad_hit.device)
+        gh = grad_hit.contiguous()
+        self._check(_lib.rt_trace_bwd(self._h, C.c_void_p(tape.data_ptr()), C.c_void_p(gh.data_ptr()),
+                                      C.c_void_p(g.data_ptr()), C.c_void_p(stream.cuda_stream)))
+        return g
+
     def sync(self, stream=None):
         import torch
         if stream is None:
@@ -218,3 +277,33 @@ class Tracer:
 
 def to_numpy(out):
     return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+def make_trace_function():
+    """torch.autograd.Function: hit map of a graph-metric RK4 trace as a
+    differentiable function of the bump parameters.
+
+        hit, ids = TraceFn.apply(params, tracer, metric, camera, rule, ckpt_every)
+
+    params [n_sets, n_bumps, 5] (a, cx, cy, cz, sigma); hit [n_sets*H*W, 3].
+    The forward uploads params to the context (host copy), traces with the
+    adjoint tape; the backward runs the HIP adjoint on the incoming
+    gradient of hit (pixels that miss receive none)."""
+    import torch
+
+    class TraceFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, params, tracer, metric, camera, rule, ckpt_every):
+            m = dict(metric, bumps=params.detach().float().cpu().numpy())
+            tracer.set_metric(m)
+            out, tape = tracer.trace_fwd_ckpt(camera, rule, rule["max_steps"], ckpt_every)
+            ctx.tracer, ctx.tape, ctx.nb, ctx.pdev = tracer, tape, params.shape[1], params.device
+            ctx.mark_non_differentiable(out["id"])
+            return out["hit"], out["id"]
+
+        @staticmethod
+        def backward(ctx, grad_hit, grad_id):
+            g = ctx.tracer.trace_bwd(ctx.tape, grad_hit.float(), ctx.nb)
+            return g.to(ctx.pdev), None, None, None, None, None
+
+    return TraceFn

@@ -20,7 +20,7 @@ def _rt():
 
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "rt.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:rt_status|void|int|const char \*)\s*\*?\s*(rt_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:rt_status|void|int|size_t|const char \*)\s*\*?\s*(rt_\w+)\s*\(", src, re.M)))
 
 
 def test_every_declared_symbol_is_exported():
