@@ -84,6 +84,57 @@ def cpu_baseline(wl, budget_s):
                 done, cam["width"], cam["height"], dt)}
 
 
+def bench_adjoint(args, wl, torch, rt):
+    """One step = forward trace with the adjoint tape + masked L2 loss against
+    the target map + the adjoint, for every set and pixel."""
+    cam, rule = wl["camera"], dict(wl["rule"])
+    ck = wl["ckpt_every"]
+    tr = rt.Tracer(0)
+    tr.set_scene(wl["scene"])
+    tr.set_metric(dict(wl["metric"], bumps=wl["target_bumps"]))
+    target = tr.trace(cam, rule)
+    tr.set_metric(wl["metric"])
+    nb = wl["metric"]["bumps"].shape[1]
+    out, tape = tr.trace_fwd_ckpt(cam, rule, rule["max_steps"], ck)
+    print("[bench] adjoint workload %s: %d sets x %dx%d, tape %.2f GB" % (
+        args.workload, tr.n_sets, cam["width"], cam["height"], tape.numel() * 4 / 1e9), flush=True)
+
+    def step():
+        tr.trace_fwd_ckpt(cam, rule, rule["max_steps"], ck, out=out, tape=tape)
+        e1.record()
+        loss, gh = tr.loss_l2(cam, out["hit"], out["id"], target["hit"], target["id"])
+        g = tr.trace_bwd(tape, gh, nb)
+        return loss, g
+
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fwd_ms = tot_ms = 0.0
+    for _ in range(args.steps):
+        e0.record()
+        loss, g = step()
+        e2.record()
+        torch.cuda.synchronize()
+        fwd_ms += e0.elapsed_time(e1)
+        tot_ms += e0.elapsed_time(e2)
+    st = tr.stats()
+    n_rays = tr.n_sets * cam["width"] * cam["height"]
+    ms = tot_ms / args.steps
+    line = {
+        "metric": "differentiable trace: rays/s for forward + adjoint (64 sets x 512^2, 8 bumps)",
+        "value": n_rays / (ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"], "n_sets": tr.n_sets,
+                   "bumps": nb, "h": rule["h"], "max_steps": rule["max_steps"], "ckpt_every": ck},
+        "forward_ms": fwd_ms / args.steps, "backward_ms": (tot_ms - fwd_ms) / args.steps,
+        "tape_gb": tape.numel() * 4 / 1e9, "ray_steps_forward": st["ray_steps"],
+        "loss_mean": float(loss.mean()), "grad_abs_max": float(g.abs().max()),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +155,8 @@ def main():
     from paper_2005_05386_amd import rt
 
     wl = W.get(args.workload)
+    if "ckpt_every" in wl:
+        return bench_adjoint(args, wl, torch, rt)
     cam, rule = wl["camera"], dict(wl["rule"])
     tr = rt.Tracer(0)
     tr.set_metric(wl["metric"])

@@ -67,13 +67,12 @@ __device__ __forceinline__ bool step_rk4(F &acc, V3<T> p, V3<T> y, T h, V3<T> &d
     // Classical RK4 on (x, y): stage s evaluates k_s = a(P_s, Y_s) with
     // (P_0, Y_0) = (p, y) and (P_s, Y_s) = (p + c_s Y_{s-1}, y + c_s k_{s-1}),
     // c = (h/2, h/2, h); the stage sums with weights (1, 2, 2, 1) are
-    // accumulated as the stages are produced.  The stage loop is kept rolled
-    // so that the acceleration (the bump walk) is emitted once.
+    // accumulated as the stages are produced.
     const T hh = T(0.5) * h;
     V3<T> P = p, Y = y;
     V3<T> sx = mk(T(0), T(0), T(0)), sv = mk(T(0), T(0), T(0));
     bool ok = true;
-#pragma unroll 1
+#pragma unroll
     for (int st = 0; st < 4; ++st) {
         V3<T> k;
         if (st == 0 && k1)

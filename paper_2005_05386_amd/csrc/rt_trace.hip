@@ -98,8 +98,10 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
 }
 
 // ================================================================ the pass
+// Occupancy: 6 waves per SIMD (at most 80 VGPRs) measured fastest for the
+// RK4 graph and twist kernels although a few long-lived values spill.
 template <int KIND, int STEP, bool COUNT>
-__global__ __launch_bounds__(256) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
                                                     const float *__restrict__ TOR) {

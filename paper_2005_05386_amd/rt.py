@@ -138,9 +138,9 @@ class Tracer:
         self._keep = []
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.rt_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
