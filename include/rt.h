@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 1
+#define RT_ABI_VERSION 2
 
 typedef enum rt_status {
     RT_OK = 0,
@@ -184,6 +184,10 @@ typedef struct rt_step_rule {
  *   outputs, slower.  Used to compute algorithmic FLOP counts. */
 #define RT_FLAG_TIMING 1
 #define RT_FLAG_COUNT_WORK 2
+/* RT_FLAG_SURROGATE: use the networks given to rt_surrogate_load for the
+ *   support spheres of eligible bumps (graph metric, RT_STEP_RK4, one
+ *   parameter set; RT_EUNSUPPORTED otherwise, RT_ESTATE if none loaded). */
+#define RT_FLAG_SURROGATE 4
 
 /* ----------------------------------------------------------------- outputs
  * Caller-owned device arrays, indexed [set][row][column] (pixel index
@@ -232,6 +236,9 @@ typedef struct rt_stats {
     float refine_ms;        /* TIMING: duration of the FP64 refinement kernel */
     float compact_ms;       /* TIMING: summed duration of the survivor compaction between passes */
     float total_ms;         /* TIMING: reset + passes + refinement */
+    uint64_t crossings;     /* SURROGATE: rays parked on an eligible support sphere */
+    uint64_t accepted;      /* SURROGATE: crossings replaced by the network's prediction */
+    float surr_ms;          /* SURROGATE + TIMING: summed duration of the crossing stages */
 } rt_stats;
 
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
@@ -279,6 +286,95 @@ rt_status rt_loss_l2(rt_ctx *ctx, const rt_camera *camera, const float *hit, con
  * tape of the last rt_trace_fwd_ckpt on this context, with the metric
  * unchanged since (RT_ESTATE otherwise). */
 rt_status rt_trace_bwd(rt_ctx *ctx, const void *tape, const float *grad_hit, float *grad_params, void *hip_stream);
+
+/* ------------------------------------------------------------- surrogate
+ * Learned crossing map of one bump's support sphere: an MLP
+ * 6 -> 256 -> 256 -> 256 -> 6 with SiLU hidden activations, run on the BF16
+ * matrix cores with FP32 accumulation.  Parameters of one network, in this
+ * order (RT_MLP_PARAMS floats): W1[256][6], b1[256], W2[256][256], b2[256],
+ * W3[256][256], b3[256], W4[6][256], b4[6]  (h = silu(W x + b)).
+ * Weights are used from a bf16 copy (uint16 bit patterns, same layout),
+ * biases from the FP32 master.  Several networks (n_nets) are processed in
+ * one launch, each on its own batch rows: x [n_nets][batch][6]. */
+#define RT_MLP_PARAMS 134918
+
+/* Bytes of device workspace for rt_mlp_fwd/rt_mlp_bwd at this size. */
+size_t rt_mlp_work_bytes(int n_nets, int batch);
+
+/* y = MLP(x) per network; the workspace keeps the activations for a
+ * following rt_mlp_bwd with the same sizes and workspace. */
+rt_status rt_mlp_fwd(rt_ctx *ctx, int n_nets, int batch, const uint16_t *w_bf16, const float *params,
+                     const float *x, float *y, void *work, size_t work_bytes, void *hip_stream);
+
+/* Inference forward for rows grouped by network (the kernel the tracer
+ * runs on its crossings): network g maps rows [off_g, off_g + rows[g]) of
+ * x [sum rows][6] to y [sum rows][6], off_g = rows[0] + ... + rows[g-1].
+ * rows is a host array [n_nets], n_nets <= 64; same rounding points as
+ * rt_mlp_fwd. */
+rt_status rt_mlp_fwd_grouped(rt_ctx *ctx, int n_nets, const int32_t *rows, const uint16_t *w_bf16,
+                             const float *params, const float *x, float *y, void *hip_stream);
+
+/* grad [n_nets][RT_MLP_PARAMS] = d/dparams of sum_rows dy . y, for the
+ * activations stored in work by the last rt_mlp_fwd.  Bias gradients are
+ * reduced in a fixed order. */
+rt_status rt_mlp_bwd(rt_ctx *ctx, int n_nets, int batch, const uint16_t *w_bf16, const float *dy, float *grad,
+                     void *work, size_t work_bytes, void *hip_stream);
+
+/* Mean-squared-error gradient for training: dy = 2 (y - t) / batch over n
+ * values (device arrays), and 64 partial sums of (y - t)^2 written to
+ * sq_partial[64] (their sum / batch is the loss); fixed summation order. */
+rt_status rt_mse_grad(rt_ctx *ctx, const float *y, const float *t, float *dy, size_t n, int batch, float *sq_partial,
+                      void *hip_stream);
+
+/* AdamW with bias correction (step >= 1) on n FP32 parameters; refreshes
+ * the bf16 copy. */
+rt_status rt_adamw_step(rt_ctx *ctx, float *params, uint16_t *w_bf16, float *m, float *v, const float *grad, size_t n,
+                        float lr, float beta1, float beta2, float eps, float weight_decay, int step, void *hip_stream);
+
+/* Training data for the surrogate networks (one per bump shape kappa =
+ * a / sigma; the metric depends on |kappa| only): n_per_shape single-bump
+ * geodesics per shape, integrated with RK4 (step h in units of sigma, the
+ * graph-metric acceleration of Eq. 5.4) from the support sphere of radius
+ * 3 sigma to the exit, which is refined by bisection.  In the canonical
+ * frame the entry point is (3, 0, 0) and the direction (-cos th, sin th, 0).
+ * grid = 0: sin^2 th uniform in [0, 1) from a counter-based generator of
+ * (seed, shape, sample), i.e. entry points uniform over the disc of impact
+ * parameters; grid = 1: cos th = i / (n_per_shape - 1).  kappa and scale
+ * are host arrays [n_shapes]; outputs are device arrays:
+ *   x   [n_shapes][n_per_shape][6]  network input (1, 0, 0, -cos th, sin th, 0)
+ *   y   [n_shapes][n_per_shape][6]  target: (exit point / 3 - (-cos 2th, sin 2th, 0),
+ *                                   unit exit direction - input direction) / scale[shape]
+ *   aux [n_shapes][n_per_shape][4]  impact parameter 3 sin th, arc length inside
+ *                                   the sphere (units of sigma; -1 if the
+ *                                   ray did not exit), exit / 3 (x, y) */
+rt_status rt_surrogate_gen(rt_ctx *ctx, int n_shapes, const float *kappa, const float *scale, int n_per_shape,
+                           float h, int grid, uint64_t seed, float *x, float *y, float *aux, void *hip_stream);
+
+/* Calibration of the surrogate's error bounds: for predictions `pred` and
+ * targets `target` (scaled residuals as produced by rt_surrogate_gen, both
+ * [n_shapes][n_per_shape][6], inputs x as produced there), the maximum over
+ * samples of the decoded exit-point error and unit-direction error, per bin
+ * of cos th (n_bins equal bins of [0, 1]), written to err
+ * [n_shapes][n_bins][2] (device).  scale is a host array [n_shapes]. */
+rt_status rt_surrogate_calibrate(rt_ctx *ctx, int n_shapes, int n_per_shape, const float *x, const float *pred,
+                                 const float *target, const float *scale, int n_bins, float *err, void *hip_stream);
+
+/* Hand trained networks to the tracer (used by traces with
+ * RT_FLAG_SURROGATE).  The context copies everything:
+ *   w_bf16 [n_nets][RT_MLP_PARAMS], params [n_nets][RT_MLP_PARAMS] (device)
+ *   scale  [n_nets] (host)  target scale of each network
+ *   arc    [n_nets][n_tab] (device)  arc length through the sphere in units
+ *          of sigma at cos th = i / (n_tab - 1), n_tab >= 2
+ *   err    [n_nets][n_bins][2] (device)  calibrated error bounds
+ *   net_of_bump [n_bumps] (host)  network of every bump of the current
+ *          metric, -1 for none; checked against the metric at trace time
+ *   tol    probe tolerance on the estimated hit error (scene units).
+ * A bump is eligible when its support sphere (radius 3 sigma) meets no
+ * object and no other bump's cut sphere; eligibility is recomputed when the
+ * metric or scene changes.  n_nets = 0 unloads.  At most 64 networks. */
+rt_status rt_surrogate_load(rt_ctx *ctx, int n_nets, const uint16_t *w_bf16, const float *params, const float *scale,
+                            const float *arc, int n_tab, const float *err, int n_bins, const int32_t *net_of_bump,
+                            int n_bumps, float tol);
 
 #ifdef __cplusplus
 }

@@ -51,6 +51,7 @@ struct rt_ctx {
     bool traced = false;
     int last_passes = 0;
     bool last_timed = false;
+    bool last_surr = false;
     std::vector<hipEvent_t> ev;  // timing events of the last trace
     // differentiation
     bool adj_valid = false;
@@ -58,6 +59,26 @@ struct rt_ctx {
     rti::TraceArgs adj_args{};
     float *d_adj_scr = nullptr, *d_adj_part = nullptr, *d_loss_blk = nullptr;
     int64_t adj_scr_cap = 0, adj_part_cap = 0, loss_cap = 0;
+    // surrogate
+    void *d_gen_ks = nullptr;
+    size_t gen_ks_bytes = 0;
+    int surr_nets = 0, surr_tab = 0, surr_bins = 0;
+    float surr_tol = 1e-3f;
+    std::vector<float> surr_scale;
+    std::vector<int> surr_net_of_bump;
+    void *d_surr = nullptr;            // networks and tables (context copy)
+    size_t surr_bytes = 0;
+    rti::SurrArgs surr{};
+    void *d_surr_sb = nullptr;         // per-bump eligibility records
+    size_t surr_sb_bytes = 0;
+    bool surr_sb_dirty = true;
+    int surr_eligible = 0;
+    void *d_grp_ctl = nullptr;         // control block of rt_mlp_fwd_grouped
+    size_t grp_ctl_bytes = 0;
+    void *d_grp_w = nullptr;           // its aligned copy of the networks
+    size_t grp_w_bytes = 0;
+    void *d_xbuf = nullptr;            // crossing queues, sized for xbuf_cap rays
+    int64_t xbuf_cap = 0;
 };
 
 static rt_status fail(rt_ctx *c, rt_status s, const std::string &msg) {
@@ -142,6 +163,12 @@ void rt_destroy(rt_ctx *c) {
         hipFree(c->d_adj_scr);
         hipFree(c->d_adj_part);
         hipFree(c->d_loss_blk);
+        hipFree(c->d_gen_ks);
+        hipFree(c->d_surr);
+        hipFree(c->d_surr_sb);
+        hipFree(c->d_xbuf);
+        hipFree(c->d_grp_ctl);
+        hipFree(c->d_grp_w);
         for (hipEvent_t e : c->ev) hipEventDestroy(e);
     }
     delete c;
@@ -238,6 +265,7 @@ rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
     c->cull = m->cull_sigmas;
     c->bumps.assign(m->bumps, m->bumps + n);
     c->has_metric = true;
+    c->surr_sb_dirty = true;
     c->adj_valid = false;
     c->err.clear();
     return RT_OK;
@@ -315,6 +343,7 @@ rt_status rt_set_scene(rt_ctx *c, const rt_scene *s) {
     c->pln.assign(s->planes, s->planes + s->n_planes);
     c->tor.assign(s->tori, s->tori + s->n_tori);
     c->has_scene = true;
+    c->surr_sb_dirty = true;
     c->err.clear();
     return RT_OK;
 }
@@ -344,7 +373,8 @@ static void free_workspace(rt_ctx *c) {
 static rt_status ensure_workspace(rt_ctx *c, int64_t cap) {
     hipError_t e;
     if (!c->d_ctr) {
-        e = hipMalloc((void **)&c->d_ctr, sizeof(int) * (rti::CTR_PASS0 + rti::MAX_PASSES_API * rti::CTR_PASS_WORDS));
+        e = hipMalloc((void **)&c->d_ctr, sizeof(int) * (rti::CTR_PASS0 + rti::MAX_PASSES_API * rti::CTR_PASS_WORDS +
+                                                         rti::CTR_SURR_WORDS));
         if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (counters)");
     }
     if (c->ws_cap >= cap) return RT_OK;
@@ -364,6 +394,75 @@ static rt_status ensure_workspace(rt_ctx *c, int64_t cap) {
         return hip_fail(c, e, "hipMalloc (workspace)");
     }
     c->ws_cap = cap;
+    return RT_OK;
+}
+
+// Eligibility of every bump for the learned crossing (one parameter set):
+// its support sphere S (centre c, radius R = 3 sigma) must meet no object and
+// lie outside every other bump's cut sphere, so that inside S the culled
+// metric is exactly that of the bump alone.  Uploads two float4 per bump:
+// (c, R^2), (sigma, network or -1, R, 0).
+static rt_status surr_prepare(rt_ctx *c) {
+    if (!c->surr_sb_dirty) return RT_OK;
+    const int nb = c->n_bumps;
+    std::vector<float> sb(std::max(nb, 1) * 8, 0.f);
+    int n_el = 0;
+    for (int b = 0; b < nb; ++b) {
+        const rt_bump &B = c->bumps[b];
+        const double R = 3.0 * (double)B.sigma;
+        int net = c->surr_net_of_bump[b];
+        auto dist = [&](double x, double y, double z) {
+            return std::sqrt((B.cx - x) * (B.cx - x) + (B.cy - y) * (B.cy - y) + (B.cz - z) * (B.cz - z));
+        };
+        if (!(B.a != 0.f)) net = -1;
+        for (int j = 0; j < nb && net >= 0; ++j) {
+            if (j == b) continue;
+            const rt_bump &O = c->bumps[j];
+            if (dist(O.cx, O.cy, O.cz) < R + (double)c->cull * O.sigma) net = -1;
+        }
+        for (const rt_sphere &o : c->sph)
+            if (net >= 0 && dist(o.cx, o.cy, o.cz) < R + o.r) net = -1;
+        for (const rt_plane &o : c->pln)
+            if (net >= 0 && std::fabs(o.nx * B.cx + o.ny * B.cy + o.nz * B.cz - o.d) < R) net = -1;
+        for (const rt_torus &o : c->tor) {
+            if (net < 0) break;
+            // exact distance from the centre to the torus surface
+            double px = B.cx - o.cx, py = B.cy - o.cy, pz = B.cz - o.cz;
+            double along = px * o.ax + py * o.ay + pz * o.az;
+            double qx = px - along * o.ax, qy = py - along * o.ay, qz = pz - along * o.az;
+            double rad = std::sqrt(qx * qx + qy * qy + qz * qz) - o.R;
+            if (std::sqrt(rad * rad + along * along) - o.r < R) net = -1;
+        }
+        if (net >= 0) n_el++;
+        sb[8 * b + 0] = B.cx;
+        sb[8 * b + 1] = B.cy;
+        sb[8 * b + 2] = B.cz;
+        sb[8 * b + 3] = (float)(R * R);
+        sb[8 * b + 4] = B.sigma;
+        int32_t nv = net;
+        std::memcpy(&sb[8 * b + 5], &nv, 4);
+        sb[8 * b + 6] = (float)R;
+        sb[8 * b + 7] = 0.f;
+    }
+    rt_status st = upload(c, &c->d_surr_sb, &c->surr_sb_bytes, sb.data(), sb.size() * sizeof(float));
+    if (st != RT_OK) return st;
+    c->surr_eligible = n_el;
+    c->surr_sb_dirty = false;
+    return RT_OK;
+}
+
+// Crossing queue (int4), slots (int2), network inputs and outputs (6 floats
+// each) for `cap` rays; grow-only.
+static rt_status ensure_xbuf(rt_ctx *c, int64_t cap) {
+    if (c->xbuf_cap >= cap) return RT_OK;
+    rt_status st = sync_last(c);
+    if (st != RT_OK) return st;
+    hipFree(c->d_xbuf);
+    c->d_xbuf = nullptr;
+    c->xbuf_cap = 0;
+    hipError_t e = hipMalloc(&c->d_xbuf, (size_t)cap * (16 + 8 + 24 + 24) + 1024);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (crossing queues)");
+    c->xbuf_cap = cap;
     return RT_OK;
 }
 
@@ -406,9 +505,21 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     if (r->cull_every < 1 || r->cull_every > 256) return fail(c, RT_EINVAL, "rt_trace: cull_every must be in 1..256");
     if (r->pass_steps < 16) return fail(c, RT_EINVAL, "rt_trace: pass_steps must be >= 16");
     if (r->bisect_iters < 0 || r->bisect_iters > 60) return fail(c, RT_EINVAL, "rt_trace: bisect_iters must be in 0..60");
-    if (r->flags & ~(RT_FLAG_TIMING | RT_FLAG_COUNT_WORK)) return fail(c, RT_EINVAL, "rt_trace: unknown flag bits");
+    if (r->flags & ~(RT_FLAG_TIMING | RT_FLAG_COUNT_WORK | RT_FLAG_SURROGATE))
+        return fail(c, RT_EINVAL, "rt_trace: unknown flag bits");
     if (max_steps < 1 || max_steps > 1000000) return fail(c, RT_EINVAL, "rt_trace: max_steps must be in 1..1000000");
+    const bool surr = (r->flags & RT_FLAG_SURROGATE) != 0;
+    if (surr) {
+        if (c->kind != RT_METRIC_GRAPH_GAUSS || r->kind != RT_STEP_RK4 || c->n_sets != 1 || tape)
+            return fail(c, RT_EUNSUPPORTED, "rt_trace: the surrogate needs the graph metric, RK4, one parameter set "
+                                            "and no tape");
+        if (c->surr_nets < 1) return fail(c, RT_ESTATE, "rt_trace: no surrogate networks loaded");
+        if ((int)c->surr_net_of_bump.size() != c->n_bumps)
+            return fail(c, RT_ESTATE, "rt_trace: surrogate net_of_bump does not match the metric's bump count");
+    }
     int n_passes = (max_steps + r->pass_steps - 1) / r->pass_steps;
+    // each learned crossing ends a ray's pass early: allow extra passes
+    if (surr) n_passes = std::min(n_passes + 1 + std::max(16, 2 * c->n_bumps), rti::MAX_PASSES_API);
     if (n_passes > rti::MAX_PASSES_API)
         return fail(c, RT_EINVAL, "rt_trace: max_steps / pass_steps must be <= " + std::to_string(rti::MAX_PASSES_API));
     if (!o->hit || !o->t || !o->id || !o->dir) return fail(c, RT_EINVAL, "rt_trace: NULL output pointer");
@@ -497,6 +608,21 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
         a.tape_hit = (float *)tape + (size_t)cap * a.n_ckpt * 9;
     }
 
+    a.surr = surr ? 1 : 0;
+    a.n_passes = n_passes;
+    a.xctl = c->d_ctr + rti::CTR_PASS0 + n_passes * rti::CTR_PASS_WORDS;
+    rti::SurrArgs S = c->surr;
+    if (surr) {
+        if ((st = surr_prepare(c)) != RT_OK) return st;
+        if ((st = ensure_xbuf(c, cap)) != RT_OK) return st;
+        char *xb = (char *)c->d_xbuf;
+        a.surr_sb = (const float4 *)c->d_surr_sb;
+        a.xq = (int4 *)xb;
+        S.sorted = (int2 *)(xb + (size_t)cap * 16);
+        S.xin = (float *)(xb + (size_t)cap * 24);
+        S.xout = (float *)(xb + (size_t)cap * 48);
+    }
+
     int bpc = rti::trace_blocks_per_cu(a.kind, a.step_kind);
     int64_t chunks = cap / 64 + 1;
     int64_t grid = (int64_t)c->n_cu * bpc;
@@ -511,18 +637,20 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     hipStream_t s = (hipStream_t)stream;
     bool timed = (r->flags & RT_FLAG_TIMING) != 0;
     if (timed) {
-        while ((int)c->ev.size() < 3 * n_passes + 3) {
+        while ((int)c->ev.size() < 4 * n_passes + 3) {
             hipEvent_t ev;
             if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(c, e, "hipEventCreate");
             c->ev.push_back(ev);
         }
     }
-    e = rti::launch_trace(a, c->dd, n_passes, (int)grid, rgrid, s, timed ? c->ev.data() : nullptr);
+    e = rti::launch_trace(a, c->dd, n_passes, (int)grid, rgrid, s, timed ? c->ev.data() : nullptr,
+                          surr ? &S : nullptr, 2 * c->n_cu);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     c->last_stream = s;
     c->traced = true;
     c->last_passes = n_passes;
     c->last_timed = timed;
+    c->last_surr = surr;
     if (tape) {
         c->adj_args = a;
         c->adj_tape = tape;
@@ -622,6 +750,252 @@ rt_status rt_trace_bwd(rt_ctx *c, const void *tape, const float *grad_hit, float
     return RT_OK;
 }
 
+size_t rt_mlp_work_bytes(int n_nets, int batch) {
+    if (n_nets < 1 || batch < 1) return 0;
+    return rti::mlp_work_bytes(n_nets, batch);
+}
+
+static rt_status mlp_check(rt_ctx *c, int n_nets, int batch, const void *w, void *work, size_t work_bytes,
+                           const char *who) {
+    if (!c) return RT_EINVAL;
+    if (n_nets < 1 || n_nets > 4096 || batch < 1 || (int64_t)n_nets * batch > (1LL << 28))
+        return fail(c, RT_EINVAL, std::string(who) + ": bad n_nets or batch");
+    if (!w || !work) return fail(c, RT_EINVAL, std::string(who) + ": NULL argument");
+    if (work_bytes < rti::mlp_work_bytes(n_nets, batch))
+        return fail(c, RT_EINVAL, std::string(who) + ": workspace too small");
+    if (c->host_only) return fail(c, RT_ESTATE, std::string(who) + ": host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    return RT_OK;
+}
+
+rt_status rt_mlp_fwd(rt_ctx *c, int n_nets, int batch, const uint16_t *w_bf16, const float *params, const float *x,
+                     float *y, void *work, size_t work_bytes, void *stream) {
+    rt_status st = mlp_check(c, n_nets, batch, w_bf16, work, work_bytes, "rt_mlp_fwd");
+    if (st != RT_OK) return st;
+    if (!params || !x || !y) return fail(c, RT_EINVAL, "rt_mlp_fwd: NULL argument");
+    rti::MlpWork w;
+    rti::mlp_work_carve(work, n_nets, batch, w);
+    hipError_t e = rti::mlp_forward(n_nets, batch, (const __bf16 *)w_bf16, params, x, y, w, true, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (mlp forward)");
+    return RT_OK;
+}
+
+rt_status rt_mlp_fwd_grouped(rt_ctx *c, int n_nets, const int32_t *rows, const uint16_t *w_bf16,
+                             const float *params, const float *x, float *y, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (n_nets < 1 || n_nets > rti::MAX_NETS) return fail(c, RT_EINVAL, "rt_mlp_fwd_grouped: n_nets must be in 1..64");
+    if (!rows || !w_bf16 || !params || !x || !y) return fail(c, RT_EINVAL, "rt_mlp_fwd_grouped: NULL argument");
+    std::vector<int> ctl(rti::CTR_SURR_WORDS, 0);
+    int64_t tot = 0, tiles = 0;
+    for (int g = 0; g < n_nets; ++g) {
+        if (rows[g] < 0) return fail(c, RT_EINVAL, "rt_mlp_fwd_grouped: negative row count");
+        ctl[rti::XC_ROW + g] = (int)tot;
+        ctl[rti::XC_TILE + g] = (int)tiles;
+        tot += rows[g];
+        tiles += (rows[g] + 63) / 64;
+        if (tot > (1LL << 30)) return fail(c, RT_EINVAL, "rt_mlp_fwd_grouped: too many rows");
+    }
+    for (int g = n_nets; g <= 64; ++g) {
+        ctl[rti::XC_ROW + g] = (int)tot;
+        ctl[rti::XC_TILE + g] = (int)tiles;
+    }
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_mlp_fwd_grouped: host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    rt_status st = sync_last(c);
+    if (st != RT_OK) return st;
+    if ((st = upload(c, &c->d_grp_ctl, &c->grp_ctl_bytes, ctl.data(), ctl.size() * sizeof(int))) != RT_OK) return st;
+    if (tiles == 0) return RT_OK;
+    // the kernel reads weight rows with 128-bit loads: copy them to 16-byte
+    // aligned rows of MLP_P_PAD values
+    const size_t P = RT_MLP_PARAMS, PP = rti::MLP_P_PAD;
+    const size_t need = (size_t)n_nets * PP * 6;
+    if (c->grp_w_bytes < need) {
+        hipFree(c->d_grp_w);
+        c->d_grp_w = nullptr;
+        c->grp_w_bytes = 0;
+        if ((e = hipMalloc(&c->d_grp_w, need)) != hipSuccess) return hip_fail(c, e, "hipMalloc (grouped mlp)");
+        c->grp_w_bytes = need;
+    }
+    char *gw = (char *)c->d_grp_w;
+    hipStream_t hs = (hipStream_t)stream;
+    if ((e = hipMemcpy2DAsync(gw, PP * 2, w_bf16, P * 2, P * 2, n_nets, hipMemcpyDeviceToDevice, hs)) != hipSuccess ||
+        (e = hipMemcpy2DAsync(gw + (size_t)n_nets * PP * 2, PP * 4, params, P * 4, P * 4, n_nets,
+                              hipMemcpyDeviceToDevice, hs)) != hipSuccess)
+        return hip_fail(c, e, "hipMemcpy2DAsync (grouped mlp)");
+    rti::SurrArgs S{};
+    S.n_nets = n_nets;
+    S.stride = (int64_t)PP;
+    S.wb = (const __bf16 *)gw;
+    S.params = (const float *)(gw + (size_t)n_nets * PP * 2);
+    S.xin = (float *)x;
+    S.xout = y;
+    int blocks = (int)std::min<int64_t>(tiles, 2 * (int64_t)c->n_cu);
+    e = rti::launch_mlp_grouped((const int *)c->d_grp_ctl, S, blocks, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (grouped mlp)");
+    c->last_stream = (hipStream_t)stream;
+    c->traced = true;
+    return RT_OK;
+}
+
+rt_status rt_mlp_bwd(rt_ctx *c, int n_nets, int batch, const uint16_t *w_bf16, const float *dy, float *grad,
+                     void *work, size_t work_bytes, void *stream) {
+    rt_status st = mlp_check(c, n_nets, batch, w_bf16, work, work_bytes, "rt_mlp_bwd");
+    if (st != RT_OK) return st;
+    if (!dy || !grad) return fail(c, RT_EINVAL, "rt_mlp_bwd: NULL argument");
+    rti::MlpWork w;
+    rti::mlp_work_carve(work, n_nets, batch, w);
+    hipError_t e = rti::mlp_backward(n_nets, batch, (const __bf16 *)w_bf16, dy, grad, w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (mlp backward)");
+    return RT_OK;
+}
+
+rt_status rt_mse_grad(rt_ctx *c, const float *y, const float *t, float *dy, size_t n, int batch, float *part,
+                      void *stream) {
+    if (!c) return RT_EINVAL;
+    if (!y || !t || !dy || !part || batch < 1) return fail(c, RT_EINVAL, "rt_mse_grad: bad argument");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_mse_grad: host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    e = rti::launch_mse_grad(y, t, dy, (int64_t)n, batch, part, 64, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (mse)");
+    return RT_OK;
+}
+
+rt_status rt_adamw_step(rt_ctx *c, float *params, uint16_t *w_bf16, float *m, float *v, const float *grad, size_t n,
+                        float lr, float beta1, float beta2, float eps, float wd, int step, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (!params || !w_bf16 || !m || !v || !grad) return fail(c, RT_EINVAL, "rt_adamw_step: NULL argument");
+    if (step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) ||
+        !finite(lr) || !finite(wd))
+        return fail(c, RT_EINVAL, "rt_adamw_step: bad hyper-parameters");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_adamw_step: host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    e = rti::launch_adamw(params, (__bf16 *)w_bf16, m, v, grad, (int64_t)n, lr, beta1, beta2, eps, wd, step,
+                          (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (adamw)");
+    return RT_OK;
+}
+
+rt_status rt_surrogate_gen(rt_ctx *c, int n_shapes, const float *kappa, const float *scale, int n_per, float h,
+                           int grid, uint64_t seed, float *x, float *y, float *aux, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (n_shapes < 1 || n_shapes > 4096 || n_per < 1 || (int64_t)n_shapes * n_per > (1LL << 31) - 1)
+        return fail(c, RT_EINVAL, "rt_surrogate_gen: bad sizes");
+    if (!kappa || !scale || !x || !y || !aux) return fail(c, RT_EINVAL, "rt_surrogate_gen: NULL argument");
+    if (!(h >= 1e-3f && h <= 0.5f) || (grid != 0 && grid != 1))
+        return fail(c, RT_EINVAL, "rt_surrogate_gen: need 1e-3 <= h <= 0.5 and grid in {0, 1}");
+    for (int i = 0; i < n_shapes; ++i)
+        if (!finite(kappa[i]) || std::fabs(kappa[i]) > 100.f || !(scale[i] > 0.f) || !finite(scale[i]))
+            return fail(c, RT_EINVAL, "rt_surrogate_gen: bad kappa or scale");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_surrogate_gen: host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    std::vector<float> ks(2 * (size_t)n_shapes);
+    for (int i = 0; i < n_shapes; ++i) {
+        ks[i] = kappa[i];
+        ks[n_shapes + i] = scale[i];
+    }
+    rt_status st = upload(c, &c->d_gen_ks, &c->gen_ks_bytes, ks.data(), ks.size() * sizeof(float));
+    if (st != RT_OK) return st;
+    const float *dk = (const float *)c->d_gen_ks;
+    e = rti::launch_cross_gen(dk, dk + n_shapes, n_shapes, n_per, h, grid, seed, x, y, aux, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (surrogate data)");
+    c->last_stream = (hipStream_t)stream;
+    c->traced = true;
+    return RT_OK;
+}
+
+rt_status rt_surrogate_calibrate(rt_ctx *c, int n_shapes, int n_per, const float *x, const float *pred,
+                                 const float *target, const float *scale, int n_bins, float *err, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (n_shapes < 1 || n_shapes > 4096 || n_per < 1 || (int64_t)n_shapes * n_per > (1LL << 31) - 1 || n_bins < 1 ||
+        n_bins > 4096)
+        return fail(c, RT_EINVAL, "rt_surrogate_calibrate: bad sizes");
+    if (!x || !pred || !target || !scale || !err) return fail(c, RT_EINVAL, "rt_surrogate_calibrate: NULL argument");
+    for (int i = 0; i < n_shapes; ++i)
+        if (!(scale[i] > 0.f) || !finite(scale[i])) return fail(c, RT_EINVAL, "rt_surrogate_calibrate: bad scale");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_surrogate_calibrate: host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    rt_status st = upload(c, &c->d_gen_ks, &c->gen_ks_bytes, scale, (size_t)n_shapes * sizeof(float));
+    if (st != RT_OK) return st;
+    e = rti::launch_cross_cal(x, pred, target, (const float *)c->d_gen_ks, n_shapes, n_per, n_bins, err,
+                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch (surrogate calibration)");
+    c->last_stream = (hipStream_t)stream;
+    c->traced = true;
+    return RT_OK;
+}
+
+rt_status rt_surrogate_load(rt_ctx *c, int n_nets, const uint16_t *w_bf16, const float *params, const float *scale,
+                            const float *arc, int n_tab, const float *err, int n_bins, const int32_t *net_of_bump,
+                            int n_bumps, float tol) {
+    if (!c) return RT_EINVAL;
+    if (n_nets == 0) {
+        c->surr_nets = 0;
+        c->err.clear();
+        return RT_OK;
+    }
+    if (n_nets < 0 || n_nets > rti::MAX_NETS) return fail(c, RT_EINVAL, "rt_surrogate_load: n_nets must be in 0..64");
+    if (!w_bf16 || !params || !scale || !arc || !err || (n_bumps > 0 && !net_of_bump))
+        return fail(c, RT_EINVAL, "rt_surrogate_load: NULL argument");
+    if (n_tab < 2 || n_tab > 1 << 20 || n_bins < 1 || n_bins > 4096 || n_bumps < 0 || n_bumps > MAX_BUMPS)
+        return fail(c, RT_EINVAL, "rt_surrogate_load: bad table sizes or bump count");
+    if (!(tol > 0.f) || !finite(tol)) return fail(c, RT_EINVAL, "rt_surrogate_load: tol must be finite and > 0");
+    for (int i = 0; i < n_nets; ++i)
+        if (!(scale[i] > 0.f) || !finite(scale[i])) return fail(c, RT_EINVAL, "rt_surrogate_load: bad scale");
+    for (int b = 0; b < n_bumps; ++b)
+        if (net_of_bump[b] < -1 || net_of_bump[b] >= n_nets)
+            return fail(c, RT_EINVAL, "rt_surrogate_load: net_of_bump out of range");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_surrogate_load: host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    rt_status st = sync_last(c);
+    if (st != RT_OK) return st;
+    const size_t P = RT_MLP_PARAMS, PP = rti::MLP_P_PAD;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_w = 0, o_p = al(n_nets * PP * 2), o_s = o_p + al(n_nets * PP * 4), o_a = o_s + al(n_nets * 4),
+                 o_e = o_a + al((size_t)n_nets * n_tab * 4), total = o_e + al((size_t)n_nets * n_bins * 8);
+    if (c->surr_bytes < total) {
+        hipFree(c->d_surr);
+        c->d_surr = nullptr;
+        c->surr_bytes = 0;
+        if ((e = hipMalloc(&c->d_surr, total)) != hipSuccess) return hip_fail(c, e, "hipMalloc (surrogate)");
+        c->surr_bytes = total;
+    }
+    char *d = (char *)c->d_surr;
+    if ((e = hipMemcpy2D(d + o_w, PP * 2, w_bf16, P * 2, P * 2, n_nets, hipMemcpyDeviceToDevice)) != hipSuccess ||
+        (e = hipMemcpy2D(d + o_p, PP * 4, params, P * 4, P * 4, n_nets, hipMemcpyDeviceToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d + o_s, scale, n_nets * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d + o_a, arc, (size_t)n_nets * n_tab * 4, hipMemcpyDeviceToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d + o_e, err, (size_t)n_nets * n_bins * 8, hipMemcpyDeviceToDevice)) != hipSuccess)
+        return hip_fail(c, e, "hipMemcpy (surrogate)");
+    rti::SurrArgs S{};
+    S.n_nets = n_nets;
+    S.stride = (int64_t)PP;
+    S.n_tab = n_tab;
+    S.n_bins = n_bins;
+    S.tol = tol;
+    S.wb = (const __bf16 *)(d + o_w);
+    S.params = (const float *)(d + o_p);
+    S.scale = (const float *)(d + o_s);
+    S.arc = (const float *)(d + o_a);
+    S.err = (const float *)(d + o_e);
+    c->surr = S;
+    c->surr_nets = n_nets;
+    c->surr_tab = n_tab;
+    c->surr_bins = n_bins;
+    c->surr_tol = tol;
+    c->surr_scale.assign(scale, scale + n_nets);
+    c->surr_net_of_bump.assign(net_of_bump, net_of_bump + n_bumps);
+    c->surr_sb_dirty = true;
+    c->err.clear();
+    return RT_OK;
+}
+
 rt_status rt_sync(rt_ctx *c, void *stream) {
     if (!c) return RT_EINVAL;
     if (c->host_only) return RT_OK;
@@ -651,23 +1025,34 @@ rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
     out->bump_evals = v[rti::ST_BUMP_EVALS];
     out->obj_tests = v[rti::ST_OBJ_TESTS];
     out->passes = c->last_passes;
+    out->crossings = v[rti::ST_XING];
+    out->accepted = v[rti::ST_XACC];
     if (c->last_timed) {
         // events: 0 before reset, 1 after reset, 2+p after pass p, 2+np after
-        // refine, 2np+2+p after the compaction that precedes pass p (p >= 1)
-        float ms = 0.f, pass = 0.f, comp = 0.f;
+        // refine, 2np+2+p after the compaction that precedes pass p (p >= 1),
+        // 3np+3+p after the crossing stage that follows pass p
+        float ms = 0.f, pass = 0.f, comp = 0.f, xs = 0.f;
         int np = c->last_passes;
         for (int p = 0; p < np; ++p) {
             hipEvent_t start = p == 0 ? c->ev[1] : c->ev[2 * np + 2 + p];
             if ((e = hipEventElapsedTime(&ms, start, c->ev[2 + p])) != hipSuccess) return hip_fail(c, e, "timing");
             pass += ms;
             if (p > 0) {
-                if ((e = hipEventElapsedTime(&ms, c->ev[1 + p], start)) != hipSuccess) return hip_fail(c, e, "timing");
+                hipEvent_t prev = c->last_surr ? c->ev[3 * np + 3 + p - 1] : c->ev[1 + p];
+                if ((e = hipEventElapsedTime(&ms, prev, start)) != hipSuccess) return hip_fail(c, e, "timing");
                 comp += ms;
+            }
+            if (c->last_surr) {
+                if ((e = hipEventElapsedTime(&ms, c->ev[2 + p], c->ev[3 * np + 3 + p])) != hipSuccess)
+                    return hip_fail(c, e, "timing");
+                xs += ms;
             }
         }
         out->pass_ms = pass;
         out->compact_ms = comp;
-        if ((e = hipEventElapsedTime(&ms, c->ev[1 + np], c->ev[2 + np])) != hipSuccess) return hip_fail(c, e, "timing");
+        out->surr_ms = xs;
+        hipEvent_t rstart = c->last_surr ? c->ev[4 * np + 2] : c->ev[1 + np];
+        if ((e = hipEventElapsedTime(&ms, rstart, c->ev[2 + np])) != hipSuccess) return hip_fail(c, e, "timing");
         out->refine_ms = ms;
         if ((e = hipEventElapsedTime(&ms, c->ev[0], c->ev[2 + np])) != hipSuccess) return hip_fail(c, e, "timing");
         out->total_ms = ms;

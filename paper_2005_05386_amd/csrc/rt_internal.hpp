@@ -22,7 +22,8 @@ enum QField {
     Q_H = 11,   // current trial step (RK45)
     Q_STEPS = 12,  // accepted steps (int bits)
     Q_ATT = 13,    // trial steps incl. rejected (int bits)
-    Q_NFIELDS = 14
+    Q_SKIP = 14,   // surrogate: bump whose support sphere is integrated through (int bits, -1 none)
+    Q_NFIELDS = 15
 };
 
 // Counter block layout (int32 words).
@@ -32,6 +33,16 @@ constexpr int CTR_PASS_WORDS = 256;  // per pass: 8 chunk counters (16 words apa
 constexpr int CTR_CHUNK_STRIDE = 16;
 constexpr int CTR_SURV = 128;        // offset of the survivor counts inside a pass block
 constexpr int CTR_NCH = 192;         // offset of the pass's chunk count
+constexpr int CTR_XQ = 193;          // offset of the pass's crossing count (surrogate)
+// Surrogate control block after the last pass block: per-network crossing
+// counts [64] at XC_CNT, row offsets [65] at XC_ROW, tile offsets [65] at
+// XC_TILE (entry 64 of each: the totals).
+constexpr int CTR_SURR_WORDS = 256;
+constexpr int MAX_NETS = 64;
+constexpr int XC_CNT = 0, XC_ROW = 64, XC_TILE = 136;
+// Per-network parameter stride of the networks the tracer holds (16-byte
+// aligned rows for vector loads of bf16 weights).
+constexpr int64_t MLP_P_PAD = 134920;
 
 constexpr int MAX_PASSES_API = 512;
 constexpr int SCAN_BLOCK = 1024;     // chunks per block of the survivor scan
@@ -51,6 +62,8 @@ enum Stat {
     ST_ACC_EVALS,
     ST_BUMP_EVALS,
     ST_OBJ_TESTS,
+    ST_XING,  // surrogate crossings queued
+    ST_XACC,  // surrogate crossings accepted
     ST_N
 };
 
@@ -94,6 +107,29 @@ struct TraceArgs {
     float *tape_ck;
     float *tape_hit;
     int ckpt_every, n_ckpt;
+    // surrogate (graph metric, RK4, one set): per bump two float4
+    //   (cx, cy, cz, R^2), (sigma, network (int bits, -1: not eligible), R, 0)
+    // with R = 3 sigma; rays entering an eligible support sphere park there
+    // and push (ray id, bump, rank within the network's rows) to xq.
+    int surr;
+    int n_passes;
+    const float4 *surr_sb;
+    int4 *xq;
+    int *xctl;  // control block: per-network counts, offsets, tile offsets
+};
+
+// Learned crossing stage run between passes.
+struct SurrArgs {
+    int n_nets, n_tab, n_bins;
+    int64_t stride;       // parameters per network in wb / params (multiple of 8)
+    float tol;
+    const __bf16 *wb;     // [n_nets][stride], 16-byte aligned
+    const float *params;  // [n_nets][stride]
+    const float *scale;   // [n_nets]
+    const float *arc;     // [n_nets][n_tab] arc in units of sigma at cos(theta) = i / (n_tab - 1)
+    const float *err;     // [n_nets][n_bins][2] position / direction error bounds per bin of cos(theta)
+    int2 *sorted;         // crossing slot -> (ray id, bump), grouped by network
+    float *xin, *xout;    // [slots][6]
 };
 
 constexpr int TAPE_REC = 12;
@@ -111,10 +147,84 @@ struct DeviceData {
 
 // Enqueue a full trace (reset, passes, refine).  Returns hipSuccess or the
 // first launch error.
-// ev: NULL, or n_passes + 3 events recorded before the reset, after the
-// reset, after each pass and after the refinement.
+// ev: NULL, or 4 n_passes + 3 events: before the reset, after the reset,
+// after each pass [2 + p], after the refinement [2 + n_passes], after each
+// compaction [2 n_passes + 2 + p] and after each crossing stage
+// [3 n_passes + 3 + p].  S: crossing stage (a.surr), else NULL; the
+// control block after the pass blocks must hold CTR_SURR_WORDS words.
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid_blocks,
-                        int refine_blocks, hipStream_t s, hipEvent_t *ev);
+                        int refine_blocks, hipStream_t s, hipEvent_t *ev, const struct SurrArgs *S, int mlp_blocks);
+// ------------------------------------------------------------- MLP (BF16)
+enum Epi { EPI_NONE = 0, EPI_HIDDEN = 1, EPI_BIAS = 2, EPI_DSILU = 3 };
+
+// Grouped GEMM C = A B (see rt_mlp.hip).  Group g offsets every operand by
+// its group stride; with rows != NULL group g has rows[g] rows starting at
+// row row_off[g] of A and C (A's group stride is then normally 0).
+struct GemmArgs {
+    const __bf16 *A;
+    int64_t a_g;
+    int64_t sam, sak;
+    const __bf16 *B;
+    int64_t b_g;
+    int64_t sbk, sbn;
+    int M, N, K;
+    const int *rows;
+    const int *row_off;
+    int epi;
+    const float *bias;
+    int64_t bias_g;
+    float *Cf;
+    int64_t cf_g, ldcf;
+    __bf16 *Cb;
+    int64_t cb_g, ldcb;
+    const float *Z;
+    int64_t z_g, ldz;
+};
+
+// Per-network parameter layout (floats / bf16 values).
+constexpr int64_t MLP_H = 256, MLP_IN = 6, MLP_OUT = 6;
+constexpr int64_t OFF_W1 = 0, OFF_B1 = OFF_W1 + MLP_H * MLP_IN, OFF_W2 = OFF_B1 + MLP_H, OFF_B2 = OFF_W2 + MLP_H * MLP_H,
+                  OFF_W3 = OFF_B2 + MLP_H, OFF_B3 = OFF_W3 + MLP_H * MLP_H, OFF_W4 = OFF_B3 + MLP_H,
+                  OFF_B4 = OFF_W4 + MLP_OUT * MLP_H, MLP_P = OFF_B4 + MLP_OUT;
+
+// Activation workspace of a forward pass kept for the backward.
+struct MlpWork {
+    float *xf;        // [n][B][6] inputs (FP32 first layer)
+    float *z[3];      // [n][B][256] pre-activations
+    __bf16 *h[3];     // [n][B][256] activations
+    __bf16 *dyb;      // [n][B][6]
+    float *dzf[2];    // [n][B][256]
+    __bf16 *dzb[2];   // [n][B][256]
+    float *part;      // colsum partials [n][ceil(B/256)][256]
+};
+size_t mlp_work_bytes(int n_nets, int batch);
+void mlp_work_carve(void *base, int n_nets, int batch, MlpWork &w);
+hipError_t mlp_forward(int n_nets, int batch, const __bf16 *wb, const float *params, const float *x, float *y,
+                       const MlpWork &w, bool keep, hipStream_t s);
+hipError_t mlp_backward(int n_nets, int batch, const __bf16 *wb, const float *dy, float *grad, const MlpWork &w,
+                        hipStream_t s);
+hipError_t launch_gemm(const GemmArgs &G, int groups, int max_rows, hipStream_t s);
+hipError_t launch_colsum(const float *X, int64_t xg, int rows, int N, int groups, float *part, float *out,
+                         int64_t out_g, hipStream_t s);
+hipError_t launch_adamw(float *p, __bf16 *pb, float *m, float *v, const float *g, int64_t n, float lr, float b1,
+                        float b2, float eps, float wd, int step, hipStream_t s);
+hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t s);
+hipError_t launch_mse_grad(const float *y, const float *t, float *dy, int64_t n, int batch, float *part, int nblk,
+                           hipStream_t s);
+
+hipError_t launch_cross_gen(const float *kappa, const float *scale, int n_shapes, int n_per, float h, int grid,
+                            uint64_t seed, float *X, float *Y, float *AUX, hipStream_t s);
+hipError_t launch_cross_cal(const float *X, const float *P, const float *Y, const float *scale, int n_shapes,
+                            int n_per, int n_bins, float *err, hipStream_t s);
+// Crossing stage after pass `pass`: group by network, fused MLP forward,
+// decode, probe, and jump or fall back.
+// Fused grouped MLP forward: ctl holds per-network row offsets at XC_ROW
+// and tile offsets at XC_TILE; uses S.wb, S.params, S.stride, S.n_nets,
+// S.xin, S.xout.
+hipError_t launch_mlp_grouped(const int *ctl, const SurrArgs &S, int blocks, hipStream_t s);
+hipError_t launch_surr_stage(const TraceArgs &a, const SurrArgs &S, const float4 *bump_f, int pass, int mlp_blocks,
+                             hipStream_t s);
+
 // Adjoint of a taped RK4 trace (graph metric): per-chunk partial gradients,
 // then per-set sums into grad [n_sets][n_bumps][5].
 hipError_t launch_adjoint(const TraceArgs &a, const DeviceData &d, const float *grad_hit, float *partial,

@@ -1,0 +1,448 @@
+// Kernels of the surrogate MLP (6 -> 256 -> 256 -> 256 -> 6, SiLU): the
+// first layer (K = 6, negligible work) in FP32 on the vector units so that
+// the input direction keeps full precision, the three 256-wide products as
+// BF16 matrix-core GEMMs with FP32 accumulation and fused epilogues, column
+// sums for bias gradients, and the AdamW update.
+//
+// GEMM: for every group g (one network), C[m][n] = sum_k A(m,k) B(k,n) with
+// A(m,k) = A[a_off(g) + m*sam + k*sak], B(k,n) = B[b_off(g) + k*sbk + n*sbn]
+// (bf16), arbitrary strides so that transposed operands need no copies.
+// A 256-thread workgroup computes a 64x64 tile of C: the 64x32 A slice and
+// 32x64 B slice of each K step are staged in LDS (zero-filled outside the
+// matrix), then each wave accumulates a 32x32 block with four
+// v_mfma_f32_16x16x32_bf16 per step.  Lane l of a 16x16x32 MFMA supplies
+// A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. +7][l%16] and receives
+// D[4(l/16) + j][l%16], j = 0..3.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "rt_internal.hpp"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+    float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+__global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G) {
+    __shared__ __bf16 As[64][32 + 8];
+    __shared__ __bf16 Bs[64][32 + 8];  // transposed: Bs[n][k]
+    const int g = blockIdx.z;
+    int M = G.M;
+    int64_t row0 = 0;
+    if (G.rows) {
+        M = G.rows[g];
+        row0 = G.row_off[g];
+    }
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    if (m0 >= M) return;
+    const __bf16 *__restrict__ A = G.A + g * G.a_g + row0 * G.sam;
+    const __bf16 *__restrict__ B = G.B + g * G.b_g;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const __bf16 zero = (__bf16)0.0f;
+    for (int k0 = 0; k0 < G.K; k0 += 32) {
+        // stage: thread t loads row t/4 (A) / column t/4 (B), 8 k values
+        {
+            const int r = tid >> 2, kc = (tid & 3) * 8;
+            const int m = m0 + r, n = n0 + r;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = k0 + kc + i;
+                As[r][kc + i] = (m < M && k < G.K) ? A[(int64_t)m * G.sam + (int64_t)k * G.sak] : zero;
+                Bs[r][kc + i] = (n < G.N && k < G.K) ? B[(int64_t)k * G.sbk + (int64_t)n * G.sbn] : zero;
+            }
+        }
+        __syncthreads();
+        const int kq = (lane >> 4) * 8;
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                a[i][e] = As[wm + 16 * i + (lane & 15)][kq + e];
+                b[i][e] = Bs[wn + 16 * i + (lane & 15)][kq + e];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // epilogue
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + e;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                if (m >= M || n >= G.N) continue;
+                const int64_t gm = row0 + m;
+                float v = acc[i][j][e];
+                switch (G.epi) {
+                case rti::EPI_HIDDEN: {
+                    const float z = v + G.bias[g * G.bias_g + n];
+                    if (G.Cf) G.Cf[g * G.cf_g + gm * G.ldcf + n] = z;
+                    G.Cb[g * G.cb_g + gm * G.ldcb + n] = (__bf16)silu(z);
+                    break;
+                }
+                case rti::EPI_BIAS:
+                    G.Cf[g * G.cf_g + gm * G.ldcf + n] = v + G.bias[g * G.bias_g + n];
+                    break;
+                case rti::EPI_DSILU: {
+                    const float d = v * dsilu(G.Z[g * G.z_g + gm * G.ldz + n]);
+                    G.Cf[g * G.cf_g + gm * G.ldcf + n] = d;
+                    G.Cb[g * G.cb_g + gm * G.ldcb + n] = (__bf16)d;
+                    break;
+                }
+                default:
+                    G.Cf[g * G.cf_g + gm * G.ldcf + n] = v;
+                    break;
+                }
+            }
+}
+
+// First layer in FP32: thread o of a 256-thread block computes unit o of
+// z1 = W1 x + b1 for up to 64 rows of network blockIdx.y; h1 = silu(z1) is
+// stored in bf16 for the next product, z1 (and x) for a backward pass.
+__global__ __launch_bounds__(256) void k_l1_fwd(const float *__restrict__ params, const float *__restrict__ X, int B,
+                                                float *__restrict__ Z, __bf16 *__restrict__ H,
+                                                float *__restrict__ Xkeep) {
+    const int g = blockIdx.y, o = threadIdx.x;
+    const int m0 = blockIdx.x * 64;
+    if (m0 >= B) return;
+    const float *__restrict__ W = params + g * rti::MLP_P + rti::OFF_W1 + o * 6;
+    const float w0 = W[0], w1 = W[1], w2 = W[2], w3 = W[3], w4 = W[4], w5 = W[5];
+    const float bias = params[g * rti::MLP_P + rti::OFF_B1 + o];
+    const int m1 = min(B, m0 + 64);
+    for (int m = m0; m < m1; ++m) {
+        const int64_t r = (int64_t)g * B + m;
+        const float *__restrict__ x = X + r * 6;
+        float z = bias;
+        z = fmaf(w0, x[0], z);
+        z = fmaf(w1, x[1], z);
+        z = fmaf(w2, x[2], z);
+        z = fmaf(w3, x[3], z);
+        z = fmaf(w4, x[4], z);
+        z = fmaf(w5, x[5], z);
+        if (Z) Z[r * rti::MLP_H + o] = z;
+        H[r * rti::MLP_H + o] = (__bf16)silu(z);
+        if (Xkeep && o < 6) Xkeep[r * 6 + o] = x[o];
+    }
+}
+
+// First-layer gradients in FP32: dW1[o][i] = sum_m dz1[m][o] x[m][i] and
+// db1[o] = sum_m dz1[m][o]; per block of 256 rows a sequential partial,
+// then the partials summed in order.
+__global__ __launch_bounds__(256) void k_l1_grad_part(const float *__restrict__ DZ, const float *__restrict__ X, int B,
+                                                      float *__restrict__ part) {
+    const int g = blockIdx.y, c = blockIdx.x, o = threadIdx.x;
+    const int r0 = c * 256, r1 = min(B, r0 + 256);
+    float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int m = r0; m < r1; ++m) {
+        const int64_t r = (int64_t)g * B + m;
+        const float d = DZ[r * rti::MLP_H + o];
+        const float *__restrict__ x = X + r * 6;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) a[i] = fmaf(d, x[i], a[i]);
+        a[6] += d;
+    }
+    float *__restrict__ dst = part + (((int64_t)g * gridDim.x + c) * rti::MLP_H + o) * 7;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) dst[i] = a[i];
+}
+__global__ __launch_bounds__(256) void k_l1_grad_final(const float *__restrict__ part, int nchunk,
+                                                       float *__restrict__ grad) {
+    const int g = blockIdx.x, o = threadIdx.x;
+    float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < nchunk; ++c) {
+        const float *__restrict__ src = part + (((int64_t)g * nchunk + c) * rti::MLP_H + o) * 7;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) a[i] += src[i];
+    }
+    float *__restrict__ G = grad + (int64_t)g * rti::MLP_P;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) G[rti::OFF_W1 + o * 6 + i] = a[i];
+    G[rti::OFF_B1 + o] = a[6];
+}
+
+// out[g][n] = sum_m X[g][m][n], fixed order: per block of 256 rows a
+// sequential partial, then partials summed in order.
+__global__ void k_colsum_part(const float *__restrict__ X, int64_t xg, int rows, int N, float *__restrict__ part) {
+    const int g = blockIdx.z, n = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+    if (n >= N) return;
+    const int r0 = c * 256, r1 = min(rows, r0 + 256);
+    float s = 0.f;
+    for (int r = r0; r < r1; ++r) s += X[g * xg + (int64_t)r * N + n];
+    part[((int64_t)g * gridDim.y + c) * N + n] = s;
+}
+__global__ void k_colsum_final(const float *__restrict__ part, int nchunk, int N, float *__restrict__ out,
+                               int64_t out_g) {
+    const int g = blockIdx.y, n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[((int64_t)g * nchunk + c) * N + n];
+    out[g * out_g + n] = s;
+}
+
+// AdamW with bias correction; refreshes the bf16 copy of the parameters.
+__global__ void k_adamw(float *__restrict__ p, __bf16 *__restrict__ pb, float *__restrict__ m, float *__restrict__ v,
+                        const float *__restrict__ gr, int64_t n, float lr, float b1, float b2, float eps, float wd,
+                        float c1, float c2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float g = gr[i];
+        float mi = b1 * m[i] + (1.f - b1) * g;
+        float vi = b2 * v[i] + (1.f - b2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        float pi = p[i] - lr * ((mi * c1) / (sqrtf(vi * c2) + eps) + wd * p[i]);
+        p[i] = pi;
+        pb[i] = (__bf16)pi;
+    }
+}
+
+// dy = 2 (y - t) / batch and per-block squared-error sums (fixed order).
+__global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ y, const float *__restrict__ t,
+                                                  float *__restrict__ dy, int64_t n, float inv_batch,
+                                                  float *__restrict__ part) {
+    __shared__ float sh[256];
+    float acc = 0.f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float d = y[i] - t[i];
+        dy[i] = 2.f * d * inv_batch;
+        acc += d * d;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_to_bf16(const float *__restrict__ x, __bf16 *__restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (__bf16)x[i];
+}
+
+}  // namespace
+
+namespace rti {
+
+hipError_t launch_gemm(const GemmArgs &G, int groups, int max_rows, hipStream_t s) {
+    dim3 grid((G.N + 63) / 64, (max_rows + 63) / 64, groups);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float *X, int64_t xg, int rows, int N, int groups, float *part, float *out,
+                         int64_t out_g, hipStream_t s) {
+    int nchunk = (rows + 255) / 256;
+    hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, nchunk, groups), dim3(64), 0, s, X, xg, rows, N, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3((N + 63) / 64, groups), dim3(64), 0, s, (const float *)part, nchunk, N,
+                       out, out_g);
+    return hipGetLastError();
+}
+
+hipError_t launch_adamw(float *p, __bf16 *pb, float *m, float *v, const float *g, int64_t n, float lr, float b1,
+                        float b2, float eps, float wd, int step, hipStream_t s) {
+    float c1 = 1.0f / (1.0f - powf(b1, (float)step)), c2 = 1.0f / (1.0f - powf(b2, (float)step));
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_adamw, dim3(blocks), dim3(256), 0, s, p, pb, m, v, g, n, lr, b1, b2, eps, wd, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse_grad(const float *y, const float *t, float *dy, int64_t n, int batch, float *part, int nblk,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_mse_grad, dim3(nblk), dim3(256), 0, s, y, t, dy, n, 1.0f / (float)batch, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+}  // namespace rti
+
+namespace rti {
+
+size_t mlp_work_bytes(int n_nets, int batch) {
+    size_t nb = (size_t)n_nets * batch;
+    size_t nch = ((size_t)batch + 255) / 256;
+    return nb * MLP_IN * 4 + nb * MLP_OUT * 2 + nb * MLP_H * (3 * 4 + 3 * 2 + 2 * 4 + 2 * 2) +
+           (size_t)n_nets * nch * MLP_H * 7 * 4 + 16 * 256;
+}
+
+void mlp_work_carve(void *base, int n_nets, int batch, MlpWork &w) {
+    size_t nb = (size_t)n_nets * batch;
+    size_t nch = ((size_t)batch + 255) / 256;
+    char *p = (char *)base;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += (bytes + 255) & ~(size_t)255;
+        return (void *)r;
+    };
+    w.xf = (float *)take(nb * MLP_IN * 4);
+    for (int i = 0; i < 3; ++i) w.z[i] = (float *)take(nb * MLP_H * 4);
+    for (int i = 0; i < 3; ++i) w.h[i] = (__bf16 *)take(nb * MLP_H * 2);
+    w.dyb = (__bf16 *)take(nb * MLP_OUT * 2);
+    for (int i = 0; i < 2; ++i) w.dzf[i] = (float *)take(nb * MLP_H * 4);
+    for (int i = 0; i < 2; ++i) w.dzb[i] = (__bf16 *)take(nb * MLP_H * 2);
+    w.part = (float *)take((size_t)n_nets * nch * MLP_H * 7 * 4);
+}
+
+static GemmArgs gemm0() {
+    GemmArgs G{};
+    G.epi = EPI_NONE;
+    return G;
+}
+
+// y = MLP(x) for n_nets networks of batch rows each.  keep: store the
+// pre-activations for a backward pass.
+hipError_t mlp_forward(int n, int B, const __bf16 *wb, const float *params, const float *x, float *y, const MlpWork &w,
+                       bool keep, hipStream_t s) {
+    hipLaunchKernelGGL(k_l1_fwd, dim3((B + 63) / 64, n), dim3(256), 0, s, params, x, B, keep ? w.z[0] : nullptr,
+                       w.h[0], keep ? w.xf : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const __bf16 *in = w.h[0];
+    const int64_t in_w = MLP_H;
+    const int64_t offW[3] = {OFF_W1, OFF_W2, OFF_W3}, offB[3] = {OFF_B1, OFF_B2, OFF_B3};
+    for (int l = 1; l < 3; ++l) {
+        GemmArgs G = gemm0();
+        G.A = in;
+        G.a_g = (int64_t)B * in_w;
+        G.sam = in_w;
+        G.sak = 1;
+        G.B = wb + offW[l];
+        G.b_g = MLP_P;
+        G.sbk = 1;
+        G.sbn = in_w;
+        G.M = B;
+        G.N = (int)MLP_H;
+        G.K = (int)in_w;
+        G.epi = EPI_HIDDEN;
+        G.bias = params + offB[l];
+        G.bias_g = MLP_P;
+        G.Cf = keep ? w.z[l] : nullptr;
+        G.cf_g = (int64_t)B * MLP_H;
+        G.ldcf = MLP_H;
+        G.Cb = w.h[l];
+        G.cb_g = (int64_t)B * MLP_H;
+        G.ldcb = MLP_H;
+        if ((e = launch_gemm(G, n, B, s)) != hipSuccess) return e;
+        in = w.h[l];
+    }
+    GemmArgs G = gemm0();
+    G.A = in;
+    G.a_g = (int64_t)B * MLP_H;
+    G.sam = MLP_H;
+    G.sak = 1;
+    G.B = wb + OFF_W4;
+    G.b_g = MLP_P;
+    G.sbk = 1;
+    G.sbn = MLP_H;
+    G.M = B;
+    G.N = (int)MLP_OUT;
+    G.K = (int)MLP_H;
+    G.epi = EPI_BIAS;
+    G.bias = params + OFF_B4;
+    G.bias_g = MLP_P;
+    G.Cf = y;
+    G.cf_g = (int64_t)B * MLP_OUT;
+    G.ldcf = MLP_OUT;
+    return launch_gemm(G, n, B, s);
+}
+
+// grad = dL/dparams given dy = dL/dy, using the workspace of the last
+// forward with keep = true.
+hipError_t mlp_backward(int n, int B, const __bf16 *wb, const float *dy, float *grad, const MlpWork &w, hipStream_t s) {
+    hipError_t e = launch_to_bf16(dy, w.dyb, (int64_t)n * B * MLP_OUT, s);
+    if (e != hipSuccess) return e;
+    // weight gradient dW[o][i] = sum_b d[b][o] in[b][i]
+    auto wgrad = [&](const __bf16 *d, int64_t dw, const __bf16 *in, int64_t iw, int64_t off) {
+        GemmArgs G = gemm0();
+        G.A = d;
+        G.a_g = (int64_t)B * dw;
+        G.sam = 1;
+        G.sak = dw;
+        G.B = in;
+        G.b_g = (int64_t)B * iw;
+        G.sbk = iw;
+        G.sbn = 1;
+        G.M = (int)dw;
+        G.N = (int)iw;
+        G.K = B;
+        G.Cf = grad + off;
+        G.cf_g = MLP_P;
+        G.ldcf = iw;
+        return launch_gemm(G, n, (int)dw, s);
+    };
+    // back-propagated signal dz = (d W) * silu'(z)
+    auto bprop = [&](const __bf16 *d, int64_t dw, int64_t offW, const float *z, float *dzf, __bf16 *dzb) {
+        GemmArgs G = gemm0();
+        G.A = d;
+        G.a_g = (int64_t)B * dw;
+        G.sam = dw;
+        G.sak = 1;
+        G.B = wb + offW;
+        G.b_g = MLP_P;
+        G.sbk = MLP_H;
+        G.sbn = 1;
+        G.M = B;
+        G.N = (int)MLP_H;
+        G.K = (int)dw;
+        G.epi = EPI_DSILU;
+        G.Z = z;
+        G.z_g = (int64_t)B * MLP_H;
+        G.ldz = MLP_H;
+        G.Cf = dzf;
+        G.cf_g = (int64_t)B * MLP_H;
+        G.ldcf = MLP_H;
+        G.Cb = dzb;
+        G.cb_g = (int64_t)B * MLP_H;
+        G.ldcb = MLP_H;
+        return launch_gemm(G, n, B, s);
+    };
+    if ((e = wgrad(w.dyb, MLP_OUT, w.h[2], MLP_H, OFF_W4)) != hipSuccess) return e;
+    if ((e = launch_colsum(dy, (int64_t)B * MLP_OUT, B, (int)MLP_OUT, n, w.part, grad + OFF_B4, MLP_P, s)) != hipSuccess)
+        return e;
+    if ((e = bprop(w.dyb, MLP_OUT, OFF_W4, w.z[2], w.dzf[0], w.dzb[0])) != hipSuccess) return e;
+    // layer 3: dz in buffer 0
+    if ((e = wgrad(w.dzb[0], MLP_H, w.h[1], MLP_H, OFF_W3)) != hipSuccess) return e;
+    if ((e = launch_colsum(w.dzf[0], (int64_t)B * MLP_H, B, (int)MLP_H, n, w.part, grad + OFF_B3, MLP_P, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = bprop(w.dzb[0], MLP_H, OFF_W3, w.z[1], w.dzf[1], w.dzb[1])) != hipSuccess) return e;
+    // layer 2: dz in buffer 1
+    if ((e = wgrad(w.dzb[1], MLP_H, w.h[0], MLP_H, OFF_W2)) != hipSuccess) return e;
+    if ((e = launch_colsum(w.dzf[1], (int64_t)B * MLP_H, B, (int)MLP_H, n, w.part, grad + OFF_B2, MLP_P, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = bprop(w.dzb[1], MLP_H, OFF_W2, w.z[0], w.dzf[0], w.dzb[0])) != hipSuccess) return e;
+    // layer 1 (FP32): dz in buffer 0, input x
+    const int nch = (B + 255) / 256;
+    hipLaunchKernelGGL(k_l1_grad_part, dim3(nch, n), dim3(256), 0, s, w.dzf[0], w.xf, B, w.part);
+    hipLaunchKernelGGL(k_l1_grad_final, dim3(n), dim3(256), 0, s, w.part, nch, grad);
+    return hipGetLastError();
+}
+
+}  // namespace rti

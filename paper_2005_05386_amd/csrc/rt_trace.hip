@@ -94,13 +94,18 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
         P(rti::Q_H, A.h);
         P(rti::Q_STEPS, __int_as_float(0));
         P(rti::Q_ATT, __int_as_float(0));
+        P(rti::Q_SKIP, __int_as_float(-1));
     }
 }
 
 // ================================================================ the pass
 // Occupancy: 6 waves per SIMD (at most 80 VGPRs) measured fastest for the
 // RK4 graph and twist kernels although a few long-lived values spill.
-template <int KIND, int STEP, bool COUNT>
+// SURR: learned crossings (graph metric, RK4, one parameter set): a ray whose
+// step chord enters the support sphere of an eligible bump stops on the
+// sphere (the partial step is committed, its fraction of h added to t) and
+// is queued for the crossing stage that runs after the pass.
+template <int KIND, int STEP, bool COUNT, bool SURR = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
@@ -170,6 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
             V3<float> xh, xl, y;
             float th = 0.f, tl = 0.f, hc = A.h;
             int steps = 0, att = 0;
+            int skip = -1;  // SURR only
             if (valid) {
                 const float *__restrict__ src = st + ((int64_t)(id >> 6) * rti::Q_NFIELDS * 64 + (id & 63));
                 auto F = [&](int f) { return src[f * 64]; };
@@ -181,22 +187,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                 hc = F(rti::Q_H);
                 steps = __float_as_int(F(rti::Q_STEPS));
                 att = __float_as_int(F(rti::Q_ATT));
+                if constexpr (SURR) skip = __float_as_int(F(rti::Q_SKIP));
             } else {
                 xh = xl = y = mk(0.f, 0.f, 0.f);
             }
             if (pass == 0) st_rays += __popcll(ballot(valid));
 
             bool alive = valid;
+            bool parked = false;  // SURR only
             int acc_pass = 0;
             int it = 0;
-            uint64_t bmask = 0, omask = 0;
+            uint64_t bmask = 0, omask = 0, emask = 0;
             uint64_t sm[4] = {0, 0, 0, 0};
             V3<float> A0 = mk(0.f, 0.f, 0.f);
             bool need_a0 = true;
             unsigned c_eval = 0, c_bump = 0, c_obj = 0, lane_objs = 0;  // COUNT only
 
             for (;;) {
-                bool act = alive && (STEP == STEP_RK45 ? acc_pass < A.S : it < A.S);
+                bool act = alive && (STEP == STEP_RK45 ? acc_pass < A.S : it < A.S) && !(SURR && parked);
                 uint64_t am = ballot(act);
                 if (am == 0) break;
 
@@ -211,6 +219,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             sm[w] = rem >= 64 ? ~0ull : (rem > 0 ? ((1ull << rem) - 1ull) : 0ull);
                         }
                         omask = ((1ull << np) - 1ull) | (((1ull << nt) - 1ull) << 8);
+                        if constexpr (SURR)
+                            emask = ballot(lane < n_bumps && __float_as_int(A.surr_sb[2 * lane + 1].y) >= 0);
                     } else {
                         const float inf = __builtin_huge_valf();
                         float lo[3], hi[3];
@@ -250,6 +260,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             on = box_dist2(tp[0], tp[1], tp[2], lo, hi) <= rr * rr;
                         }
                         omask = ballot(on);
+                        if constexpr (SURR) {
+                            // eligible support spheres this wave can reach in the window
+                            bool en = false;
+                            if (lane < n_bumps) {
+                                const float4 c0 = A.surr_sb[2 * lane];
+                                en = __float_as_int(A.surr_sb[2 * lane + 1].y) >= 0 &&
+                                     box_dist2(c0.x, c0.y, c0.z, lo, hi) <= c0.w;
+                            }
+                            emask = ballot(en);
+                        }
                     }
                     if (COUNT && act) {
                         // objects inside this lane's own window (what one ray alone would need)
@@ -295,6 +315,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                 // records that pre-step state without keeping copies of it.
                 bool hit = false;
                 int hit_id = -1;
+                int park_b = -1;  // SURR: sphere the lane parked on in this step
                 float hit_s = 2.f, hstep = A.h;
                 if (act) {
                     V3<float> p = xh + xl;
@@ -382,7 +403,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                                 }
                             }
                         }
-                        if (hit_id >= 0) {
+                        // ---- chord entering an eligible support sphere (SURR)
+                        float ent_s = 2.f;
+                        int ent_b = -1;
+                        if constexpr (SURR) {
+                            uint64_t em = emask;
+                            while (em) {
+                                const int b = __builtin_ctzll(em);
+                                em &= em - 1;
+                                const float4 c0 = A.surr_sb[2 * b];
+                                V3<float> o = mk((xh.x - c0.x) + xl.x, (xh.y - c0.y) + xl.y, (xh.z - c0.z) + xl.z);
+                                const float o2 = dot(o, o);
+                                const V3<float> on = o + dx;
+                                if (b != skip && o2 >= c0.w && dot(on, on) < c0.w) {
+                                    // smaller root of |o + s dx|^2 = R^2
+                                    const float B = dot(o, dx), C = o2 - c0.w;
+                                    const float disc = fmaxf(B * B - DD * C, 0.f);
+                                    const float sr = fminf(fmaxf((-B - sqrtf(disc)) / DD, 0.f), 1.f);
+                                    if (sr < ent_s) {
+                                        ent_s = sr;
+                                        ent_b = b;
+                                    }
+                                }
+                            }
+                            // park only while enough passes remain to finish the ray afterwards
+                            if (ent_b >= 0 && (A.n_passes - 1 - pass) * A.S < A.max_steps - steps) ent_b = -1;
+                        }
+                        if (SURR && ent_b >= 0 && !(hit_id >= 0 && hit_s < ent_s)) {
+                            two_sum_add(xh.x, xl.x, ent_s * dx.x);
+                            two_sum_add(xh.y, xl.y, ent_s * dx.y);
+                            two_sum_add(xh.z, xl.z, ent_s * dx.z);
+                            y = y + ent_s * dv;
+                            two_sum_add(th, tl, ent_s * A.h);
+                            parked = true;
+                            park_b = ent_b;
+                            hit_id = -1;
+                        } else if (hit_id >= 0) {
                             hit = true;
                             acc_pass++;  // the hit step was integrated: count it
                         } else {
@@ -395,13 +451,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             acc_pass++;
                             if (STEP == STEP_RK45) two_sum_add(th, tl, hstep);
                             // RK45 lands on t_max up to float rounding of the clipped last step
-                            float t = (STEP == STEP_RK45) ? th + tl : (float)steps * A.h;
+                            float t = (STEP == STEP_RK45) ? th + tl : (float)steps * A.h + (SURR ? th + tl : 0.f);
                             float t_end = (STEP == STEP_RK45) ? A.t_max * (1.0f - 1e-6f) : A.t_max;
                             done_miss = steps >= A.max_steps || t >= t_end;
                         }
                     }
                     if (done_fail || done_miss) {
-                        write_out(A, qbase + pix, xh + xl, STEP == STEP_RK45 ? th + tl : (float)steps * A.h, y,
+                        write_out(A, qbase + pix, xh + xl,
+                                  STEP == STEP_RK45 ? th + tl : (float)steps * A.h + (SURR ? th + tl : 0.f), y,
                                   done_fail ? -2 : -1, steps);
                         if (A.tape_hit) A.tape_hit[(int64_t)(qbase + pix) * rti::TAPE_REC + 11] = __int_as_float(-1);
                     }
@@ -424,6 +481,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                                              __int_as_float(steps), tl);
                         rec[4] = make_float4(__int_as_float((int)(uint32_t)bmask), __int_as_float((int)(bmask >> 32)),
                                              0.f, 0.f);
+                    }
+                }
+                if constexpr (SURR) {
+                    // ---- queue the rays that parked on a support sphere in this step
+                    const bool now = park_b >= 0;
+                    const uint64_t pm = ballot(now);
+                    if (pm) {
+                        int base = 0;
+                        if (lane == 0) base = atomicAdd(pass_ctr + rti::CTR_XQ, __popcll(pm));
+                        base = uniform_i(__shfl(base, 0));
+                        if (now) {
+                            const int net = __float_as_int(A.surr_sb[2 * park_b + 1].y);
+                            const int rank = atomicAdd(A.xctl + net, 1);
+                            A.xq[base + mbcnt64(pm)] = make_int4(id, park_b, rank, 0);
+                        }
                     }
                 }
                 it++;
@@ -452,6 +524,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                     P(rti::Q_H, hc);
                     P(rti::Q_STEPS, __int_as_float(steps));
                     P(rti::Q_ATT, __int_as_float(att));
+                    if constexpr (SURR) P(rti::Q_SKIP, __int_as_float(skip));
                 }
             }
             // accepted steps of this chunk
@@ -574,7 +647,8 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
         }
         V3<double> xs, ys;
         step(s * h, xs, ys);
-        double tk = STEP == STEP_RK45 ? tk_hi + tk_lo : (double)k * (double)A.h;
+        // RK4 and Euler: k steps of h, plus (surrogate) jumps and partial steps
+        double tk = STEP == STEP_RK45 ? tk_hi + tk_lo : (double)k * (double)A.h + (tk_hi + tk_lo);
         A.out_hit[3 * (int64_t)oi + 0] = (float)xs.x;
         A.out_hit[3 * (int64_t)oi + 1] = (float)xs.y;
         A.out_hit[3 * (int64_t)oi + 2] = (float)xs.z;
@@ -687,9 +761,20 @@ __global__ void k_reset(int *ctr, int n_words, unsigned long long *stats) {
     if (blockIdx.x == 0 && threadIdx.x < rti::ST_N) stats[threadIdx.x] = 0;
 }
 
+template <int KIND, int STEP, bool SURR>
+hipError_t launch_pass(const TraceArgs &a, const rti::DeviceData &d, int p, int grid, hipStream_t s) {
+    if (a.count)
+        hipLaunchKernelGGL((k_trace_pass<KIND, STEP, true, SURR>), dim3(grid), dim3(256), 0, s, a, p, d.bump_f,
+                           d.sph_f, d.pln_f, d.tor_f);
+    else
+        hipLaunchKernelGGL((k_trace_pass<KIND, STEP, false, SURR>), dim3(grid), dim3(256), 0, s, a, p, d.bump_f,
+                           d.sph_f, d.pln_f, d.tor_f);
+    return hipGetLastError();
+}
+
 template <int KIND, int STEP>
 hipError_t launch_kind_step(const TraceArgs &a, const rti::DeviceData &d, int n_passes, int grid, int rgrid,
-                            hipStream_t s, hipEvent_t *ev) {
+                            hipStream_t s, hipEvent_t *ev, const rti::SurrArgs *S, int mlp_blocks) {
     const int scan_blocks = std::min((a.max_chunks + rti::SCAN_BLOCK - 1) / rti::SCAN_BLOCK, 1024);
     const int scatter_blocks = std::max(1, std::min((a.max_chunks + 3) / 4, 4096));
     {
@@ -704,13 +789,20 @@ hipError_t launch_kind_step(const TraceArgs &a, const rti::DeviceData &d, int n_
             hipLaunchKernelGGL(k_scatter, dim3(scatter_blocks), dim3(256), 0, s, a, p - 1);
             if (ev) (void)hipEventRecord(ev[2 * n_passes + 2 + p], s);
         }
-        if (a.count)
-            hipLaunchKernelGGL((k_trace_pass<KIND, STEP, true>), dim3(grid), dim3(256), 0, s, a, p, d.bump_f, d.sph_f,
-                               d.pln_f, d.tor_f);
-        else
-            hipLaunchKernelGGL((k_trace_pass<KIND, STEP, false>), dim3(grid), dim3(256), 0, s, a, p, d.bump_f,
-                               d.sph_f, d.pln_f, d.tor_f);
-        hipError_t e = hipGetLastError();
+        hipError_t e;
+        if constexpr (KIND == KIND_GRAPH && STEP == STEP_RK4) {
+            if (a.surr) {
+                e = launch_pass<KIND, STEP, true>(a, d, p, grid, s);
+                if (e != hipSuccess) return e;
+                if (ev) (void)hipEventRecord(ev[2 + p], s);
+                // crossings parked in pass p (not timed as a pass)
+                e = rti::launch_surr_stage(a, *S, d.bump_f, p, mlp_blocks, s);
+                if (e != hipSuccess) return e;
+                if (ev) (void)hipEventRecord(ev[3 * n_passes + 3 + p], s);
+                continue;
+            }
+        }
+        e = launch_pass<KIND, STEP, false>(a, d, p, grid, s);
         if (e != hipSuccess) return e;
         if (ev) (void)hipEventRecord(ev[2 + p], s);
     }
@@ -752,8 +844,8 @@ int trace_blocks_per_cu(int kind, int step) {
 }
 
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid, int rgrid, hipStream_t s,
-                        hipEvent_t *ev) {
-    int words = CTR_PASS0 + n_passes * CTR_PASS_WORDS;
+                        hipEvent_t *ev, const SurrArgs *S, int mlp_blocks) {
+    int words = CTR_PASS0 + n_passes * CTR_PASS_WORDS + CTR_SURR_WORDS;
     if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_reset, dim3(64), dim3(256), 0, s, a.ctr, words, a.stats);
     hipError_t e = hipGetLastError();
@@ -761,10 +853,10 @@ hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, i
     if (ev) (void)hipEventRecord(ev[1], s);
     const int step = a.step_kind;
     switch (a.kind) {
-    case KIND_EUCLID: RT_DISPATCH(KIND_EUCLID, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev)
-    case KIND_GRAPH: RT_DISPATCH(KIND_GRAPH, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev)
-    case KIND_TWIST: RT_DISPATCH(KIND_TWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev)
-    default: RT_DISPATCH(KIND_ZTWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev)
+    case KIND_EUCLID: RT_DISPATCH(KIND_EUCLID, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    case KIND_GRAPH: RT_DISPATCH(KIND_GRAPH, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    case KIND_TWIST: RT_DISPATCH(KIND_TWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    default: RT_DISPATCH(KIND_ZTWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     }
 }
 

@@ -23,11 +23,13 @@ _lib = C.CDLL(LIB_PATH)
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED, RT_ESTATE = 0, -1, -2, -3, -4, -5
 EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST = 0, 1, 2, 3
 RK4, RK45, EULER = 0, 1, 2
-FLAG_TIMING, FLAG_COUNT_WORK = 1, 2
+FLAG_TIMING, FLAG_COUNT_WORK, FLAG_SURROGATE = 1, 2, 4
 
 EXPORTS = ["rt_abi_version", "rt_create", "rt_destroy", "rt_last_error", "rt_set_metric", "rt_set_scene",
            "rt_trace", "rt_sync", "rt_get_stats", "rt_tape_bytes", "rt_trace_fwd_ckpt", "rt_loss_l2",
-           "rt_trace_bwd"]
+           "rt_trace_bwd", "rt_mlp_work_bytes", "rt_mlp_fwd", "rt_mlp_fwd_grouped", "rt_mlp_bwd", "rt_mse_grad", "rt_adamw_step",
+           "rt_surrogate_gen", "rt_surrogate_calibrate", "rt_surrogate_load"]
+MLP_PARAMS = 134918
 
 
 class RtError(RuntimeError):
@@ -71,7 +73,8 @@ class rt_stats(C.Structure):
                 ("wave_iters", C.c_uint64), ("lane_iters", C.c_uint64), ("bump_list_sum", C.c_uint64),
                 ("obj_list_sum", C.c_uint64), ("refined", C.c_uint64), ("acc_evals", C.c_uint64),
                 ("bump_evals", C.c_uint64), ("obj_tests", C.c_uint64), ("passes", C.c_int), ("pass_ms", C.c_float),
-                ("refine_ms", C.c_float), ("compact_ms", C.c_float), ("total_ms", C.c_float)]
+                ("refine_ms", C.c_float), ("compact_ms", C.c_float), ("total_ms", C.c_float),
+                ("crossings", C.c_uint64), ("accepted", C.c_uint64), ("surr_ms", C.c_float)]
 
 
 _P = C.c_void_p
@@ -101,6 +104,25 @@ _lib.rt_loss_l2.argtypes = [_P, C.POINTER(rt_camera), _P, _P, _P, _P, _P, _P, _P
 _lib.rt_loss_l2.restype = C.c_int
 _lib.rt_trace_bwd.argtypes = [_P, _P, _P, _P, _P]
 _lib.rt_trace_bwd.restype = C.c_int
+_lib.rt_mlp_work_bytes.argtypes = [C.c_int, C.c_int]
+_lib.rt_mlp_work_bytes.restype = C.c_size_t
+_lib.rt_mlp_fwd.argtypes = [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, C.c_size_t, _P]
+_lib.rt_mlp_fwd.restype = C.c_int
+_lib.rt_mlp_bwd.argtypes = [_P, C.c_int, C.c_int, _P, _P, _P, _P, C.c_size_t, _P]
+_lib.rt_mlp_bwd.restype = C.c_int
+_lib.rt_adamw_step.argtypes = [_P, _P, _P, _P, _P, _P, C.c_size_t, C.c_float, C.c_float, C.c_float, C.c_float,
+                               C.c_float, C.c_int, _P]
+_lib.rt_adamw_step.restype = C.c_int
+_lib.rt_mse_grad.argtypes = [_P, _P, _P, _P, C.c_size_t, C.c_int, _P, _P]
+_lib.rt_mse_grad.restype = C.c_int
+_lib.rt_surrogate_gen.argtypes = [_P, C.c_int, _P, _P, C.c_int, C.c_float, C.c_int, C.c_uint64, _P, _P, _P, _P]
+_lib.rt_surrogate_gen.restype = C.c_int
+_lib.rt_mlp_fwd_grouped.argtypes = [_P, C.c_int, _P, _P, _P, _P, _P, _P]
+_lib.rt_mlp_fwd_grouped.restype = C.c_int
+_lib.rt_surrogate_calibrate.argtypes = [_P, C.c_int, C.c_int, _P, _P, _P, _P, C.c_int, _P, _P]
+_lib.rt_surrogate_calibrate.restype = C.c_int
+_lib.rt_surrogate_load.argtypes = [_P, C.c_int, _P, _P, _P, _P, C.c_int, _P, C.c_int, _P, C.c_int, C.c_float]
+_lib.rt_surrogate_load.restype = C.c_int
 
 
 def lib():
@@ -262,6 +284,115 @@ class Tracer:
         self._check(_lib.rt_trace_bwd(self._h, C.c_void_p(tape.data_ptr()), C.c_void_p(gh.data_ptr()),
                                       C.c_void_p(g.data_ptr()), C.c_void_p(stream.cuda_stream)))
         return g
+
+    # ---- surrogate MLP (BF16 matrix cores)
+    def mlp_work(self, n_nets, batch):
+        import torch
+        nb = int(_lib.rt_mlp_work_bytes(int(n_nets), int(batch)))
+        return torch.empty(nb // 4 + 64, dtype=torch.float32, device=torch.device("cuda", self.device))
+
+    def mlp_fwd(self, w_bf16, params, x, work):
+        """x [n_nets, batch, 6] float32 cuda -> y [n_nets, batch, 6]."""
+        import torch
+        n, b = x.shape[0], x.shape[1]
+        y = torch.empty((n, b, 6), dtype=torch.float32, device=x.device)
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_mlp_fwd(self._h, n, b, C.c_void_p(w_bf16.data_ptr()), C.c_void_p(params.data_ptr()),
+                                    C.c_void_p(x.contiguous().data_ptr()), C.c_void_p(y.data_ptr()),
+                                    C.c_void_p(work.data_ptr()), C.c_size_t(work.numel() * 4),
+                                    C.c_void_p(st.cuda_stream)))
+        return y
+
+    def mlp_fwd_grouped(self, w_bf16, params, x, rows):
+        """x [sum(rows), 6] float32 cuda, rows per network -> y [sum(rows), 6]."""
+        import torch
+        r = np.ascontiguousarray(rows, np.int32)
+        x = x.contiguous()
+        y = torch.empty_like(x)
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_mlp_fwd_grouped(self._h, int(len(r)), r.ctypes.data, C.c_void_p(w_bf16.data_ptr()),
+                                            C.c_void_p(params.data_ptr()), C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(y.data_ptr()), C.c_void_p(st.cuda_stream)))
+        return y
+
+    def mlp_bwd(self, w_bf16, dy, work):
+        import torch
+        n, b = dy.shape[0], dy.shape[1]
+        g = torch.empty((n, MLP_PARAMS), dtype=torch.float32, device=dy.device)
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_mlp_bwd(self._h, n, b, C.c_void_p(w_bf16.data_ptr()),
+                                    C.c_void_p(dy.contiguous().data_ptr()), C.c_void_p(g.data_ptr()),
+                                    C.c_void_p(work.data_ptr()), C.c_size_t(work.numel() * 4),
+                                    C.c_void_p(st.cuda_stream)))
+        return g
+
+    def mse_grad(self, y, t, batch):
+        """dy = 2 (y - t) / batch; returns (dy, 64 partial sums of squares)."""
+        import torch
+        dy = torch.empty_like(y)
+        part = torch.empty(64, dtype=torch.float32, device=y.device)
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_mse_grad(self._h, C.c_void_p(y.data_ptr()), C.c_void_p(t.contiguous().data_ptr()),
+                                     C.c_void_p(dy.data_ptr()), C.c_size_t(y.numel()), int(batch),
+                                     C.c_void_p(part.data_ptr()), C.c_void_p(st.cuda_stream)))
+        return dy, part
+
+    def adamw(self, params, w_bf16, m, v, grad, lr, step, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+        import torch
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_adamw_step(self._h, C.c_void_p(params.data_ptr()), C.c_void_p(w_bf16.data_ptr()),
+                                       C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()),
+                                       C.c_void_p(grad.data_ptr()), C.c_size_t(params.numel()), float(lr),
+                                       float(b1), float(b2), float(eps), float(wd), int(step),
+                                       C.c_void_p(st.cuda_stream)))
+
+    def surrogate_gen(self, kappa, scale, n_per, h, grid=False, seed=0):
+        """Crossing data for each shape kappa (random or cos-theta grid
+        entries): returns x, y [n,n_per,6], aux [n,n_per,4]."""
+        import torch
+        k = np.ascontiguousarray(kappa, np.float32)
+        sc = np.ascontiguousarray(scale, np.float32)
+        n = len(k)
+        dev = torch.device("cuda", self.device)
+        x = torch.empty((n, n_per, 6), dtype=torch.float32, device=dev)
+        y = torch.empty((n, n_per, 6), dtype=torch.float32, device=dev)
+        aux = torch.empty((n, n_per, 4), dtype=torch.float32, device=dev)
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_surrogate_gen(self._h, n, k.ctypes.data, sc.ctypes.data, int(n_per), float(h),
+                                          1 if grid else 0, int(seed), C.c_void_p(x.data_ptr()),
+                                          C.c_void_p(y.data_ptr()), C.c_void_p(aux.data_ptr()),
+                                          C.c_void_p(st.cuda_stream)))
+        return x, y, aux
+
+    def surrogate_calibrate(self, x, pred, target, scale, n_bins):
+        """Per-bin decoded error maxima [n, n_bins, 2] of pred against target."""
+        import torch
+        n, n_per = x.shape[0], x.shape[1]
+        sc = np.ascontiguousarray(scale, np.float32)
+        err = torch.empty((n, n_bins, 2), dtype=torch.float32, device=x.device)
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_surrogate_calibrate(self._h, int(n), int(n_per), C.c_void_p(x.data_ptr()),
+                                                C.c_void_p(pred.data_ptr()), C.c_void_p(target.data_ptr()),
+                                                sc.ctypes.data, int(n_bins), C.c_void_p(err.data_ptr()),
+                                                C.c_void_p(st.cuda_stream)))
+        return err
+
+    def surrogate_load(self, w_bf16, params, scale, arc, err, net_of_bump, tol=1e-3):
+        """Copy trained networks and their tables into the tracer."""
+        import torch
+        self.sync()
+        n = int(params.shape[0])
+        sc = np.ascontiguousarray(scale, np.float32)
+        nob = np.ascontiguousarray(net_of_bump, np.int32)
+        arc = arc.contiguous()
+        err = err.contiguous()
+        self._check(_lib.rt_surrogate_load(self._h, n, C.c_void_p(w_bf16.data_ptr()), C.c_void_p(params.data_ptr()),
+                                           sc.ctypes.data, C.c_void_p(arc.data_ptr()), int(arc.shape[1]),
+                                           C.c_void_p(err.data_ptr()), int(err.shape[1]), nob.ctypes.data,
+                                           int(len(nob)), float(tol)))
+
+    def surrogate_unload(self):
+        self._check(_lib.rt_surrogate_load(self._h, 0, None, None, None, None, 2, None, 1, None, 0, 1.0))
 
     def sync(self, stream=None):
         import torch

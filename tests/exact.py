@@ -299,3 +299,37 @@ class SingleBumpRay:
         r = self.b * np.cosh(self.tau[k])
         phi = self.phi[k]
         return self.c + r * (np.cos(phi) * self.e1 + np.sin(phi) * self.e2)
+
+
+def crossing_exact(kappa, c):
+    """Exact crossing of the support sphere (radius 3) of the canonical bump
+    F(r) = kappa exp(-r^2/2) (sigma = 1), entered at (3, 0, 0) with Euclidean
+    direction (-c, s, 0), s = sqrt(1 - c^2).  Returns the swept polar angle of
+    the exit point and the g-length of the arc inside the sphere.
+
+    Rotation invariance keeps J = |x x x'| constant and g(x', x') = 1 gives
+    r'^2 (1 + F'^2) + J^2 / r^2 = 1; with r = J cosh(u) the swept angle is
+    2 int_0^u1 sqrt(1 + F'^2) / cosh(u) du and the length
+    2 int_0^u1 r sqrt(1 + F'^2) du, with J cosh(u1) = 3.  At the entry the
+    g-unit speed has Euclidean size v = 1 / sqrt(1 + F'(3)^2 c^2), so
+    J = 3 v s."""
+    kappa = abs(float(kappa))
+    c = float(c)
+    s = np.sqrt(max(0.0, 1.0 - c * c))
+
+    def Fp(r):
+        return -kappa * r * np.exp(-0.5 * r * r)
+
+    if s < 1e-12:      # head-on: straight through the centre
+        edges = np.linspace(0.0, 3.0, 257)
+        half = float(np.sum(_gl(lambda r: np.sqrt(1.0 + Fp(r) ** 2), edges[:-1], edges[1:])))
+        return np.pi, 2.0 * half
+    v = 1.0 / np.sqrt(1.0 + (Fp(3.0) * c) ** 2)
+    J = 3.0 * v * s
+    u1 = np.arccosh(3.0 / J) if J < 3.0 else 0.0
+    if u1 == 0.0:
+        return 0.0, 0.0
+    edges = np.linspace(0.0, u1, 513)
+    dphi = _gl(lambda u: np.sqrt(1.0 + Fp(J * np.cosh(u)) ** 2) / np.cosh(u), edges[:-1], edges[1:])
+    dt = _gl(lambda u: J * np.cosh(u) * np.sqrt(1.0 + Fp(J * np.cosh(u)) ** 2), edges[:-1], edges[1:])
+    return 2.0 * float(np.sum(dphi)), 2.0 * float(np.sum(dt))

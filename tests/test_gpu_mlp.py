@@ -1,0 +1,94 @@
+"""GPU BF16-MFMA MLP kernels against the FP64 oracle MLP (which emulates
+the same bfloat16 rounding points)."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_05386_amd import rt
+    return rt, torch, rt.Tracer(0)
+
+
+def _params(torch, n, scale=1.0):
+    p = np.stack([mlp.init_params(10 + i) for i in range(n)]) * scale
+    rng = np.random.default_rng(1)
+    for i in range(n):   # non-zero biases
+        for k, (o, _) in zip(range(4), mlp.SIZES):
+            mlp.split(p[i])[2 * k + 1][:] = rng.normal(0, 0.1, size=o)
+    pt = torch.tensor(p, dtype=torch.float32, device="cuda")
+    return p, pt, pt.to(torch.bfloat16)
+
+
+@pytest.mark.parametrize("n,batch", [(3, 37), (2, 300), (1, 1)])
+def test_mlp_forward_backward_match_oracle(env, n, batch):
+    rt, torch, tr = env
+    say("mlp fwd/bwd n_nets=%d batch=%d" % (n, batch))
+    p, pt, pb = _params(torch, n)
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(n, batch, 6)).astype(np.float32)
+    dy = rng.normal(size=(n, batch, 6)).astype(np.float32)
+    work = tr.mlp_work(n, batch)
+    y = tr.mlp_fwd(pb, pt, torch.tensor(x, device="cuda"), work).cpu().numpy()
+    g = tr.mlp_bwd(pb, torch.tensor(dy, device="cuda"), work).cpu().numpy()
+    p32 = p.astype(np.float32).astype(np.float64)
+    for i in range(n):
+        yr, _ = mlp.forward(p32[i], x[i].astype(np.float64), bf16=True)
+        assert np.abs(y[i] - yr).max() <= 2e-3 * max(1.0, np.abs(yr).max()), (i, np.abs(y[i] - yr).max())
+        gr = mlp.backward(p32[i], x[i].astype(np.float64), dy[i].astype(np.float64), bf16=True)
+        for blk, (a, b) in enumerate(zip(mlp.split(g[i].astype(np.float64)), mlp.split(gr))):
+            err = np.abs(a - b).max()
+            assert err <= 1e-2 * max(1e-3, np.abs(b).max()), (i, blk, err, np.abs(b).max())
+
+
+def test_adamw_step(env):
+    rt, torch, tr = env
+    say("adamw")
+    rng = np.random.default_rng(3)
+    n = 1000
+    p = rng.normal(size=n).astype(np.float32)
+    m = rng.normal(size=n).astype(np.float32) * 0.1
+    v = np.abs(rng.normal(size=n)).astype(np.float32) * 0.01
+    g = rng.normal(size=n).astype(np.float32)
+    P, M, V, G = (torch.tensor(a, device="cuda") for a in (p, m, v, g))
+    PB = P.to(torch.bfloat16)
+    lr, b1, b2, eps, wd, step = 1e-3, 0.9, 0.999, 1e-8, 0.01, 7
+    tr.adamw(P, PB, M, V, G, lr, step, b1, b2, eps, wd)
+    m2 = b1 * m + (1 - b1) * g
+    v2 = b2 * v + (1 - b2) * g * g
+    p2 = p - lr * ((m2 / (1 - b1 ** step)) / (np.sqrt(v2 / (1 - b2 ** step)) + eps) + wd * p)
+    assert np.allclose(P.cpu().numpy(), p2, rtol=1e-5, atol=1e-6)
+    assert np.allclose(PB.float().cpu().numpy(), p2, rtol=1e-2, atol=1e-3)
+
+
+def test_training_reduces_loss(env):
+    rt, torch, tr = env
+    say("mlp training on a smooth 6->6 map")
+    n, batch = 2, 512
+    p, pt, pb = _params(torch, n, scale=0.5)
+    rng = np.random.default_rng(4)
+    x = torch.tensor(rng.uniform(-1, 1, size=(n, batch, 6)), dtype=torch.float32, device="cuda")
+    t = torch.sin(2.0 * x) * 0.5 + x.roll(1, dims=2) * 0.3
+    m = torch.zeros_like(pt)
+    v = torch.zeros_like(pt)
+    work = tr.mlp_work(n, batch)
+    losses = []
+    for step in range(1, 301):
+        y = tr.mlp_fwd(pb, pt, x, work)
+        diff = y - t
+        losses.append(float((diff * diff).sum() / (n * batch)))
+        g = tr.mlp_bwd(pb, 2.0 * diff / batch, work)
+        tr.adamw(pt, pb, m, v, g, 2e-3, step)
+    say("loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.05 * losses[0]

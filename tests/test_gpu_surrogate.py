@@ -1,0 +1,204 @@
+"""Learned crossing surrogate on the GPU: training data against the exact
+crossing, the fused grouped MLP forward against the FP64 oracle MLP, the
+calibration kernel, eligibility, and surrogate traces against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import mlp
+from tests import exact
+from tests.parity import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_05386_amd import rt, surrogate
+    return rt, surrogate, torch, rt.Tracer(0)
+
+
+@pytest.mark.parametrize("kappa", [0.3, 1.2, 3.0])
+def test_crossing_data_matches_exact(env, kappa):
+    """Labels of the data generator (RK4, h = 0.01 in units of sigma) against
+    the quadrature of the exact crossing: exit point, exit direction (at
+    polar angle swept + th), arc length."""
+    rt, surrogate, torch, tr = env
+    say("crossing data kappa=%g" % kappa)
+    n = 65
+    x, y, aux = tr.surrogate_gen([kappa], [1.0], n, 0.01, grid=True)
+    x, y, aux = (a.cpu().numpy()[0].astype(np.float64) for a in (x, y, aux))
+    for i in range(n):
+        c = i / (n - 1)
+        assert abs(-x[i, 3] - c) < 1e-6
+        dphi, arc = exact.crossing_exact(kappa, c)
+        s = np.sqrt(1 - c * c)
+        th = np.arctan2(s, c)
+        u = np.array([-(c * c - s * s), 2 * s * c, 0.0]) + y[i, :3]
+        w = np.array([-c, s, 0.0]) + y[i, 3:]
+        assert abs(np.linalg.norm(u) - 1) < 2e-6, (i, u)
+        assert abs(u[2]) < 1e-6 and abs(w[2]) < 1e-6
+        if c > 0.0:
+            assert abs(np.arctan2(u[1], u[0]) % (2 * np.pi) - dphi) < 2e-5, (i, np.arctan2(u[1], u[0]), dphi)
+            ang = np.arctan2(w[1], w[0]) - (dphi + th)
+            assert abs((ang + np.pi) % (2 * np.pi) - np.pi) < 4e-5, (i, ang)
+        assert abs(aux[i, 1] - arc) < 2e-4, (i, aux[i, 1], arc)
+        assert abs(aux[i, 0] - 3 * s) < 1e-5
+
+
+def test_crossing_data_random_mode(env):
+    rt, surrogate, torch, tr = env
+    say("crossing data random mode")
+    x, y, aux = tr.surrogate_gen([0.5, 2.0], [1.0, 1.0], 4096, 0.02, grid=False, seed=7)
+    x2, _, _ = tr.surrogate_gen([0.5, 2.0], [1.0, 1.0], 4096, 0.02, grid=False, seed=7)
+    x3, _, _ = tr.surrogate_gen([0.5, 2.0], [1.0, 1.0], 4096, 0.02, grid=False, seed=8)
+    x, aux = x.cpu().numpy(), aux.cpu().numpy()
+    assert np.array_equal(x, x2.cpu().numpy())           # counter-based: reproducible
+    assert not np.array_equal(x, x3.cpu().numpy())
+    s2 = x[..., 4].astype(np.float64) ** 2                 # sin^2 th uniform on [0, 1)
+    assert abs(s2.mean() - 0.5) < 0.02 and s2.min() >= 0 and s2.max() < 1
+    assert np.all(aux[..., 1] >= 0)                        # every ray left the sphere
+
+
+def _nets(torch, n, seed=10):
+    p = np.stack([mlp.init_params(seed + i) for i in range(n)])
+    rng = np.random.default_rng(seed)
+    for i in range(n):
+        for k, (o, _) in zip(range(4), mlp.SIZES):
+            mlp.split(p[i])[2 * k + 1][:] = rng.normal(0, 0.1, size=o)
+    pt = torch.tensor(p, dtype=torch.float32, device="cuda")
+    return p.astype(np.float32).astype(np.float64), pt, pt.to(torch.bfloat16)
+
+
+@pytest.mark.parametrize("rows", [[37, 0, 130], [1], [64, 64], [200, 3, 0, 65]])
+def test_grouped_forward_matches_oracle(env, rows):
+    rt, surrogate, torch, tr = env
+    say("grouped forward rows=%s" % rows)
+    n = len(rows)
+    p, pt, pb = _nets(torch, n)
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(sum(rows), 6)).astype(np.float32)
+    y = tr.mlp_fwd_grouped(pb, pt, torch.tensor(x, device="cuda"), rows).cpu().numpy()
+    off = 0
+    for g, r in enumerate(rows):
+        if r == 0:
+            continue
+        yr, _ = mlp.forward(p[g], x[off:off + r].astype(np.float64), bf16=True)
+        err = np.abs(y[off:off + r] - yr).max()
+        assert err <= 2e-3 * max(1.0, np.abs(yr).max()), (g, err)
+        off += r
+    # same rounding points as the training forward
+    if len(set(r for r in rows if r)) == 1 and all(rows):
+        B = rows[0]
+        work = tr.mlp_work(n, B)
+        yl = tr.mlp_fwd(pb, pt, torch.tensor(x.reshape(n, B, 6), device="cuda"), work).cpu().numpy()
+        assert np.abs(yl.reshape(-1, 6) - y).max() <= 1e-4 * max(1.0, np.abs(yl).max())
+
+
+def test_calibration_is_the_decoded_maximum(env):
+    rt, surrogate, torch, tr = env
+    say("calibration")
+    n_per, n_bins = 2000, 16
+    x, y, _ = tr.surrogate_gen([0.7, 1.9], [0.05, 0.2], n_per, 0.02, grid=False, seed=3)
+    rng = np.random.default_rng(5)
+    noise = rng.normal(0, 0.01, size=tuple(y.shape)).astype(np.float32)
+    pred = y + torch.tensor(noise, device="cuda")
+    err = tr.surrogate_calibrate(x, pred, y, [0.05, 0.2], n_bins).cpu().numpy()
+    X, Y, P = (a.cpu().numpy().astype(np.float64) for a in (x, y, pred))
+    want = np.zeros((2, n_bins, 2))
+    for sh, sc in enumerate([0.05, 0.2]):
+        c, s = -X[sh, :, 3], X[sh, :, 4]
+        uc = np.stack([-(c * c - s * s), 2 * s * c, 0 * c], 1)
+        vin = np.stack([-c, s, 0 * c], 1)
+        up, ut = uc + sc * P[sh, :, :3], uc + sc * Y[sh, :, :3]
+        wp, wt = vin + sc * P[sh, :, 3:], vin + sc * Y[sh, :, 3:]
+        wp /= np.linalg.norm(wp, axis=1, keepdims=True)
+        wt /= np.linalg.norm(wt, axis=1, keepdims=True)
+        ep = np.linalg.norm(up - ut, axis=1)
+        ed = np.linalg.norm(wp - wt, axis=1)
+        b = np.minimum((c * n_bins).astype(int), n_bins - 1)
+        for k in range(n_bins):
+            if np.any(b == k):
+                want[sh, k] = [ep[b == k].max(), ed[b == k].max()]
+    assert np.allclose(err, want, rtol=1e-4, atol=1e-7)
+
+
+# ---------------------------------------------------------------- traces
+def _scene_three_bumps(width=96, height=64):
+    """Three isolated bumps in view (kappa 0.4, 1.0, 1.6), a sphere and the
+    plane y = -1 outside their support spheres, and one bump whose support
+    the plane cuts (not eligible)."""
+    bumps = [[0.06, -1.5, 0.5, 1.5, 0.15],
+             [-0.15, 0.0, 0.2, 1.5, 0.15],
+             [0.32, 1.7, 0.5, 2.2, 0.2],
+             [0.2, 0.3, -1.2, 3.0, 0.2]]
+    return dict(camera=W.camera(width, height, vfov_deg=40.0),
+                metric=W.metric(W.GRAPH_GAUSS, [bumps]),
+                scene=W.scene(spheres=[[0.0, 1.6, 5.0, 0.6]], planes=W.PLANE_Y_MINUS_1),
+                rule=W.rule(W.RK4, h=0.005, max_steps=2400, t_max=12.0, pass_steps=64))
+
+
+@pytest.fixture(scope="module")
+def trained(env):
+    rt, surrogate, torch, tr = env
+    wl = _scene_three_bumps()
+    kappa, net = surrogate.shapes_of(wl["metric"]["bumps"][0])
+    say("training %d networks" % len(kappa))
+    model = surrogate.train(tr, kappa, samples=1_500_000, batch=1024, h=0.01, seed=1, log=say)
+    say("trained in %.1f s, loss %s" % (model.train_s, model.losses[-1]))
+    return wl, model, net
+
+
+def _trace(rt, tr, wl, flags=0):
+    rule = dict(wl["rule"])
+    rule["flags"] = flags
+    out = tr.trace(wl["camera"], rule)
+    tr.sync()
+    return rt.to_numpy(out), tr.stats()
+
+
+def test_eligibility_and_flag_off_are_exact(env, trained):
+    """Without the flag the trace is the plain one; with it, rays that never
+    park (ineligible bumps only) are bit-identical to the plain trace."""
+    rt, surrogate, torch, tr = env
+    wl, model, net = trained
+    say("eligibility")
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    surrogate.load(tr, model, net, tol=1e-3)
+    plain, _ = _trace(rt, tr, wl, 0)
+    nob = np.array(net)
+    nob[:3] = -1    # only the plane-cut bump keeps a network: nothing eligible
+    tr.surrogate_load(model.w_bf16, model.params, model.scale, model.arc, model.err, nob, 1e-3)
+    surr, st = _trace(rt, tr, wl, rt.FLAG_SURROGATE)
+    assert st["crossings"] == 0
+    for k in ("hit", "t", "id", "dir"):
+        assert np.array_equal(plain[k], surr[k]), k
+
+
+def test_surrogate_trace_matches_oracle(env, trained):
+    rt, surrogate, torch, tr = env
+    wl, model, net = trained
+    say("surrogate trace 96x64 vs oracle")
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    surrogate.load(tr, model, net, tol=1e-3)
+    out, st = _trace(rt, tr, wl, rt.FLAG_SURROGATE | rt.FLAG_TIMING)
+    say("crossings %d accepted %d" % (st["crossings"], st["accepted"]))
+    assert st["crossings"] > 100
+    assert st["accepted"] > 0
+    ref = oracle.Oracle(wl["metric"], wl["scene"]).trace(wl["camera"], wl["rule"])
+    rep = compare(out, ref)
+    say(rep)
+    assert_parity(rep)
+    plain, st0 = _trace(rt, tr, wl, 0)
+    say("ray steps plain %d surrogate %d" % (st0["ray_steps"], st["ray_steps"]))
+    assert st["ray_steps"] < st0["ray_steps"]

@@ -30,6 +30,12 @@ Workloads (sizes are the ones the throughput and parity runs use):
   adjoint_64x512      64 parameter sets x 8 bumps, 512x512, RK4 h=0.01,
                       2000 steps, scene of single_bump_64
   surrogate_64_4k     3840x2160, 64 random bumps, scene of bumps16_1080p
+  surrogate_isolated_4k
+                      3840x2160, 64 bumps with the distributions of
+                      surrogate_64_4k but centres in [-8,8]^3 drawn by
+                      rejection so that no bump's 6-sigma cut sphere reaches
+                      another's 3-sigma support sphere (seed 3), 64 spheres
+                      (seed 4) kept outside every support, plane y=-1, torus
 """
 from __future__ import annotations
 
@@ -67,6 +73,45 @@ def random_bumps(n, seed, box=2.0, amp=0.6, sigma=(0.15, 0.5)):
     a = rng.uniform(-amp, amp, size=n)
     s = rng.uniform(sigma[0], sigma[1], size=n)
     return f32(np.concatenate([a[:, None], c, s[:, None]], axis=1))
+
+
+def isolated_bumps(n, seed, box=8.0, amp=0.6, sigma=(0.15, 0.5), gap=0.1):
+    """Amplitudes U(-amp,amp), then sigmas U(sigma), then centres
+    U[-box,box]^3 redrawn until |c_i - c_j| >= max(3 s_i + 6 s_j,
+    3 s_j + 6 s_i) + gap for every earlier bump j."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-amp, amp, size=n)
+    s = rng.uniform(sigma[0], sigma[1], size=n)
+    c = np.zeros((n, 3))
+    for i in range(n):
+        for _ in range(100000):
+            p = rng.uniform(-box, box, size=3)
+            d = np.linalg.norm(c[:i] - p, axis=1)
+            need = np.maximum(3 * s[i] + 6 * s[:i], 3 * s[:i] + 6 * s[i]) + gap
+            if np.all(d >= need):
+                break
+        else:
+            raise RuntimeError("isolated_bumps: could not place bump %d" % i)
+        c[i] = p
+    return f32(np.concatenate([a[:, None], c, s[:, None]], axis=1))
+
+
+def spheres_outside(n, seed, bumps, box=2.0, radius=(0.1, 0.4), gap=0.05):
+    """Radii U(radius), then centres U[-box,box]^3 redrawn until the sphere
+    stays outside every bump's 3-sigma support sphere."""
+    rng = np.random.default_rng(seed)
+    b = np.asarray(bumps, np.float64).reshape(-1, 5)
+    r = rng.uniform(radius[0], radius[1], size=n)
+    c = np.zeros((n, 3))
+    for i in range(n):
+        for _ in range(100000):
+            p = rng.uniform(-box, box, size=3)
+            if np.all(np.linalg.norm(b[:, 1:4] - p, axis=1) >= 3 * b[:, 4] + r[i] + gap):
+                break
+        else:
+            raise RuntimeError("spheres_outside: could not place sphere %d" % i)
+        c[i] = p
+    return f32(np.concatenate([c, r[:, None]], axis=1))
 
 
 def random_spheres(n, seed, box=2.0, radius=(0.1, 0.4)):
@@ -184,6 +229,15 @@ def surrogate_64_4k(width=3840, height=2160):
                 rule=rule(RK4, h=0.005, max_steps=4000, t_max=20.0))
 
 
+def surrogate_isolated_4k(width=3840, height=2160):
+    bumps = isolated_bumps(64, seed=3)
+    return dict(name="surrogate_isolated_4k", camera=camera(width, height),
+                metric=metric(GRAPH_GAUSS, bumps),
+                scene=scene(spheres=spheres_outside(64, seed=4, bumps=bumps),
+                            planes=PLANE_Y_MINUS_1, tori=TORUS_Z),
+                rule=rule(RK4, h=0.005, max_steps=4000, t_max=20.0))
+
+
 WORKLOADS = {
     "single_bump_64": single_bump_64,
     "bumps16_1080p": bumps16_1080p,
@@ -191,6 +245,7 @@ WORKLOADS = {
     "twist_4k": twist_4k,
     "adjoint_64x512": adjoint_64x512,
     "surrogate_64_4k": surrogate_64_4k,
+    "surrogate_isolated_4k": surrogate_isolated_4k,
 }
 
 
