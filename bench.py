@@ -41,6 +41,54 @@ FLOPS = {
 }
 
 
+KERNEL_SOURCES = ["paper_2005_05386_amd/csrc/rt_trace.hip", "paper_2005_05386_amd/csrc/rt_device.hpp",
+                  "paper_2005_05386_amd/csrc/rt_step.hpp", "paper_2005_05386_amd/csrc/rt_internal.hpp"]
+
+
+def kernel_source_digest():
+    """SHA-256 over the sources the pass kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per pass-kernel launch from the committed PMC summary of
+    this workload, or None when there is none or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_trace_pass_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ":" in ln and ln.startswith("- "):
+                k, v = ln[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(nbytes, reps=4):
+    """Plain device-to-device copies of a known size (calibration of the
+    FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def algorithmic_flops(kind, step, st):
     ev = st["acc_evals"]
     if kind == 1:
@@ -135,6 +183,117 @@ def bench_adjoint(args, wl, torch, rt):
     print(json.dumps(line), flush=True)
 
 
+def _frame_error(out, ref, tol=1e-3):
+    """Pixels whose object id differs from the reference frame or whose hit
+    point is off by more than tol (any coordinate); hit-error quantiles over
+    pixels with the same id."""
+    import numpy as np
+    same = out["id"] == ref["id"]
+    err = np.abs(out["hit"] - ref["hit"]).max(axis=1)
+    bad = (~same) | (err > tol)
+    e = err[same]
+    return {"frac_within_tol": float(1.0 - bad.mean()), "frac_id_equal": float(same.mean()),
+            "p999_hit_err": float(np.quantile(e, 0.999)) if e.size else 0.0,
+            "max_hit_err": float(e.max()) if e.size else 0.0}
+
+
+def _timed_frames(tr, cam, rule, out, steps, torch):
+    """Mean wall time (ms) of `steps` traces between two stream events, and
+    the stats of the last one."""
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    agg = {"pass_ms": 0.0, "surr_ms": 0.0, "refine_ms": 0.0, "compact_ms": 0.0}
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        tr.trace_into(cam, dict(rule, flags=rule.get("flags", 0) | 1), rule["max_steps"], out)
+        st = tr.stats()
+        for k in agg:
+            agg[k] += st[k] / steps
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, st, agg
+
+
+def bench_surrogate(args, wl, torch, rt):
+    """Learned crossings against plain RK4 on the same frame: train one
+    network per bump shape, time the RK4-only frame (the judge) and the
+    surrogate frame, measure acceptance and hit error against the RK4 frame,
+    and find the largest RK4 step whose error is no larger (equal-error
+    comparison)."""
+    import numpy as np
+
+    from paper_2005_05386_amd import surrogate as S
+    cam, rule = wl["camera"], dict(wl["rule"], pass_steps=args.surr_pass_steps)
+    tr = rt.Tracer(0)
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    out = tr.alloc_outputs(cam)
+    n_rays = cam["width"] * cam["height"]
+    kappa, net = S.shapes_of(wl["metric"]["bumps"][0])
+    print("[bench] surrogate workload %s: %d shapes, training %d crossings each" % (
+        args.workload, len(kappa), args.surr_samples), flush=True)
+    model = S.train(tr, kappa, samples=args.surr_samples, batch=1024, h=0.01, seed=0,
+                    log=lambda m: print("[bench] " + m, flush=True))
+    # MLP FLOPs per training row: forward 2*(6*256 + 2*256^2 + 256*6), backward about twice that
+    fwd_flops = 2 * (6 * 256 + 2 * 256 * 256 + 256 * 6)
+    train_tflops = 3 * fwd_flops * model.samples * len(kappa) / model.train_s / 1e12
+    S.load(tr, model, net, tol=args.surr_tol)
+
+    for _ in range(args.warmup):
+        tr.trace_into(cam, rule, rule["max_steps"], out)
+    rk4_ms, rk4_st, rk4_k = _timed_frames(tr, cam, rule, out, args.steps, torch)
+    ref = rt.to_numpy(out)
+    srule = dict(rule, flags=rt.FLAG_SURROGATE)
+    for _ in range(args.warmup):
+        tr.trace_into(cam, srule, rule["max_steps"], out)
+    sur_ms, sur_st, sur_k = _timed_frames(tr, cam, srule, out, args.steps, torch)
+    sur = rt.to_numpy(out)
+    sur_err = _frame_error(sur, ref)
+    print("[bench] rk4 %.2f ms, surrogate %.2f ms, crossings %d accepted %d, %s" % (
+        rk4_ms, sur_ms, sur_st["crossings"], sur_st["accepted"], json.dumps(sur_err)), flush=True)
+
+    # equal error: the largest RK4 step (same t_max) whose frame is at least as close to the h = 0.005 frame
+    eq = []
+    for hh in (0.0075, 0.01, 0.015, 0.02, 0.03, 0.04):
+        r2 = dict(rule, h=float(np.float32(hh)), max_steps=int(round(rule["t_max"] / hh)))
+        tr.trace_into(cam, r2, r2["max_steps"], out)
+        ms2, st2, _ = _timed_frames(tr, cam, r2, out, max(1, args.steps // 2), torch)
+        e2 = _frame_error(rt.to_numpy(out), ref)
+        eq.append({"h": hh, "ms": ms2, **e2})
+        print("[bench] rk4 h=%g: %.2f ms %s" % (hh, ms2, json.dumps(e2)), flush=True)
+    ok = [e for e in eq if e["frac_within_tol"] >= sur_err["frac_within_tol"]]
+    best = max(ok, key=lambda e: e["h"]) if ok else None
+
+    mlp_flops = fwd_flops * sur_st["crossings"]
+    line = {
+        "metric": "surrogate vs RK4 at equal error (learned crossings, rays/s)",
+        "value": n_rays / (sur_ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sur_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"], "h": rule["h"],
+                   "max_steps": rule["max_steps"], "bumps": int(wl["metric"]["bumps"].shape[1]),
+                   "pass_steps": rule["pass_steps"], "probe_tol": args.surr_tol},
+        "rk4_ms_per_frame": rk4_ms, "rk4_rays_per_s": n_rays / (rk4_ms / 1e3),
+        "speedup_vs_rk4": rk4_ms / sur_ms,
+        "crossings": sur_st["crossings"], "accepted": sur_st["accepted"],
+        "acceptance": sur_st["accepted"] / max(1, sur_st["crossings"]),
+        "eligible_bumps": sur_st["eligible"],
+        "ray_steps": {"rk4": rk4_st["ray_steps"], "surrogate": sur_st["ray_steps"]},
+        "error_vs_rk4": sur_err,
+        "equal_error": {"rk4_h": best["h"] if best else None, "rk4_ms": best["ms"] if best else None,
+                        "speedup_surrogate_vs_equal_error_rk4": (best["ms"] / sur_ms) if best else None,
+                        "sweep": eq},
+        "kernel_ms": {"rk4": rk4_k, "surrogate": sur_k},
+        "mlp": {"inference_tflops_over_crossing_stages": mlp_flops / max(1e-9, sur_k["surr_ms"] / 1e3) / 1e12,
+                "bf16_peak_tflops": 2500.0, "training_s": model.train_s, "training_steps": model.steps,
+                "training_samples_per_shape": model.samples, "training_mlp_tflops": train_tflops,
+                "final_loss": model.losses[-1][1] if model.losses else None},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,7 +302,13 @@ def main():
     ap.add_argument("--workload", default="bumps16_1080p")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--surr-samples", type=int, default=10_000_000, help="training crossings per bump shape")
+    ap.add_argument("--surr-tol", type=float, default=1e-3, help="probe tolerance on the hit error")
+    ap.add_argument("--surr-pass-steps", type=int, default=64, help="steps per pass in surrogate traces")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run plain copies of this many bytes")
     args = ap.parse_args()
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); DESIGN.md describes how the trace "
               "would shard across GPUs, but no multi-GPU path is built", file=sys.stderr)
@@ -157,6 +322,8 @@ def main():
     wl = W.get(args.workload)
     if "ckpt_every" in wl:
         return bench_adjoint(args, wl, torch, rt)
+    if args.workload.startswith("surrogate"):
+        return bench_surrogate(args, wl, torch, rt)
     cam, rule = wl["camera"], dict(wl["rule"])
     tr = rt.Tracer(0)
     tr.set_metric(wl["metric"])
@@ -209,7 +376,7 @@ def main():
                    "spheres": int(len(wl["scene"]["spheres"]))},
         "ray_steps_per_s": work["ray_steps"] / (ms / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_trace_pass", "flops_per_trace": flops,
                      "kernel_ms_per_launch": pass_ms / max(1, n_pass_launches),
                      "frac_of_nonpacked_peak": achieved / FP32_PEAK_NONPACKED},

@@ -239,6 +239,7 @@ typedef struct rt_stats {
     uint64_t crossings;     /* SURROGATE: rays parked on an eligible support sphere */
     uint64_t accepted;      /* SURROGATE: crossings replaced by the network's prediction */
     float surr_ms;          /* SURROGATE + TIMING: summed duration of the crossing stages */
+    int eligible;           /* SURROGATE: bumps whose support sphere the networks may replace */
 } rt_stats;
 
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
@@ -289,13 +290,16 @@ rt_status rt_trace_bwd(rt_ctx *ctx, const void *tape, const float *grad_hit, flo
 
 /* ------------------------------------------------------------- surrogate
  * Learned crossing map of one bump's support sphere: an MLP
- * 6 -> 256 -> 256 -> 256 -> 6 with SiLU hidden activations, run on the BF16
- * matrix cores with FP32 accumulation.  Parameters of one network, in this
- * order (RT_MLP_PARAMS floats): W1[256][6], b1[256], W2[256][256], b2[256],
+ * 6 -> 256 -> 256 -> 256 -> 6 with SiLU hidden activations.  The two
+ * 256x256 products run on the BF16 matrix cores with FP32 accumulation
+ * (W2, W3 from a bf16 copy of the parameters, uint16 bit patterns in the
+ * same layout; their inputs h1, h2 rounded to bf16); the first layer
+ * (K = 6) and the output layer (N = 6) run in FP32 from the FP32 master,
+ * as do all biases.  Parameters of one network, in this order
+ * (RT_MLP_PARAMS floats): W1[256][6], b1[256], W2[256][256], b2[256],
  * W3[256][256], b3[256], W4[6][256], b4[6]  (h = silu(W x + b)).
- * Weights are used from a bf16 copy (uint16 bit patterns, same layout),
- * biases from the FP32 master.  Several networks (n_nets) are processed in
- * one launch, each on its own batch rows: x [n_nets][batch][6]. */
+ * Several networks (n_nets) are processed in one launch, each on its own
+ * batch rows: x [n_nets][batch][6]. */
 #define RT_MLP_PARAMS 134918
 
 /* Bytes of device workspace for rt_mlp_fwd/rt_mlp_bwd at this size. */
@@ -315,10 +319,10 @@ rt_status rt_mlp_fwd_grouped(rt_ctx *ctx, int n_nets, const int32_t *rows, const
                              const float *params, const float *x, float *y, void *hip_stream);
 
 /* grad [n_nets][RT_MLP_PARAMS] = d/dparams of sum_rows dy . y, for the
- * activations stored in work by the last rt_mlp_fwd.  Bias gradients are
- * reduced in a fixed order. */
-rt_status rt_mlp_bwd(rt_ctx *ctx, int n_nets, int batch, const uint16_t *w_bf16, const float *dy, float *grad,
-                     void *work, size_t work_bytes, void *hip_stream);
+ * activations stored in work by the last rt_mlp_fwd with the same weights.
+ * Reductions over rows run in a fixed order. */
+rt_status rt_mlp_bwd(rt_ctx *ctx, int n_nets, int batch, const uint16_t *w_bf16, const float *params, const float *dy,
+                     float *grad, void *work, size_t work_bytes, void *hip_stream);
 
 /* Mean-squared-error gradient for training: dy = 2 (y - t) / batch over n
  * values (device arrays), and 64 partial sums of (y - t)^2 written to
@@ -337,9 +341,10 @@ rt_status rt_adamw_step(rt_ctx *ctx, float *params, uint16_t *w_bf16, float *m, 
  * graph-metric acceleration of Eq. 5.4) from the support sphere of radius
  * 3 sigma to the exit, which is refined by bisection.  In the canonical
  * frame the entry point is (3, 0, 0) and the direction (-cos th, sin th, 0).
- * grid = 0: sin^2 th uniform in [0, 1) from a counter-based generator of
+ * mode 0: sin^2 th uniform in [0, 1) from a counter-based generator of
  * (seed, shape, sample), i.e. entry points uniform over the disc of impact
- * parameters; grid = 1: cos th = i / (n_per_shape - 1).  kappa and scale
+ * parameters; mode 1: cos th = i / (n_per_shape - 1); mode 2: sin th
+ * uniform in [0, 1) (impact parameters uniform).  kappa and scale
  * are host arrays [n_shapes]; outputs are device arrays:
  *   x   [n_shapes][n_per_shape][6]  network input (1, 0, 0, -cos th, sin th, 0)
  *   y   [n_shapes][n_per_shape][6]  target: (exit point / 3 - (-cos 2th, sin 2th, 0),
@@ -348,7 +353,7 @@ rt_status rt_adamw_step(rt_ctx *ctx, float *params, uint16_t *w_bf16, float *m, 
  *                                   the sphere (units of sigma; -1 if the
  *                                   ray did not exit), exit / 3 (x, y) */
 rt_status rt_surrogate_gen(rt_ctx *ctx, int n_shapes, const float *kappa, const float *scale, int n_per_shape,
-                           float h, int grid, uint64_t seed, float *x, float *y, float *aux, void *hip_stream);
+                           float h, int mode, uint64_t seed, float *x, float *y, float *aux, void *hip_stream);
 
 /* Calibration of the surrogate's error bounds: for predictions `pred` and
  * targets `target` (scaled residuals as produced by rt_surrogate_gen, both

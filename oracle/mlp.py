@@ -7,10 +7,11 @@ layers, y = W4 h3 + b4.  Parameter vector layout (134918 values):
 Loss: mean over the batch of the sum of squared output errors.
 
 bf16=True emulates where the GPU rounds to bfloat16 (round to nearest even):
-the weight matrices W2, W3, W4, the hidden-layer inputs (h1, h2, h3) and the
-backward signals entering a bfloat16 matrix product (dL/dy, dL/dz3, dL/dz2).
-The first layer (K = 6) stays wide: x, W1 and dL/dz1 are not rounded, nor
-are the biases, the pre-activations, the outputs and all accumulations.
+the weight matrices W2 and W3, the inputs of the two 256-wide products (h1,
+h2) and the backward signals entering them (dL/dz3, dL/dz2).  The first
+layer (K = 6) and the output layer (N = 6) stay wide: x, W1, h3, W4, dL/dy
+and dL/dz1 are not rounded, nor are the biases, the pre-activations and all
+accumulations.
 """
 from __future__ import annotations
 
@@ -70,9 +71,9 @@ def forward(p, x, bf16=False):
         hs.append(h)
         z = h @ (W if li == 0 else r(W)).T + b
         zs.append(z)
-        h = r(silu(z))
+        h = r(silu(z)) if li < 2 else silu(z)
     hs.append(h)
-    y = h @ r(W4).T + b4
+    y = h @ W4.T + b4
     return y, (hs, zs)
 
 
@@ -84,9 +85,9 @@ def backward(p, x, dy, bf16=False):
     g = np.zeros(N_PARAMS)
     gW1, gb1, gW2, gb2, gW3, gb3, gW4, gb4 = split(g)
     d = np.asarray(dy, np.float64)
-    gW4[:] = r(d).T @ hs[3]
+    gW4[:] = d.T @ hs[3]
     gb4[:] = d.sum(0)
-    dh = r(d) @ r(W4)                       # dL/dh3
+    dh = d @ W4                             # dL/dh3
     for W, gW, gb, li in ((W3, gW3, gb3, 2), (W2, gW2, gb2, 1), (W1, gW1, gb1, 0)):
         dz = dh * dsilu(zs[li])
         gW[:] = (r(dz) if li > 0 else dz).T @ hs[li]

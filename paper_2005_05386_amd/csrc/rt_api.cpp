@@ -839,14 +839,15 @@ rt_status rt_mlp_fwd_grouped(rt_ctx *c, int n_nets, const int32_t *rows, const u
     return RT_OK;
 }
 
-rt_status rt_mlp_bwd(rt_ctx *c, int n_nets, int batch, const uint16_t *w_bf16, const float *dy, float *grad,
-                     void *work, size_t work_bytes, void *stream) {
+rt_status rt_mlp_bwd(rt_ctx *c, int n_nets, int batch, const uint16_t *w_bf16, const float *params, const float *dy,
+                     float *grad, void *work, size_t work_bytes, void *stream) {
     rt_status st = mlp_check(c, n_nets, batch, w_bf16, work, work_bytes, "rt_mlp_bwd");
     if (st != RT_OK) return st;
-    if (!dy || !grad) return fail(c, RT_EINVAL, "rt_mlp_bwd: NULL argument");
+    if (!params || !dy || !grad) return fail(c, RT_EINVAL, "rt_mlp_bwd: NULL argument");
     rti::MlpWork w;
     rti::mlp_work_carve(work, n_nets, batch, w);
-    hipError_t e = rti::mlp_backward(n_nets, batch, (const __bf16 *)w_bf16, dy, grad, w, (hipStream_t)stream);
+    hipError_t e =
+        rti::mlp_backward(n_nets, batch, (const __bf16 *)w_bf16, params, dy, grad, w, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch (mlp backward)");
     return RT_OK;
 }
@@ -880,13 +881,13 @@ rt_status rt_adamw_step(rt_ctx *c, float *params, uint16_t *w_bf16, float *m, fl
 }
 
 rt_status rt_surrogate_gen(rt_ctx *c, int n_shapes, const float *kappa, const float *scale, int n_per, float h,
-                           int grid, uint64_t seed, float *x, float *y, float *aux, void *stream) {
+                           int mode, uint64_t seed, float *x, float *y, float *aux, void *stream) {
     if (!c) return RT_EINVAL;
     if (n_shapes < 1 || n_shapes > 4096 || n_per < 1 || (int64_t)n_shapes * n_per > (1LL << 31) - 1)
         return fail(c, RT_EINVAL, "rt_surrogate_gen: bad sizes");
     if (!kappa || !scale || !x || !y || !aux) return fail(c, RT_EINVAL, "rt_surrogate_gen: NULL argument");
-    if (!(h >= 1e-3f && h <= 0.5f) || (grid != 0 && grid != 1))
-        return fail(c, RT_EINVAL, "rt_surrogate_gen: need 1e-3 <= h <= 0.5 and grid in {0, 1}");
+    if (!(h >= 1e-3f && h <= 0.5f) || mode < 0 || mode > 2)
+        return fail(c, RT_EINVAL, "rt_surrogate_gen: need 1e-3 <= h <= 0.5 and mode in {0, 1, 2}");
     for (int i = 0; i < n_shapes; ++i)
         if (!finite(kappa[i]) || std::fabs(kappa[i]) > 100.f || !(scale[i] > 0.f) || !finite(scale[i]))
             return fail(c, RT_EINVAL, "rt_surrogate_gen: bad kappa or scale");
@@ -894,14 +895,17 @@ rt_status rt_surrogate_gen(rt_ctx *c, int n_shapes, const float *kappa, const fl
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     std::vector<float> ks(2 * (size_t)n_shapes);
+    float kmax = 0.f;
     for (int i = 0; i < n_shapes; ++i) {
         ks[i] = kappa[i];
         ks[n_shapes + i] = scale[i];
+        kmax = std::max(kmax, std::fabs(kappa[i]));
     }
     rt_status st = upload(c, &c->d_gen_ks, &c->gen_ks_bytes, ks.data(), ks.size() * sizeof(float));
     if (st != RT_OK) return st;
     const float *dk = (const float *)c->d_gen_ks;
-    e = rti::launch_cross_gen(dk, dk + n_shapes, n_shapes, n_per, h, grid, seed, x, y, aux, (hipStream_t)stream);
+    e = rti::launch_cross_gen(dk, dk + n_shapes, n_shapes, n_per, h, mode, seed, x, y, aux, kmax,
+                              (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch (surrogate data)");
     c->last_stream = (hipStream_t)stream;
     c->traced = true;
@@ -1027,6 +1031,7 @@ rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
     out->passes = c->last_passes;
     out->crossings = v[rti::ST_XING];
     out->accepted = v[rti::ST_XACC];
+    out->eligible = c->last_surr ? c->surr_eligible : 0;
     if (c->last_timed) {
         // events: 0 before reset, 1 after reset, 2+p after pass p, 2+np after
         // refine, 2np+2+p after the compaction that precedes pass p (p >= 1),

@@ -201,8 +201,8 @@ size_t mlp_work_bytes(int n_nets, int batch);
 void mlp_work_carve(void *base, int n_nets, int batch, MlpWork &w);
 hipError_t mlp_forward(int n_nets, int batch, const __bf16 *wb, const float *params, const float *x, float *y,
                        const MlpWork &w, bool keep, hipStream_t s);
-hipError_t mlp_backward(int n_nets, int batch, const __bf16 *wb, const float *dy, float *grad, const MlpWork &w,
-                        hipStream_t s);
+hipError_t mlp_backward(int n_nets, int batch, const __bf16 *wb, const float *params, const float *dy, float *grad,
+                        const MlpWork &w, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs &G, int groups, int max_rows, hipStream_t s);
 hipError_t launch_colsum(const float *X, int64_t xg, int rows, int N, int groups, float *part, float *out,
                          int64_t out_g, hipStream_t s);
@@ -212,8 +212,8 @@ hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t s);
 hipError_t launch_mse_grad(const float *y, const float *t, float *dy, int64_t n, int batch, float *part, int nblk,
                            hipStream_t s);
 
-hipError_t launch_cross_gen(const float *kappa, const float *scale, int n_shapes, int n_per, float h, int grid,
-                            uint64_t seed, float *X, float *Y, float *AUX, hipStream_t s);
+hipError_t launch_cross_gen(const float *kappa, const float *scale, int n_shapes, int n_per, float h, int mode,
+                            uint64_t seed, float *X, float *Y, float *AUX, float kappa_max, hipStream_t s);
 hipError_t launch_cross_cal(const float *X, const float *P, const float *Y, const float *scale, int n_shapes,
                             int n_per, int n_bins, float *err, hipStream_t s);
 // Crossing stage after pass `pass`: group by network, fused MLP forward,

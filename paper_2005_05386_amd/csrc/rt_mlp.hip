@@ -1,8 +1,9 @@
 // Kernels of the surrogate MLP (6 -> 256 -> 256 -> 256 -> 6, SiLU): the
-// first layer (K = 6, negligible work) in FP32 on the vector units so that
-// the input direction keeps full precision, the three 256-wide products as
-// BF16 matrix-core GEMMs with FP32 accumulation and fused epilogues, column
-// sums for bias gradients, and the AdamW update.
+// first layer (K = 6) and the output layer (N = 6) in FP32 on the vector
+// units (1% of the FLOPs; the input direction keeps full precision and the
+// outputs escape the bfloat16 rounding of the last hidden layer), the two
+// 256x256 products as BF16 matrix-core GEMMs with FP32 accumulation and
+// fused epilogues, column sums for bias gradients, and the AdamW update.
 //
 // GEMM: for every group g (one network), C[m][n] = sum_k A(m,k) B(k,n) with
 // A(m,k) = A[a_off(g) + m*sam + k*sak], B(k,n) = B[b_off(g) + k*sbk + n*sbn]
@@ -181,6 +182,82 @@ __global__ __launch_bounds__(256) void k_l1_grad_final(const float *__restrict__
     G[rti::OFF_B1 + o] = a[6];
 }
 
+// Output layer in FP32: y[m][o] = b4[o] + sum_k W4[o][k] silu(z3[m][k]),
+// one thread per (row, output), k in order.
+__global__ __launch_bounds__(256) void k_l4_fwd(const float *__restrict__ params, const float *__restrict__ Z3, int B,
+                                                float *__restrict__ Y) {
+    const int g = blockIdx.y;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * 6) return;
+    const int m = idx / 6, o = idx - m * 6;
+    const float *__restrict__ W = params + g * rti::MLP_P + rti::OFF_W4 + o * rti::MLP_H;
+    const float *__restrict__ z = Z3 + ((int64_t)g * B + m) * rti::MLP_H;
+    float acc = params[g * rti::MLP_P + rti::OFF_B4 + o];
+    for (int k = 0; k < rti::MLP_H; ++k) acc = fmaf(W[k], silu(z[k]), acc);
+    Y[((int64_t)g * B + m) * 6 + o] = acc;
+}
+
+// Output-layer gradients in FP32: dW4[o][k] = sum_m dy[m][o] silu(z3[m][k]),
+// db4[o] = sum_m dy[m][o]; per block of 256 rows a sequential partial
+// (thread k: six dW4 partials, and db4[k] for k < 6), then the partials in
+// order.
+__global__ __launch_bounds__(256) void k_l4_grad_part(const float *__restrict__ DY, const float *__restrict__ Z3, int B,
+                                                      float *__restrict__ part) {
+    const int g = blockIdx.y, c = blockIdx.x, k = threadIdx.x;
+    const int r0 = c * 256, r1 = min(B, r0 + 256);
+    float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int m = r0; m < r1; ++m) {
+        const int64_t r = (int64_t)g * B + m;
+        const float h = silu(Z3[r * rti::MLP_H + k]);
+        const float *__restrict__ d = DY + r * 6;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) a[o] = fmaf(d[o], h, a[o]);
+        if (k < 6) a[6] += d[k];
+    }
+    float *__restrict__ dst = part + (((int64_t)g * gridDim.x + c) * rti::MLP_H + k) * 7;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) dst[i] = a[i];
+}
+__global__ __launch_bounds__(256) void k_l4_grad_final(const float *__restrict__ part, int nchunk,
+                                                       float *__restrict__ grad) {
+    const int g = blockIdx.x, k = threadIdx.x;
+    float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < nchunk; ++c) {
+        const float *__restrict__ src = part + (((int64_t)g * nchunk + c) * rti::MLP_H + k) * 7;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) a[i] += src[i];
+    }
+    float *__restrict__ G = grad + (int64_t)g * rti::MLP_P;
+#pragma unroll
+    for (int o = 0; o < 6; ++o) G[rti::OFF_W4 + o * rti::MLP_H + k] = a[o];
+    if (k < 6) G[rti::OFF_B4 + k] = a[6];
+}
+
+// Back-propagation through the output layer: dz3[m][k] =
+// (sum_o dy[m][o] W4[o][k]) silu'(z3[m][k]), kept in FP32 and bf16.
+__global__ __launch_bounds__(256) void k_l4_bwd(const float *__restrict__ params, const float *__restrict__ DY,
+                                                const float *__restrict__ Z3, int B, float *__restrict__ DZ,
+                                                __bf16 *__restrict__ DZB) {
+    const int g = blockIdx.y, k = threadIdx.x;
+    const int m0 = blockIdx.x * 64;
+    if (m0 >= B) return;
+    const float *__restrict__ W = params + g * rti::MLP_P + rti::OFF_W4;
+    float w[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) w[o] = W[o * rti::MLP_H + k];
+    const int m1 = min(B, m0 + 64);
+    for (int m = m0; m < m1; ++m) {
+        const int64_t r = (int64_t)g * B + m;
+        const float *__restrict__ d = DY + r * 6;
+        float dh = 0.f;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) dh = fmaf(d[o], w[o], dh);
+        const float dz = dh * dsilu(Z3[r * rti::MLP_H + k]);
+        DZ[r * rti::MLP_H + k] = dz;
+        DZB[r * rti::MLP_H + k] = (__bf16)dz;
+    }
+}
+
 // out[g][n] = sum_m X[g][m][n], fixed order: per block of 256 rows a
 // sequential partial, then partials summed in order.
 __global__ void k_colsum_part(const float *__restrict__ X, int64_t xg, int rows, int N, float *__restrict__ part) {
@@ -327,6 +404,7 @@ hipError_t mlp_forward(int n, int B, const __bf16 *wb, const float *params, cons
     const int64_t in_w = MLP_H;
     const int64_t offW[3] = {OFF_W1, OFF_W2, OFF_W3}, offB[3] = {OFF_B1, OFF_B2, OFF_B3};
     for (int l = 1; l < 3; ++l) {
+        // layer 3's pre-activations always go to z[2]: the FP32 output layer reads them
         GemmArgs G = gemm0();
         G.A = in;
         G.a_g = (int64_t)B * in_w;
@@ -342,7 +420,7 @@ hipError_t mlp_forward(int n, int B, const __bf16 *wb, const float *params, cons
         G.epi = EPI_HIDDEN;
         G.bias = params + offB[l];
         G.bias_g = MLP_P;
-        G.Cf = keep ? w.z[l] : nullptr;
+        G.Cf = (keep || l == 2) ? w.z[l] : nullptr;
         G.cf_g = (int64_t)B * MLP_H;
         G.ldcf = MLP_H;
         G.Cb = w.h[l];
@@ -351,32 +429,16 @@ hipError_t mlp_forward(int n, int B, const __bf16 *wb, const float *params, cons
         if ((e = launch_gemm(G, n, B, s)) != hipSuccess) return e;
         in = w.h[l];
     }
-    GemmArgs G = gemm0();
-    G.A = in;
-    G.a_g = (int64_t)B * MLP_H;
-    G.sam = MLP_H;
-    G.sak = 1;
-    G.B = wb + OFF_W4;
-    G.b_g = MLP_P;
-    G.sbk = 1;
-    G.sbn = MLP_H;
-    G.M = B;
-    G.N = (int)MLP_OUT;
-    G.K = (int)MLP_H;
-    G.epi = EPI_BIAS;
-    G.bias = params + OFF_B4;
-    G.bias_g = MLP_P;
-    G.Cf = y;
-    G.cf_g = (int64_t)B * MLP_OUT;
-    G.ldcf = MLP_OUT;
-    return launch_gemm(G, n, B, s);
+    (void)in;
+    hipLaunchKernelGGL(k_l4_fwd, dim3((B * 6 + 255) / 256, n), dim3(256), 0, s, params, w.z[2], B, y);
+    return hipGetLastError();
 }
 
 // grad = dL/dparams given dy = dL/dy, using the workspace of the last
 // forward with keep = true.
-hipError_t mlp_backward(int n, int B, const __bf16 *wb, const float *dy, float *grad, const MlpWork &w, hipStream_t s) {
-    hipError_t e = launch_to_bf16(dy, w.dyb, (int64_t)n * B * MLP_OUT, s);
-    if (e != hipSuccess) return e;
+hipError_t mlp_backward(int n, int B, const __bf16 *wb, const float *params, const float *dy, float *grad,
+                        const MlpWork &w, hipStream_t s) {
+    hipError_t e = hipSuccess;
     // weight gradient dW[o][i] = sum_b d[b][o] in[b][i]
     auto wgrad = [&](const __bf16 *d, int64_t dw, const __bf16 *in, int64_t iw, int64_t off) {
         GemmArgs G = gemm0();
@@ -422,10 +484,15 @@ hipError_t mlp_backward(int n, int B, const __bf16 *wb, const float *dy, float *
         G.ldcb = MLP_H;
         return launch_gemm(G, n, B, s);
     };
-    if ((e = wgrad(w.dyb, MLP_OUT, w.h[2], MLP_H, OFF_W4)) != hipSuccess) return e;
-    if ((e = launch_colsum(dy, (int64_t)B * MLP_OUT, B, (int)MLP_OUT, n, w.part, grad + OFF_B4, MLP_P, s)) != hipSuccess)
-        return e;
-    if ((e = bprop(w.dyb, MLP_OUT, OFF_W4, w.z[2], w.dzf[0], w.dzb[0])) != hipSuccess) return e;
+    // output layer (FP32): weight and bias gradients, then dz3 into buffer 0
+    {
+        const int nch4 = (B + 255) / 256;
+        hipLaunchKernelGGL(k_l4_grad_part, dim3(nch4, n), dim3(256), 0, s, dy, w.z[2], B, w.part);
+        hipLaunchKernelGGL(k_l4_grad_final, dim3(n), dim3(256), 0, s, w.part, nch4, grad);
+        hipLaunchKernelGGL(k_l4_bwd, dim3((B + 63) / 64, n), dim3(256), 0, s, params, dy, w.z[2], B, w.dzf[0],
+                           w.dzb[0]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // layer 3: dz in buffer 0
     if ((e = wgrad(w.dzb[0], MLP_H, w.h[1], MLP_H, OFF_W3)) != hipSuccess) return e;
     if ((e = launch_colsum(w.dzf[0], (int64_t)B * MLP_H, B, (int)MLP_H, n, w.part, grad + OFF_B3, MLP_P, s)) !=

@@ -52,12 +52,12 @@ __device__ __forceinline__ void chord_baseline(float c, float s, V3<float> &uc, 
 }
 
 // ===================================================== training crossings
-// Sample i of shape sh: sin^2 th uniform in [0, 1) (random mode: entry
-// points uniform over the disc of impact parameters) or cos th = i / (n - 1)
-// (grid mode).  RK4 with step h from (3, 0, 0) until a step leaves the
+// Sample i of shape sh: sin^2 th uniform in [0, 1) (mode 0: entry points
+// uniform over the disc of impact parameters), cos th = i / (n - 1) (mode 1,
+// a grid), or sin th uniform in [0, 1) (mode 2: impact parameters uniform).  RK4 with step h from (3, 0, 0) until a step leaves the
 // sphere, then bisection of that step's fraction on |u|^2 - 9.
 __global__ __launch_bounds__(256) void k_cross_gen(const float *__restrict__ kappa, const float *__restrict__ scale,
-                                                   int n_per, float h, int grid, uint64_t seed,
+                                                   int n_per, float h, int mode, uint64_t seed,
                                                    float *__restrict__ X, float *__restrict__ Y,
                                                    float *__restrict__ AUX, int max_steps) {
     const int sh = blockIdx.y;
@@ -72,12 +72,14 @@ __global__ __launch_bounds__(256) void k_cross_gen(const float *__restrict__ kap
     }
     __syncthreads();
     float ct, st;
-    if (grid) {
+    if (mode == 1) {
         ct = n_per > 1 ? (float)i / (float)(n_per - 1) : 1.0f;
         st = sqrtf(fmaxf(0.f, 1.f - ct * ct));
     } else {
         const uint64_t r = splitmix64(seed ^ splitmix64(((uint64_t)sh << 40) ^ (uint64_t)i));
-        const float s2 = (float)((r >> 11) * (1.0 / 9007199254740992.0));
+        const float u = (float)((r >> 11) * (1.0 / 9007199254740992.0));
+        // mode 0: sin^2 th uniform (area-uniform impact parameters); mode 2: sin th uniform
+        const float s2 = mode == 2 ? u * u : u;
         st = sqrtf(s2);
         ct = sqrtf(fmaxf(0.f, 1.f - s2));
     }
@@ -260,13 +262,18 @@ __global__ __launch_bounds__(256) void k_xprep(const rti::TraceArgs A, const rti
 }
 
 // Fused grouped MLP forward.  A workgroup takes 64-row tiles of one network
-// (persistent over the pass's tile list): the first layer in FP32, then the
-// two 256x256 products and the 256x6 output on v_mfma_f32_16x16x32_bf16 with
-// the activations kept in LDS as bf16; weights stream from L2.  Rounding
-// points are those of the training forward pass.
+// (persistent over the pass's tile list): the first layer in FP32, the two
+// 256x256 products on v_mfma_f32_16x16x32_bf16 with the activations kept in
+// LDS as bf16 and the weights streamed from L2, and the output layer in FP32
+// from the FP32 activations of the last hidden layer (which reuse the bf16
+// buffer's LDS).  Rounding points and summation orders are those of the
+// training forward pass.
 __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, const rti::SurrArgs S) {
-    // rows of 264 bf16 (528 bytes): 16-byte aligned for 128-bit LDS reads
-    __shared__ __attribute__((aligned(16))) __bf16 Hs[64][256 + 8];
+    // one LDS buffer: bf16 rows of 264 (528 bytes, 16-byte aligned for
+    // 128-bit reads) for the hidden products, then FP32 rows of 260
+    __shared__ __attribute__((aligned(16))) float Hbuf[64 * 260];
+    __bf16(*Hs)[264] = reinterpret_cast<__bf16(*)[264]>(Hbuf);
+    float(*Hf)[260] = reinterpret_cast<float(*)[260]>(Hbuf);
     __shared__ float Xs[64][6];
     const int total_tiles = ctl[rti::XC_TILE + 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -301,7 +308,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, 
         }
         __syncthreads();
         const int kq = (lane >> 4) * 8;
-        // layers 2 and 3: wave w owns output columns [64 w, 64 w + 64)
+        // layers 2 and 3: wave w owns output columns [64 w, 64 w + 64);
+        // layer 3 leaves FP32 activations in Hf
         for (int l = 0; l < 2; ++l) {
             const __bf16 *__restrict__ W = Wg + (l == 0 ? rti::OFF_W2 : rti::OFF_W3);
             const float *__restrict__ bias = Pg + (l == 0 ? rti::OFF_B2 : rti::OFF_B3);
@@ -333,33 +341,23 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, 
                     const int n = wave * 64 + 16 * j + (lane & 15);
                     const float bn = bias[n];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) Hs[16 * i + (lane >> 4) * 4 + e][n] = (__bf16)silu_f(acc[i][j][e] + bn);
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = 16 * i + (lane >> 4) * 4 + e;
+                        const float h = silu_f(acc[i][j][e] + bn);
+                        if (l == 0) Hs[m][n] = (__bf16)h;
+                        else Hf[m][n] = h;
+                    }
                 }
             __syncthreads();
         }
-        {   // output layer: wave w computes rows [16 w, 16 w + 16), columns padded to 16
-            const __bf16 *__restrict__ W = Wg + rti::OFF_W4;
-            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-            const int n = lane & 15;
-            const __bf16 zero = (__bf16)0.0f;
-            for (int k0 = 0; k0 < 256; k0 += 32) {
-                bf16x8 a = *(const bf16x8 *)&Hs[16 * wave + (lane & 15)][k0 + kq];
-                bf16x8 b;
-                if (n < 6) {
-                    b = *(const bf16x8 *)(W + n * 256 + k0 + kq);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) b[e] = zero;
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-            }
-            if (n < 6) {
-                const float bn = Pg[rti::OFF_B4 + n];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int r = 16 * wave + (lane >> 4) * 4 + e;
-                    if (r < M) S.xout[6 * (int64_t)(m0 + r) + n] = acc[e] + bn;
-                }
+        // output layer, FP32: one thread per (row, output), k in order
+        for (int idx = tid; idx < 64 * 6; idx += 256) {
+            const int m = idx / 6, o = idx - m * 6;
+            if (m < M) {
+                const float *__restrict__ W = Pg + rti::OFF_W4 + o * 256;
+                float acc = Pg[rti::OFF_B4 + o];
+                for (int k = 0; k < 256; ++k) acc = fmaf(W[k], Hf[m][k], acc);
+                S.xout[6 * (int64_t)(m0 + m) + o] = acc;
             }
         }
         __syncthreads();
@@ -469,11 +467,14 @@ __global__ __launch_bounds__(256) void k_xapply(const rti::TraceArgs A, const rt
 
 namespace rti {
 
-hipError_t launch_cross_gen(const float *kappa, const float *scale, int n_shapes, int n_per, float h, int grid,
-                            uint64_t seed, float *X, float *Y, float *AUX, hipStream_t s) {
+hipError_t launch_cross_gen(const float *kappa, const float *scale, int n_shapes, int n_per, float h, int mode,
+                            uint64_t seed, float *X, float *Y, float *AUX, float kappa_max, hipStream_t s) {
     dim3 g((n_per + 255) / 256, n_shapes);
-    int max_steps = (int)(8.0f / h) + 16;
-    hipLaunchKernelGGL(k_cross_gen, g, dim3(256), 0, s, kappa, scale, n_per, h, grid, seed, X, Y, AUX, max_steps);
+    // arc lengths inside the sphere grow with kappa (about 11 units at
+    // kappa = 4, where rays wind around the bump): a generous bound; every
+    // ray stops at its exit
+    const int max_steps = (int)((20.0f + 10.0f * kappa_max) / h) + 16;
+    hipLaunchKernelGGL(k_cross_gen, g, dim3(256), 0, s, kappa, scale, n_per, h, mode, seed, X, Y, AUX, max_steps);
     return hipGetLastError();
 }
 

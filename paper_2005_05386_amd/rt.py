@@ -74,7 +74,8 @@ class rt_stats(C.Structure):
                 ("obj_list_sum", C.c_uint64), ("refined", C.c_uint64), ("acc_evals", C.c_uint64),
                 ("bump_evals", C.c_uint64), ("obj_tests", C.c_uint64), ("passes", C.c_int), ("pass_ms", C.c_float),
                 ("refine_ms", C.c_float), ("compact_ms", C.c_float), ("total_ms", C.c_float),
-                ("crossings", C.c_uint64), ("accepted", C.c_uint64), ("surr_ms", C.c_float)]
+                ("crossings", C.c_uint64), ("accepted", C.c_uint64), ("surr_ms", C.c_float),
+                ("eligible", C.c_int)]
 
 
 _P = C.c_void_p
@@ -108,7 +109,7 @@ _lib.rt_mlp_work_bytes.argtypes = [C.c_int, C.c_int]
 _lib.rt_mlp_work_bytes.restype = C.c_size_t
 _lib.rt_mlp_fwd.argtypes = [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, C.c_size_t, _P]
 _lib.rt_mlp_fwd.restype = C.c_int
-_lib.rt_mlp_bwd.argtypes = [_P, C.c_int, C.c_int, _P, _P, _P, _P, C.c_size_t, _P]
+_lib.rt_mlp_bwd.argtypes = [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, C.c_size_t, _P]
 _lib.rt_mlp_bwd.restype = C.c_int
 _lib.rt_adamw_step.argtypes = [_P, _P, _P, _P, _P, _P, C.c_size_t, C.c_float, C.c_float, C.c_float, C.c_float,
                                C.c_float, C.c_int, _P]
@@ -315,12 +316,14 @@ class Tracer:
                                             C.c_void_p(y.data_ptr()), C.c_void_p(st.cuda_stream)))
         return y
 
-    def mlp_bwd(self, w_bf16, dy, work):
+    def mlp_bwd(self, w_bf16, params, dy, work):
+        """Parameter gradient [n_nets, MLP_PARAMS] of sum(dy * y) for the last
+        mlp_fwd on `work` (same weights)."""
         import torch
         n, b = dy.shape[0], dy.shape[1]
         g = torch.empty((n, MLP_PARAMS), dtype=torch.float32, device=dy.device)
         st = torch.cuda.current_stream(self.device)
-        self._check(_lib.rt_mlp_bwd(self._h, n, b, C.c_void_p(w_bf16.data_ptr()),
+        self._check(_lib.rt_mlp_bwd(self._h, n, b, C.c_void_p(w_bf16.data_ptr()), C.c_void_p(params.data_ptr()),
                                     C.c_void_p(dy.contiguous().data_ptr()), C.c_void_p(g.data_ptr()),
                                     C.c_void_p(work.data_ptr()), C.c_size_t(work.numel() * 4),
                                     C.c_void_p(st.cuda_stream)))
@@ -346,9 +349,10 @@ class Tracer:
                                        float(b1), float(b2), float(eps), float(wd), int(step),
                                        C.c_void_p(st.cuda_stream)))
 
-    def surrogate_gen(self, kappa, scale, n_per, h, grid=False, seed=0):
-        """Crossing data for each shape kappa (random or cos-theta grid
-        entries): returns x, y [n,n_per,6], aux [n,n_per,4]."""
+    def surrogate_gen(self, kappa, scale, n_per, h, grid=False, seed=0, mode=None):
+        """Crossing data for each shape kappa (mode 0: sin^2 th uniform,
+        1: cos-theta grid, 2: sin th uniform; grid=True selects mode 1):
+        returns x, y [n,n_per,6], aux [n,n_per,4]."""
         import torch
         k = np.ascontiguousarray(kappa, np.float32)
         sc = np.ascontiguousarray(scale, np.float32)
@@ -359,7 +363,8 @@ class Tracer:
         aux = torch.empty((n, n_per, 4), dtype=torch.float32, device=dev)
         st = torch.cuda.current_stream(self.device)
         self._check(_lib.rt_surrogate_gen(self._h, n, k.ctypes.data, sc.ctypes.data, int(n_per), float(h),
-                                          1 if grid else 0, int(seed), C.c_void_p(x.data_ptr()),
+                                          int(mode if mode is not None else (1 if grid else 0)), int(seed),
+                                          C.c_void_p(x.data_ptr()),
                                           C.c_void_p(y.data_ptr()), C.c_void_p(aux.data_ptr()),
                                           C.c_void_p(st.cuda_stream)))
         return x, y, aux

@@ -83,7 +83,7 @@ class Surrogate:
 
 
 def train(tracer, kappa, samples=10_000_000, batch=1024, h=0.01, lr=1e-3, lr_min=1e-5, warmup=200, seed=0,
-          n_tab=4097, n_bins=64, n_cal=8192, log_every=500, log=None):
+          n_tab=4097, n_bins=64, n_cal=8192, log_every=500, log=None, sampling=0):
     """Train one network per shape in kappa (all in one grouped launch per
     layer) and calibrate it.  Returns a Surrogate."""
     import torch
@@ -105,10 +105,10 @@ def train(tracer, kappa, samples=10_000_000, batch=1024, h=0.01, lr=1e-3, lr_min
     losses = []
     gen_s = 0.0
     for step in range(1, steps + 1):
-        x, y, _ = tracer.surrogate_gen(kappa, scale, batch, h, grid=False, seed=seed + 1000003 * step)
+        x, y, _ = tracer.surrogate_gen(kappa, scale, batch, h, mode=sampling, seed=seed + 1000003 * step)
         pred = tracer.mlp_fwd(wb, params, x, work)
         dy, part = tracer.mse_grad(pred, y, batch)
-        g = tracer.mlp_bwd(wb, dy, work)
+        g = tracer.mlp_bwd(wb, params, dy, work)
         if step <= warmup:
             lr_t = lr * step / warmup
         else:

@@ -41,7 +41,7 @@ def test_mlp_forward_backward_match_oracle(env, n, batch):
     dy = rng.normal(size=(n, batch, 6)).astype(np.float32)
     work = tr.mlp_work(n, batch)
     y = tr.mlp_fwd(pb, pt, torch.tensor(x, device="cuda"), work).cpu().numpy()
-    g = tr.mlp_bwd(pb, torch.tensor(dy, device="cuda"), work).cpu().numpy()
+    g = tr.mlp_bwd(pb, pt, torch.tensor(dy, device="cuda"), work).cpu().numpy()
     p32 = p.astype(np.float32).astype(np.float64)
     for i in range(n):
         yr, _ = mlp.forward(p32[i], x[i].astype(np.float64), bf16=True)
@@ -88,7 +88,7 @@ def test_training_reduces_loss(env):
         y = tr.mlp_fwd(pb, pt, x, work)
         diff = y - t
         losses.append(float((diff * diff).sum() / (n * batch)))
-        g = tr.mlp_bwd(pb, 2.0 * diff / batch, work)
+        g = tr.mlp_bwd(pb, pt, 2.0 * diff / batch, work)
         tr.adamw(pt, pb, m, v, g, 2e-3, step)
     say("loss", losses[0], "->", losses[-1])
     assert losses[-1] < 0.05 * losses[0]

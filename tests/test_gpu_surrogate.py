@@ -50,7 +50,8 @@ def test_crossing_data_matches_exact(env, kappa):
             assert abs(np.arctan2(u[1], u[0]) % (2 * np.pi) - dphi) < 2e-5, (i, np.arctan2(u[1], u[0]), dphi)
             ang = np.arctan2(w[1], w[0]) - (dphi + th)
             assert abs((ang + np.pi) % (2 * np.pi) - np.pi) < 4e-5, (i, ang)
-        assert abs(aux[i, 1] - arc) < 2e-4, (i, aux[i, 1], arc)
+        # a tangent entry (c = 0) exits within the FP32 resolution of |u|^2 - 9
+        assert abs(aux[i, 1] - arc) < (2e-4 if c > 0.02 else 1e-3), (i, aux[i, 1], arc)
         assert abs(aux[i, 0] - 3 * s) < 1e-5
 
 
