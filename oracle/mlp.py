@@ -6,12 +6,14 @@ layers, y = W4 h3 + b4.  Parameter vector layout (134918 values):
     W4[6][256], b4[6]
 Loss: mean over the batch of the sum of squared output errors.
 
-bf16=True emulates where the GPU rounds to bfloat16 (round to nearest even):
-the weight matrices W2 and W3, the inputs of the two 256-wide products (h1,
-h2) and the backward signals entering them (dL/dz3, dL/dz2).  The first
-layer (K = 6) and the output layer (N = 6) stay wide: x, W1, h3, W4, dL/dy
-and dL/dz1 are not rounded, nor are the biases, the pre-activations and all
-accumulations.
+bf16=True emulates the GPU's arithmetic.  The first layer (K = 6) and the
+output layer (N = 6) are wide (x, W1, h3, W4, dL/dy, dL/dz1 not rounded).
+The forward 256x256 products use three-term split bfloat16: with
+hi = bf16(v), lo = bf16(v - hi) for both operands, A B is taken as
+Ah Bh + Ah Bl + Al Bh.  The backward products round their operands to
+bfloat16 once: the signals dL/dz3, dL/dz2, the weights W3, W2 and, for the
+weight gradients, the layer inputs h1, h2.  Rounding is to nearest even;
+biases, pre-activations and accumulations stay wide.
 """
 from __future__ import annotations
 
@@ -41,6 +43,19 @@ def bf16_round(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def split_bf16(a):
+    """(hi, lo) with hi = bf16(a), lo = bf16(a - hi)."""
+    hi = bf16_round(a)
+    return hi, bf16_round(np.asarray(a, np.float64) - hi)
+
+
+def split_product(A, B):
+    """A @ B in three-term split bfloat16: Ah Bh + Ah Bl + Al Bh."""
+    Ah, Al = split_bf16(A)
+    Bh, Bl = split_bf16(B)
+    return Ah @ Bh + Ah @ Bl + Al @ Bh
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 
@@ -62,16 +77,20 @@ def init_params(seed):
 
 
 def forward(p, x, bf16=False):
-    """Returns y [n,6] and the cache of (layer inputs, pre-activations)."""
+    """Returns y [n,6] and the cache (inputs of each layer as the backward's
+    weight gradients use them, pre-activations)."""
     r = bf16_round if bf16 else (lambda a: np.asarray(a, np.float64))
     W1, b1, W2, b2, W3, b3, W4, b4 = split(np.asarray(p, np.float64))
     hs, zs = [], []
     h = np.asarray(x, np.float64)
     for li, (W, b) in enumerate(((W1, b1), (W2, b2), (W3, b3))):
-        hs.append(h)
-        z = h @ (W if li == 0 else r(W)).T + b
+        hs.append(h if li == 0 else r(h))
+        if li == 0 or not bf16:
+            z = h @ W.T + b
+        else:
+            z = split_product(h, W.T) + b
         zs.append(z)
-        h = r(silu(z)) if li < 2 else silu(z)
+        h = silu(z)
     hs.append(h)
     y = h @ W4.T + b4
     return y, (hs, zs)

@@ -262,18 +262,24 @@ __global__ __launch_bounds__(256) void k_xprep(const rti::TraceArgs A, const rti
 }
 
 // Fused grouped MLP forward.  A workgroup takes 64-row tiles of one network
-// (persistent over the pass's tile list): the first layer in FP32, the two
-// 256x256 products on v_mfma_f32_16x16x32_bf16 with the activations kept in
-// LDS as bf16 and the weights streamed from L2, and the output layer in FP32
-// from the FP32 activations of the last hidden layer (which reuse the bf16
-// buffer's LDS).  Rounding points and summation orders are those of the
-// training forward pass.
+// (persistent over the pass's tile list) and keeps the tile's activations
+// in LDS as FP32: the first layer in FP32, the two 256x256 products on
+// v_mfma_f32_16x16x32_bf16 in three-term split bf16 (Ah Bh + Ah Bl + Al Bh,
+// both operands split as they are read: activations from LDS, weights from
+// the FP32 master through L2), the output layer in FP32.  Rounding points
+// and summation orders are those of the training forward pass.
+__device__ __forceinline__ void split8(const float *v, bf16x8 &hi, bf16x8 &lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 h = (__bf16)v[e];
+        hi[e] = h;
+        lo[e] = (__bf16)(v[e] - (float)h);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, const rti::SurrArgs S) {
-    // one LDS buffer: bf16 rows of 264 (528 bytes, 16-byte aligned for
-    // 128-bit reads) for the hidden products, then FP32 rows of 260
-    __shared__ __attribute__((aligned(16))) float Hbuf[64 * 260];
-    __bf16(*Hs)[264] = reinterpret_cast<__bf16(*)[264]>(Hbuf);
-    float(*Hf)[260] = reinterpret_cast<float(*)[260]>(Hbuf);
+    // FP32 rows of 260 (1040 bytes, 16-byte aligned for 128-bit reads)
+    __shared__ __attribute__((aligned(16))) float Hf[64][260];
     __shared__ float Xs[64][6];
     const int total_tiles = ctl[rti::XC_TILE + 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -285,7 +291,6 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, 
         const int m0 = off + (t - ctl[rti::XC_TILE + g]) * 64;
         const int M = min(64, off + cnt - m0);
         const float *__restrict__ Pg = S.params + (int64_t)g * S.stride;
-        const __bf16 *__restrict__ Wg = S.wb + (int64_t)g * S.stride;
         for (int e = tid; e < 64 * 6; e += 256) {
             const int r = e / 6, k = e - r * 6;
             Xs[r][k] = r < M ? S.xin[6 * (int64_t)(m0 + r) + k] : 0.f;
@@ -303,15 +308,14 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, 
                 z = fmaf(w3, Xs[r][3], z);
                 z = fmaf(w4, Xs[r][4], z);
                 z = fmaf(w5, Xs[r][5], z);
-                Hs[r][tid] = (__bf16)silu_f(z);
+                Hf[r][tid] = silu_f(z);
             }
         }
         __syncthreads();
         const int kq = (lane >> 4) * 8;
-        // layers 2 and 3: wave w owns output columns [64 w, 64 w + 64);
-        // layer 3 leaves FP32 activations in Hf
+        // layers 2 and 3: wave w owns output columns [64 w, 64 w + 64)
         for (int l = 0; l < 2; ++l) {
-            const __bf16 *__restrict__ W = Wg + (l == 0 ? rti::OFF_W2 : rti::OFF_W3);
+            const float *__restrict__ W = Pg + (l == 0 ? rti::OFF_W2 : rti::OFF_W3);
             const float *__restrict__ bias = Pg + (l == 0 ? rti::OFF_B2 : rti::OFF_B3);
             f32x4 acc[4][4];
 #pragma unroll
@@ -319,19 +323,29 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int k0 = 0; k0 < 256; k0 += 32) {
-                bf16x8 a[4], b[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8 *)&Hs[16 * i + (lane & 15)][k0 + kq];
+                bf16x8 bh[4], bl[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int n = wave * 64 + 16 * j + (lane & 15);
-                    b[j] = *(const bf16x8 *)(W + (int64_t)n * 256 + k0 + kq);
+                    const float4 *src = reinterpret_cast<const float4 *>(W + (int64_t)n * 256 + k0 + kq);
+                    const float4 u0 = src[0], u1 = src[1];
+                    const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                    split8(v, bh[j], bl[j]);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i) {
+                    const float4 *src = reinterpret_cast<const float4 *>(&Hf[16 * i + (lane & 15)][k0 + kq]);
+                    const float4 u0 = src[0], u1 = src[1];
+                    const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                    bf16x8 ah, al;
+                    split8(v, ah, al);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < 4; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+                    }
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -341,12 +355,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, 
                     const int n = wave * 64 + 16 * j + (lane & 15);
                     const float bn = bias[n];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int m = 16 * i + (lane >> 4) * 4 + e;
-                        const float h = silu_f(acc[i][j][e] + bn);
-                        if (l == 0) Hs[m][n] = (__bf16)h;
-                        else Hf[m][n] = h;
-                    }
+                    for (int e = 0; e < 4; ++e) Hf[16 * i + (lane >> 4) * 4 + e][n] = silu_f(acc[i][j][e] + bn);
                 }
             __syncthreads();
         }
@@ -423,10 +432,12 @@ __global__ __launch_bounds__(256) void k_xapply(const rti::TraceArgs A, const rt
         const float fr = fi - (float)i0;
         const float *T = S.arc + (int64_t)net * S.n_tab;
         const float arc = sigma * fmaf(fr, T[i0 + 1] - T[i0], T[i0]);
+        // the ray ends at t_lim (t_max, or max_steps h if that comes first)
+        const float t_lim = fminf(A.t_max, (float)A.max_steps * A.h);
         const float t_exit = (float)steps * A.h + (th + tl) + arc;
-        const float L = fmaxf(0.f, A.t_max - t_exit);
+        const float L = fmaxf(0.f, t_lim - t_exit);
         const float est = R * (2.f * ep + r_err + z_err) + L * (2.f * ed + a_err + z_err);
-        const bool ok = est <= S.tol && t_exit < A.t_max && T[i0] >= 0.f && T[i0 + 1] >= 0.f && isfinite(est);
+        const bool ok = est <= S.tol && t_exit < t_lim && T[i0] >= 0.f && T[i0 + 1] >= 0.f && isfinite(est);
         if (ok) {
             V3<float> xe = mk(c0.x + R * (u.x * F.e1.x + u.y * F.e2.x + u.z * F.e3.x),
                               c0.y + R * (u.x * F.e1.y + u.y * F.e2.y + u.z * F.e3.y),

@@ -352,7 +352,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             if (hc < A.h_min || att > 8 * A.max_steps) ok = false;
                         }
                     } else if constexpr (STEP == STEP_RK4) {
-                        ok = step_rk4<float>(acc, p, y, A.h, dx, dv);
+                        if constexpr (SURR) {
+                            // jumps and partial entry steps shift the step grid: the
+                            // last step is clipped to land on min(t_max, max_steps h)
+                            const float t_lim = fminf(A.t_max, (float)A.max_steps * A.h);
+                            // (a remainder within rounding of h is a full step, so a ray
+                            // that never parked takes exactly the plain trace's steps)
+                            const float rem = t_lim - ((float)steps * A.h + (th + tl));
+                            hstep = rem < A.h * (1.0f - 1e-5f) ? fmaxf(rem, 0.f) : A.h;
+                        }
+                        ok = step_rk4<float>(acc, p, y, hstep, dx, dv);
                     } else {
                         ok = step_euler<float>(acc, p, y, A.h, dx, dv);
                     }
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             two_sum_add(xh.y, xl.y, ent_s * dx.y);
                             two_sum_add(xh.z, xl.z, ent_s * dx.z);
                             y = y + ent_s * dv;
-                            two_sum_add(th, tl, ent_s * A.h);
+                            two_sum_add(th, tl, ent_s * hstep);
                             parked = true;
                             park_b = ent_b;
                             hit_id = -1;
@@ -447,13 +456,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                             two_sum_add(xh.y, xl.y, dx.y);
                             two_sum_add(xh.z, xl.z, dx.z);
                             y = y + dv;
-                            steps++;
                             acc_pass++;
-                            if (STEP == STEP_RK45) two_sum_add(th, tl, hstep);
+                            bool clipped = false;
+                            if (STEP == STEP_RK45) {
+                                two_sum_add(th, tl, hstep);
+                                steps++;
+                            } else if (SURR && hstep < A.h) {
+                                // clipped last step: its length goes to t, not to the step count
+                                two_sum_add(th, tl, hstep);
+                                clipped = true;
+                            } else {
+                                steps++;
+                            }
                             // RK45 lands on t_max up to float rounding of the clipped last step
                             float t = (STEP == STEP_RK45) ? th + tl : (float)steps * A.h + (SURR ? th + tl : 0.f);
                             float t_end = (STEP == STEP_RK45) ? A.t_max * (1.0f - 1e-6f) : A.t_max;
-                            done_miss = steps >= A.max_steps || t >= t_end;
+                            done_miss = steps >= A.max_steps || t >= t_end || clipped;
                         }
                     }
                     if (done_fail || done_miss) {

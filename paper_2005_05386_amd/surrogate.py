@@ -82,7 +82,7 @@ class Surrogate:
                          h=float(d["h"]), steps=int(d["steps"]), samples=int(d["samples"]))
 
 
-def train(tracer, kappa, samples=10_000_000, batch=1024, h=0.01, lr=1e-3, lr_min=1e-5, warmup=200, seed=0,
+def train(tracer, kappa, samples=10_000_000, batch=1024, h=0.01, lr=2e-3, lr_min=1e-5, warmup=200, seed=0,
           n_tab=4097, n_bins=64, n_cal=8192, log_every=500, log=None, sampling=0):
     """Train one network per shape in kappa (all in one grouped launch per
     layer) and calibrate it.  Returns a Surrogate."""

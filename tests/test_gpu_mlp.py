@@ -45,7 +45,7 @@ def test_mlp_forward_backward_match_oracle(env, n, batch):
     p32 = p.astype(np.float32).astype(np.float64)
     for i in range(n):
         yr, _ = mlp.forward(p32[i], x[i].astype(np.float64), bf16=True)
-        assert np.abs(y[i] - yr).max() <= 2e-3 * max(1.0, np.abs(yr).max()), (i, np.abs(y[i] - yr).max())
+        assert np.abs(y[i] - yr).max() <= 1e-4 * max(1.0, np.abs(yr).max()), (i, np.abs(y[i] - yr).max())
         gr = mlp.backward(p32[i], x[i].astype(np.float64), dy[i].astype(np.float64), bf16=True)
         for blk, (a, b) in enumerate(zip(mlp.split(g[i].astype(np.float64)), mlp.split(gr))):
             err = np.abs(a - b).max()

@@ -94,14 +94,15 @@ def test_grouped_forward_matches_oracle(env, rows):
             continue
         yr, _ = mlp.forward(p[g], x[off:off + r].astype(np.float64), bf16=True)
         err = np.abs(y[off:off + r] - yr).max()
-        assert err <= 2e-3 * max(1.0, np.abs(yr).max()), (g, err)
+        assert err <= 1e-4 * max(1.0, np.abs(yr).max()), (g, err)
         off += r
     # same rounding points as the training forward
     if len(set(r for r in rows if r)) == 1 and all(rows):
         B = rows[0]
         work = tr.mlp_work(n, B)
         yl = tr.mlp_fwd(pb, pt, torch.tensor(x.reshape(n, B, 6), device="cuda"), work).cpu().numpy()
-        assert np.abs(yl.reshape(-1, 6) - y).max() <= 1e-4 * max(1.0, np.abs(yl).max())
+        # the fused kernel repeats the training forward's arithmetic exactly
+        assert np.array_equal(yl.reshape(-1, 6), y)
 
 
 def test_calibration_is_the_decoded_maximum(env):
@@ -153,7 +154,7 @@ def trained(env):
     wl = _scene_three_bumps()
     kappa, net = surrogate.shapes_of(wl["metric"]["bumps"][0])
     say("training %d networks" % len(kappa))
-    model = surrogate.train(tr, kappa, samples=1_500_000, batch=1024, h=0.01, seed=1, log=say)
+    model = surrogate.train(tr, kappa, samples=3_000_000, batch=1024, h=0.01, seed=1, log=say)
     say("trained in %.1f s, loss %s" % (model.train_s, model.losses[-1]))
     return wl, model, net
 
@@ -198,8 +199,9 @@ def test_surrogate_trace_matches_oracle(env, trained):
     assert st["accepted"] > 0
     ref = oracle.Oracle(wl["metric"], wl["scene"]).trace(wl["camera"], wl["rule"])
     rep = compare(out, ref)
-    say(rep)
-    assert_parity(rep)
+    say("vs oracle", rep)
     plain, st0 = _trace(rt, tr, wl, 0)
+    say("vs plain GPU RK4", compare(out, plain))
     say("ray steps plain %d surrogate %d" % (st0["ray_steps"], st["ray_steps"]))
+    assert_parity(rep)
     assert st["ray_steps"] < st0["ray_steps"]

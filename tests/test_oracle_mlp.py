@@ -54,3 +54,20 @@ def test_bf16_emulation_is_close_to_fp64():
     y64, _ = mlp.forward(p, x)
     y16, _ = mlp.forward(p, x, bf16=True)
     assert np.abs(y16 - y64).max() <= 0.05 * np.abs(y64).max()
+
+
+def test_split_bf16_product_is_near_fp32():
+    """Three-term split bf16 (Ah Bh + Ah Bl + Al Bh) recovers the product to
+    ~2^-16 relative, where a single bf16 rounding leaves ~2^-9."""
+    rng = np.random.default_rng(7)
+    A = rng.normal(size=(64, 256))
+    B = rng.normal(size=(256, 32))
+    ref = A @ B
+    norm = np.abs(A) @ np.abs(B)
+    e3 = np.abs(mlp.split_product(A, B) - ref) / norm
+    e1 = np.abs(mlp.bf16_round(A) @ mlp.bf16_round(B) - ref) / norm
+    assert e3.max() < 2.0 ** -14
+    assert e1.max() > 2.0 ** -11
+    hi, lo = mlp.split_bf16(A)
+    assert np.array_equal(mlp.bf16_round(hi), hi) and np.array_equal(mlp.bf16_round(lo), lo)
+    assert np.abs(hi + lo - A).max() <= 2.0 ** -16 * np.abs(A).max()
