@@ -192,8 +192,11 @@ def _frame_error(out, ref, tol=1e-3):
     err = np.abs(out["hit"] - ref["hit"]).max(axis=1)
     bad = (~same) | (err > tol)
     e = err[same]
+    # over all pixels, an id mismatch counting as an infinite error
+    e_all = np.where(same, err, np.inf)
     return {"frac_within_tol": float(1.0 - bad.mean()), "frac_id_equal": float(same.mean()),
             "p999_hit_err": float(np.quantile(e, 0.999)) if e.size else 0.0,
+            "p999_err_all_pixels": float(np.quantile(e_all, 0.999)),
             "max_hit_err": float(e.max()) if e.size else 0.0}
 
 
@@ -254,16 +257,18 @@ def bench_surrogate(args, wl, torch, rt):
     print("[bench] rk4 %.2f ms, surrogate %.2f ms, crossings %d accepted %d, %s" % (
         rk4_ms, sur_ms, sur_st["crossings"], sur_st["accepted"], json.dumps(sur_err)), flush=True)
 
-    # equal error: the largest RK4 step (same t_max) whose frame is at least as close to the h = 0.005 frame
+    # equal error: the largest RK4 step whose frame is at least as close to the h = 0.005 frame, by the
+    # 99.9th percentile over all pixels of the hit error (an id mismatch counts as infinite); steps that
+    # divide t_max, so that misses end at the same t
     eq = []
-    for hh in (0.0075, 0.01, 0.015, 0.02, 0.03, 0.04):
+    for hh in (0.00625, 0.008, 0.01, 0.0125, 0.016, 0.02, 0.025, 0.04):
         r2 = dict(rule, h=float(np.float32(hh)), max_steps=int(round(rule["t_max"] / hh)))
         tr.trace_into(cam, r2, r2["max_steps"], out)
         ms2, st2, _ = _timed_frames(tr, cam, r2, out, max(1, args.steps // 2), torch)
         e2 = _frame_error(rt.to_numpy(out), ref)
         eq.append({"h": hh, "ms": ms2, **e2})
         print("[bench] rk4 h=%g: %.2f ms %s" % (hh, ms2, json.dumps(e2)), flush=True)
-    ok = [e for e in eq if e["frac_within_tol"] >= sur_err["frac_within_tol"]]
+    ok = [e for e in eq if e["p999_err_all_pixels"] <= sur_err["p999_err_all_pixels"]]
     best = max(ok, key=lambda e: e["h"]) if ok else None
 
     mlp_flops = fwd_flops * sur_st["crossings"]
