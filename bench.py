@@ -55,10 +55,10 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, pass_steps):
     """HBM bytes per pass-kernel launch from the committed PMC summary of
-    this workload, or None when there is none or the kernel sources changed
-    since the counters were taken."""
+    this workload, or None when there is none, or the kernel sources or the
+    pass length changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_k_trace_pass_%s.md" % workload)
     if not os.path.exists(path):
         return None
@@ -68,7 +68,7 @@ def measured_traffic(workload):
             if ":" in ln and ln.startswith("- "):
                 k, v = ln[2:].split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_digest():
+    if vals.get("kernel_source_sha256_16") != kernel_source_digest() or vals.get("pass_steps") != str(pass_steps):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -228,7 +228,9 @@ def bench_surrogate(args, wl, torch, rt):
     import numpy as np
 
     from paper_2005_05386_amd import surrogate as S
-    cam, rule = wl["camera"], dict(wl["rule"], pass_steps=args.surr_pass_steps)
+    # RK4 frames with the workload's own pass length; surrogate frames with
+    # shorter passes (a parked ray resumes at the next pass)
+    cam, rule = wl["camera"], dict(wl["rule"])
     tr = rt.Tracer(0)
     tr.set_metric(wl["metric"])
     tr.set_scene(wl["scene"])
@@ -248,7 +250,7 @@ def bench_surrogate(args, wl, torch, rt):
         tr.trace_into(cam, rule, rule["max_steps"], out)
     rk4_ms, rk4_st, rk4_k = _timed_frames(tr, cam, rule, out, args.steps, torch)
     ref = rt.to_numpy(out)
-    srule = dict(rule, flags=rt.FLAG_SURROGATE)
+    srule = dict(rule, flags=rt.FLAG_SURROGATE, pass_steps=args.surr_pass_steps)
     for _ in range(args.warmup):
         tr.trace_into(cam, srule, rule["max_steps"], out)
     sur_ms, sur_st, sur_k = _timed_frames(tr, cam, srule, out, args.steps, torch)
@@ -279,7 +281,8 @@ def bench_surrogate(args, wl, torch, rt):
         "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"], "h": rule["h"],
                    "max_steps": rule["max_steps"], "bumps": int(wl["metric"]["bumps"].shape[1]),
-                   "pass_steps": rule["pass_steps"], "probe_tol": args.surr_tol},
+                   "pass_steps_rk4": rule["pass_steps"], "pass_steps_surrogate": args.surr_pass_steps,
+                   "probe_tol": args.surr_tol},
         "rk4_ms_per_frame": rk4_ms, "rk4_rays_per_s": n_rays / (rk4_ms / 1e3),
         "speedup_vs_rk4": rk4_ms / sur_ms,
         "crossings": sur_st["crossings"], "accepted": sur_st["accepted"],
@@ -309,7 +312,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--surr-samples", type=int, default=10_000_000, help="training crossings per bump shape")
     ap.add_argument("--surr-tol", type=float, default=1e-3, help="probe tolerance on the hit error")
-    ap.add_argument("--surr-pass-steps", type=int, default=64, help="steps per pass in surrogate traces")
+    ap.add_argument("--surr-pass-steps", type=int, default=1024, help="steps per pass in surrogate traces")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run plain copies of this many bytes")
     args = ap.parse_args()
     if args.copy_probe:
@@ -381,7 +384,7 @@ def main():
                    "spheres": int(len(wl["scene"]["spheres"]))},
         "ray_steps_per_s": work["ray_steps"] / (ms / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, rule["pass_steps"]),
                      "kernel": "k_trace_pass", "flops_per_trace": flops,
                      "kernel_ms_per_launch": pass_ms / max(1, n_pass_launches),
                      "frac_of_nonpacked_peak": achieved / FP32_PEAK_NONPACKED},

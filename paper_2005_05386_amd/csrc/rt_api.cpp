@@ -51,7 +51,8 @@ struct rt_ctx {
     bool traced = false;
     int last_passes = 0;
     bool last_timed = false;
-    bool last_surr = false;
+    bool last_surr = false;       // the last trace ran the crossing stages
+    bool last_surr_flag = false;  // it was asked for the surrogate
     std::vector<hipEvent_t> ev;  // timing events of the last trace
     // differentiation
     bool adj_valid = false;
@@ -518,8 +519,6 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
             return fail(c, RT_ESTATE, "rt_trace: surrogate net_of_bump does not match the metric's bump count");
     }
     int n_passes = (max_steps + r->pass_steps - 1) / r->pass_steps;
-    // each learned crossing ends a ray's pass early: allow extra passes
-    if (surr) n_passes = std::min(n_passes + 1 + std::max(16, 2 * c->n_bumps), rti::MAX_PASSES_API);
     if (n_passes > rti::MAX_PASSES_API)
         return fail(c, RT_EINVAL, "rt_trace: max_steps / pass_steps must be <= " + std::to_string(rti::MAX_PASSES_API));
     if (!o->hit || !o->t || !o->id || !o->dir) return fail(c, RT_EINVAL, "rt_trace: NULL output pointer");
@@ -527,6 +526,15 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
 
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    bool use_surr = surr;
+    if (surr) {
+        rt_status st0 = surr_prepare(c);
+        if (st0 != RT_OK) return st0;
+        // no eligible bump: no ray can park, the plain kernels give the same frame
+        if (c->surr_eligible == 0) use_surr = false;
+    }
+    // each learned crossing ends a ray's pass early: allow extra passes
+    if (use_surr) n_passes = std::min(n_passes + 1 + std::max(16, 2 * c->n_bumps), rti::MAX_PASSES_API);
     const int tiles_x = (cam->width + 7) / 8, tiles_y = (cam->height + 7) / 8;
     const int64_t T = (int64_t)tiles_x * tiles_y * 64;
     int64_t cap = T * c->n_sets;
@@ -608,12 +616,11 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
         a.tape_hit = (float *)tape + (size_t)cap * a.n_ckpt * 9;
     }
 
-    a.surr = surr ? 1 : 0;
+    a.surr = use_surr ? 1 : 0;
     a.n_passes = n_passes;
     a.xctl = c->d_ctr + rti::CTR_PASS0 + n_passes * rti::CTR_PASS_WORDS;
     rti::SurrArgs S = c->surr;
-    if (surr) {
-        if ((st = surr_prepare(c)) != RT_OK) return st;
+    if (use_surr) {
         if ((st = ensure_xbuf(c, cap)) != RT_OK) return st;
         char *xb = (char *)c->d_xbuf;
         a.surr_sb = (const float4 *)c->d_surr_sb;
@@ -644,13 +651,14 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
         }
     }
     e = rti::launch_trace(a, c->dd, n_passes, (int)grid, rgrid, s, timed ? c->ev.data() : nullptr,
-                          surr ? &S : nullptr, 2 * c->n_cu);
+                          use_surr ? &S : nullptr, 2 * c->n_cu);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     c->last_stream = s;
     c->traced = true;
     c->last_passes = n_passes;
     c->last_timed = timed;
-    c->last_surr = surr;
+    c->last_surr = use_surr;
+    c->last_surr_flag = surr;
     if (tape) {
         c->adj_args = a;
         c->adj_tape = tape;
@@ -1031,7 +1039,7 @@ rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
     out->passes = c->last_passes;
     out->crossings = v[rti::ST_XING];
     out->accepted = v[rti::ST_XACC];
-    out->eligible = c->last_surr ? c->surr_eligible : 0;
+    out->eligible = c->last_surr_flag ? c->surr_eligible : 0;
     if (c->last_timed) {
         // events: 0 before reset, 1 after reset, 2+p after pass p, 2+np after
         // refine, 2np+2+p after the compaction that precedes pass p (p >= 1),

@@ -136,12 +136,14 @@ def test_calibration_is_the_decoded_maximum(env):
 # ---------------------------------------------------------------- traces
 def _scene_three_bumps(width=96, height=64):
     """Three isolated bumps in view (kappa 0.4, 1.0, 1.6), a sphere and the
-    plane y = -1 outside their support spheres, and one bump whose support
-    the plane cuts (not eligible)."""
+    plane y = -1 outside their support spheres, one bump whose support the
+    plane cuts (not eligible), and one eligible bump behind the camera that
+    no ray reaches."""
     bumps = [[0.06, -1.5, 0.5, 1.5, 0.15],
              [-0.15, 0.0, 0.2, 1.5, 0.15],
              [0.32, 1.7, 0.5, 2.2, 0.2],
-             [0.2, 0.3, -1.2, 3.0, 0.2]]
+             [0.2, 0.3, -1.2, 3.0, 0.2],
+             [0.06, 0.0, 0.0, -7.0, 0.15]]
     return dict(camera=W.camera(width, height, vfov_deg=40.0),
                 metric=W.metric(W.GRAPH_GAUSS, [bumps]),
                 scene=W.scene(spheres=[[0.0, 1.6, 5.0, 0.6]], planes=W.PLANE_Y_MINUS_1),
@@ -168,8 +170,9 @@ def _trace(rt, tr, wl, flags=0):
 
 
 def test_eligibility_and_flag_off_are_exact(env, trained):
-    """Without the flag the trace is the plain one; with it, rays that never
-    park (ineligible bumps only) are bit-identical to the plain trace."""
+    """Eligibility follows the support-sphere rules, and rays that never park
+    are bit-identical to the plain trace (the surrogate kernel variant runs:
+    one eligible bump lies behind the camera)."""
     rt, surrogate, torch, tr = env
     wl, model, net = trained
     say("eligibility")
@@ -177,10 +180,13 @@ def test_eligibility_and_flag_off_are_exact(env, trained):
     tr.set_scene(wl["scene"])
     surrogate.load(tr, model, net, tol=1e-3)
     plain, _ = _trace(rt, tr, wl, 0)
+    _, st_all = _trace(rt, tr, wl, rt.FLAG_SURROGATE)
+    assert st_all["eligible"] == 4          # all but the bump the plane cuts
     nob = np.array(net)
-    nob[:3] = -1    # only the plane-cut bump keeps a network: nothing eligible
+    nob[:3] = -1    # keep the plane-cut bump and the one behind the camera
     tr.surrogate_load(model.w_bf16, model.params, model.scale, model.arc, model.err, nob, 1e-3)
     surr, st = _trace(rt, tr, wl, rt.FLAG_SURROGATE)
+    assert st["eligible"] == 1
     assert st["crossings"] == 0
     for k in ("hit", "t", "id", "dir"):
         assert np.array_equal(plain[k], surr[k]), k
