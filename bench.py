@@ -251,6 +251,10 @@ def bench_surrogate(args, wl, torch, rt):
     rk4_ms, rk4_st, rk4_k = _timed_frames(tr, cam, rule, out, args.steps, torch)
     ref = rt.to_numpy(out)
     srule = dict(rule, flags=rt.FLAG_SURROGATE, pass_steps=args.surr_pass_steps)
+    tr.trace_into(cam, srule, rule["max_steps"], out)
+    if tr.stats()["eligible"] == 0:
+        # nothing eligible: the library runs the plain kernels, keep the plain pass length
+        srule["pass_steps"] = rule["pass_steps"]
     for _ in range(args.warmup):
         tr.trace_into(cam, srule, rule["max_steps"], out)
     sur_ms, sur_st, sur_k = _timed_frames(tr, cam, srule, out, args.steps, torch)
@@ -281,7 +285,7 @@ def bench_surrogate(args, wl, torch, rt):
         "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"], "h": rule["h"],
                    "max_steps": rule["max_steps"], "bumps": int(wl["metric"]["bumps"].shape[1]),
-                   "pass_steps_rk4": rule["pass_steps"], "pass_steps_surrogate": args.surr_pass_steps,
+                   "pass_steps_rk4": rule["pass_steps"], "pass_steps_surrogate": srule["pass_steps"],
                    "probe_tol": args.surr_tol},
         "rk4_ms_per_frame": rk4_ms, "rk4_rays_per_s": n_rays / (rk4_ms / 1e3),
         "speedup_vs_rk4": rk4_ms / sur_ms,
