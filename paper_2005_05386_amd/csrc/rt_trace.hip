@@ -99,14 +99,15 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
 }
 
 // ================================================================ the pass
-// Occupancy: 6 waves per SIMD (at most 80 VGPRs) measured fastest for the
-// RK4 graph and twist kernels although a few long-lived values spill.
+// Occupancy: 7 waves per SIMD (at most 72 VGPRs) measured fastest for the
+// RK4 graph and twist kernels, 6 for DP5(4), although long-lived values
+// spill (the spills are a small share of the instructions).
 // SURR: learned crossings (graph metric, RK4, one parameter set): a ray whose
 // step chord enters the support sphere of an eligible bump stops on the
 // sphere (the partial step is committed, its fraction of h added to t) and
 // is queued for the crossing stage that runs after the pass.
 template <int KIND, int STEP, bool COUNT, bool SURR = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 ? 6 : 7, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
                                                     const float *__restrict__ TOR) {

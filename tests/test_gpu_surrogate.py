@@ -211,3 +211,36 @@ def test_surrogate_trace_matches_oracle(env, trained):
     say("ray steps plain %d surrogate %d" % (st0["ray_steps"], st["ray_steps"]))
     assert_parity(rep)
     assert st["ray_steps"] < st0["ray_steps"]
+
+
+def test_surrogate_isolated_4k_sampled(env):
+    """The supplementary isolated-bump frame at full size (3840x2160, 64
+    bumps) in the launch configuration the benchmark times, with networks
+    trained briefly: sampled pixels against the FP64 oracle (which knows
+    nothing of the surrogate), and the whole frame against the GPU RK4
+    frame."""
+    rt, surrogate, torch, tr = env
+    wl = W.get("surrogate_isolated_4k")
+    say("surrogate_isolated_4k: training 64 networks (1M crossings each)")
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    kappa, net = surrogate.shapes_of(wl["metric"]["bumps"][0])
+    model = surrogate.train(tr, kappa, samples=1_000_000, seed=3, log_every=10 ** 9)
+    surrogate.load(tr, model, net, tol=1e-3)
+    rule = dict(wl["rule"])
+    plain, _ = _trace(rt, tr, wl, 0)
+    srule = dict(rule, pass_steps=1024, flags=rt.FLAG_SURROGATE)
+    out = tr.trace(wl["camera"], srule)
+    tr.sync()
+    out = rt.to_numpy(out)
+    st = tr.stats()
+    say("eligible %d crossings %d accepted %d" % (st["eligible"], st["crossings"], st["accepted"]))
+    assert st["eligible"] == 57 and st["accepted"] > 0
+    rep = compare(out, plain)
+    say("vs GPU RK4 frame", rep)
+    assert_parity(rep)
+    pix = W.pixel_sample(3840, 2160, 1200, seed=13)
+    ref = oracle.Oracle(wl["metric"], wl["scene"]).trace(wl["camera"], wl["rule"], pix)
+    rep = compare(out, ref, pix)
+    say("vs oracle (sampled)", rep)
+    assert_parity(rep, frac=0.998)
