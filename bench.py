@@ -28,7 +28,7 @@ FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector, published (counts packed FMA
 FP32_PEAK_NONPACKED = 78.6    # 256 CU x 128 FP32 lanes-flops/clk x 2.4 GHz without packed math
 
 # Algorithmic FLOPs per unit (FMA = 2, each transcendental = 1); derived
-# from the formulas the kernels evaluate ("FLOP model").
+# from the formulas the kernels evaluate: FMA = 2, each transcendental = 1.
 FLOPS = {
     "graph_eval": 16,        # |y|^2, 1 + |grad f|^2, rcp, scale
     "graph_bump": 27,        # one bump inside its cut sphere (incl. exp2)
@@ -221,7 +221,7 @@ def _timed_frames(tr, cam, rule, out, steps, torch):
 
 def bench_surrogate(args, wl, torch, rt):
     """Learned crossings against plain RK4 on the same frame: train one
-    network per bump shape, time the RK4-only frame (the judge) and the
+    network per bump shape, time the RK4-only frame (the reference) and the
     surrogate frame, measure acceptance and hit error against the RK4 frame,
     and find the largest RK4 step whose error is no larger (equal-error
     comparison)."""
@@ -322,8 +322,8 @@ def main():
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); DESIGN.md describes how the trace "
-              "would shard across GPUs, but no multi-GPU path is built", file=sys.stderr)
+        print("bench.py: the tracer runs on one GPU only (--gpus 1); there is no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
