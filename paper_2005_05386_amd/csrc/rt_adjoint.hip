@@ -35,16 +35,38 @@ struct ThetaBar {
     __device__ __forceinline__ void add(int b, int j, float v) { tb[(b * 5 + j) * 64 + lane] += v; }
 };
 
+// Wave-uniform mask of the bumps whose cut sphere meets the box of the
+// active lanes' positions grown by margin (same test as the trace's
+// culling).  Must be called by the whole wave.  Bumps outside the mask
+// contribute exactly zero at every point in the box, so walking the mask
+// gives the same sums as walking every bump.
+__device__ __forceinline__ uint64_t cull_mask(const float4 *__restrict__ B, int nb, V3<float> p, bool active,
+                                              float margin) {
+    const float inf = __builtin_huge_valf();
+    const float lo[3] = {wave_min(active ? p.x : inf) - margin, wave_min(active ? p.y : inf) - margin,
+                         wave_min(active ? p.z : inf) - margin};
+    const float hi[3] = {wave_max(active ? p.x : -inf) + margin, wave_max(active ? p.y : -inf) + margin,
+                         wave_max(active ? p.z : -inf) + margin};
+    bool need = false;
+    const int lane = lane_id();
+    if (lane < nb) {
+        const float4 b0 = B[2 * lane], b1 = B[2 * lane + 1];
+        need = box_dist2(b0.x, b0.y, b0.z, lo, hi) <= b1.z;
+    }
+    return ballot(need);
+}
+
 // VJP of the graph acceleration a(p, y) = -grad f (y^T H y) / (1 + |grad f|^2)
-// with every bump of the set (per-lane cut as in the forward).  Adds the
-// cotangents of p and y to pb, yb and those of the bump parameters to T
-// when ACC is set.
+// with the bumps of a wave-uniform mask, in increasing index order (per-lane
+// cut as in the forward).  Adds the cotangents of p and y to pb, yb and
+// those of the bump parameters to T when ACC is set.
 template <bool ACC>
-__device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, int nb, V3<float> p, V3<float> y,
+__device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, uint64_t mask, V3<float> p, V3<float> y,
                                           V3<float> ab, V3<float> &pb, V3<float> &yb, ThetaBar &T) {
     float gx = 0.f, gy = 0.f, gz = 0.f, q = 0.f;
     const float yy = dot(y, y);
-    for (int b = 0; b < nb; ++b) {
+    for (uint64_t m = mask; m; m &= m - 1) {
+        const int b = __builtin_ctzll(m);
         GraphAccum G{gx, gy, gz, q};
         graph_bump_f32(B[2 * b], B[2 * b + 1], p, y, yy, G);
         gx = G.gx;
@@ -58,7 +80,8 @@ __device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, int nb, 
     // a = -(q / D) g:  gbar = -(q/D) abar + (2 q / D^2)(g . abar) g,  qbar = -(g . abar)/D
     const float qbar = -ga * invD;
     const V3<float> gbar = axpy(2.0f * q * ga * invD * invD, g, (-q * invD) * ab);
-    for (int b = 0; b < nb; ++b) {
+    for (uint64_t m = mask; m; m &= m - 1) {
+        const int b = __builtin_ctzll(m);
         const float4 b0 = B[2 * b], b1 = B[2 * b + 1];
         const V3<float> d = mk(p.x - b0.x, p.y - b0.y, p.z - b0.z);
         const float r2 = dot(d, d);
@@ -90,9 +113,9 @@ __device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, int nb, 
 // become cotangents of p and y (returned in Xb, Vb), of the bump
 // parameters (ACC) and of the step size (returned).
 template <bool ACC>
-__device__ __forceinline__ float rk4_vjp(const float4 *__restrict__ B, int nb, V3<float> p, V3<float> y, float sg,
-                                         V3<float> &Xb, V3<float> &Vb, ThetaBar &T) {
-    Acc32<KIND_GRAPH, false> acc{B, nb >= 64 ? ~0ull : ((1ull << nb) - 1ull), 0.f, 0.f, nullptr, nullptr};
+__device__ __forceinline__ float rk4_vjp(const float4 *__restrict__ B, uint64_t mask, V3<float> p, V3<float> y,
+                                         float sg, V3<float> &Xb, V3<float> &Vb, ThetaBar &T) {
+    Acc32<KIND_GRAPH, false> acc{B, mask, 0.f, 0.f, nullptr, nullptr};
     const float c1 = 0.5f * sg;
     V3<float> P[4], Y[4], K[4];
     P[0] = p;
@@ -122,7 +145,7 @@ __device__ __forceinline__ float rk4_vjp(const float4 *__restrict__ B, int nb, V
 #pragma unroll
     for (int i = 3; i >= 0; --i) {
         V3<float> Pb = mk(0.f, 0.f, 0.f), Ybi = mk(0.f, 0.f, 0.f);
-        graph_vjp<ACC>(B, nb, P[i], Y[i], Kb[i], Pb, Ybi, T);
+        graph_vjp<ACC>(B, mask, P[i], Y[i], Kb[i], Pb, Ybi, T);
         Yb[i] = Yb[i] + Ybi;
         pb = pb + Pb;
         if (i > 0) {
@@ -197,6 +220,10 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
     const int ck = A.ckpt_every;
     float *scr = J.scratch + (int64_t)blockIdx.x * ck * 9 * 64 + lane;
     ThetaBar T{tb_mem, lane};
+    // culling window: CULL steps (plus the stages of one more) of Euclidean
+    // length <= h each, since g >= I keeps a g-unit velocity at |y| <= 1
+    constexpr int CULL = 16;
+    const float margin = (float)((CULL + 1) * (double)A.h * 1.02 + 1e-4);
 
     for (int chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
         const int set = chunk / tiles;
@@ -227,24 +254,27 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
         }
         bool act = obj >= 0 && (lam.x != 0.f || lam.y != 0.f || lam.z != 0.f);
         V3<float> xb = mk(0.f, 0.f, 0.f), yb = xb;
+        // bumps a partial step from the hit records can reach (a g-unit
+        // velocity moves at most h per step, g >= I)
+        const uint64_t mask_hit = cull_mask(Bs, nb, xh + xl, act, margin);
         if (act) {
             // ---- terminal condition through the implicit hit
             const V3<float> p = xh + xl;
             const float sg = sstar * A.h;
             V3<float> dx, dv;
-            Acc32<KIND_GRAPH, false> accall{Bs, nb >= 64 ? ~0ull : ((1ull << nb) - 1ull), 0.f, 0.f, nullptr, nullptr};
-            step_rk4<float>(accall, p, y, sg, dx, dv);
+            Acc32<KIND_GRAPH, false> acch{Bs, mask_hit, 0.f, 0.f, nullptr, nullptr};
+            step_rk4<float>(acch, p, y, sg, dx, dv);
             const V3<float> hit = p + dx;
             const V3<float> gF = obj_grad(A, SPH, PLN, TOR, obj, hit);
             V3<float> Xa = lam, Va = mk(0.f, 0.f, 0.f);
-            const float sa = rk4_vjp<false>(Bs, nb, p, y, sg, Xa, Va, T);
+            const float sa = rk4_vjp<false>(Bs, mask_hit, p, y, sg, Xa, Va, T);
             V3<float> Xf = gF, Vf = mk(0.f, 0.f, 0.f);
-            const float sf = rk4_vjp<false>(Bs, nb, p, y, sg, Xf, Vf, T);
+            const float sf = rk4_vjp<false>(Bs, mask_hit, p, y, sg, Xf, Vf, T);
             if (fabsf(sf) > 1e-20f) {
                 const float c = sa / sf;
                 xb = axpy(-c, gF, lam);
                 yb = mk(0.f, 0.f, 0.f);
-                (void)rk4_vjp<true>(Bs, nb, p, y, sg, xb, yb, T);
+                (void)rk4_vjp<true>(Bs, mask_hit, p, y, sg, xb, yb, T);
             } else {
                 act = false;  // tangential hit: the hit point does not vary smoothly
             }
@@ -259,13 +289,18 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
             int lmax = len;
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
+            // recompute the segment's states into scratch (the forward's own
+            // step code; bumps culled per window of CULL steps, exact)
+            V3<float> h0 = mk(0.f, 0.f, 0.f), l0 = h0, y0 = h0;
             if (len > 0) {
                 const float *cp = A.tape_ck + (((int64_t)(id >> 6) * A.n_ckpt + seg) * 9) * 64 + (id & 63);
-                V3<float> h0 = mk(cp[0], cp[64], cp[128]), l0 = mk(cp[192], cp[256], cp[320]),
-                          y0 = mk(cp[384], cp[448], cp[512]);
-                Acc32<KIND_GRAPH, false> accall{Bs, nb >= 64 ? ~0ull : ((1ull << nb) - 1ull), 0.f, 0.f, nullptr,
-                                                nullptr};
-                for (int j = 0; j < len; ++j) {
+                h0 = mk(cp[0], cp[64], cp[128]);
+                l0 = mk(cp[192], cp[256], cp[320]);
+                y0 = mk(cp[384], cp[448], cp[512]);
+            }
+            uint64_t wm = 0;
+            for (int j = 0; j < lmax; ++j) {
+                if (j < len) {
                     float *sp = scr + (int64_t)j * 9 * 64;
                     sp[0] = h0.x;
                     sp[64] = h0.y;
@@ -276,9 +311,13 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
                     sp[384] = y0.x;
                     sp[448] = y0.y;
                     sp[512] = y0.z;
+                }
+                if (j + 1 < lmax) {
+                    if (j % CULL == 0) wm = cull_mask(Bs, nb, h0 + l0, j + 1 < len, margin);
                     if (j + 1 < len) {
+                        Acc32<KIND_GRAPH, false> accw{Bs, wm, 0.f, 0.f, nullptr, nullptr};
                         V3<float> dx, dv;
-                        step_rk4<float>(accall, h0 + l0, y0, A.h, dx, dv);
+                        step_rk4<float>(accw, h0 + l0, y0, A.h, dx, dv);
                         two_sum_add(h0.x, l0.x, dx.x);
                         two_sum_add(h0.y, l0.y, dx.y);
                         two_sum_add(h0.z, l0.z, dx.z);
@@ -286,13 +325,22 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
                     }
                 }
             }
+            // reverse the segment's steps; a window of at most CULL steps
+            // ending at j (going backward) stays within CULL steps of x_j.
+            // A window starts at every multiple of CULL and wherever a lane's
+            // steps begin (j = len - 1), so every lane is in the box of the
+            // window it is reversed under.
             for (int j = lmax - 1; j >= 0; --j) {
-                if (j < len) {
+                const bool has = j < len;
+                V3<float> ph = mk(0.f, 0.f, 0.f), pl = ph, vy = ph;
+                if (has) {
                     const float *sp = scr + (int64_t)j * 9 * 64;
-                    V3<float> ph = mk(sp[0], sp[64], sp[128]), pl = mk(sp[192], sp[256], sp[320]),
-                              vy = mk(sp[384], sp[448], sp[512]);
-                    (void)rk4_vjp<true>(Bs, nb, ph + pl, vy, A.h, xb, yb, T);
+                    ph = mk(sp[0], sp[64], sp[128]);
+                    pl = mk(sp[192], sp[256], sp[320]);
+                    vy = mk(sp[384], sp[448], sp[512]);
                 }
+                if (j % CULL == CULL - 1 || ballot(j == len - 1)) wm = cull_mask(Bs, nb, ph + pl, has, margin);
+                if (has) (void)rk4_vjp<true>(Bs, wm, ph + pl, vy, A.h, xb, yb, T);
             }
         }
         // ---- the initial velocity y0 = d / sqrt(|d|^2 + (grad f . d)^2) at the eye
