@@ -60,21 +60,27 @@ __device__ __forceinline__ uint64_t cull_mask(const float4 *__restrict__ B, int 
 // with the bumps of a wave-uniform mask, in increasing index order (per-lane
 // cut as in the forward).  Adds the cotangents of p and y to pb, yb and
 // those of the bump parameters to T when ACC is set.
-template <bool ACC>
-__device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, uint64_t mask, V3<float> p, V3<float> y,
-                                          V3<float> ab, V3<float> &pb, V3<float> &yb, ThetaBar &T) {
-    float gx = 0.f, gy = 0.f, gz = 0.f, q = 0.f;
+// The sums grad f and q of the acceleration at (p, y), bumps of the mask in
+// increasing index order (the order of the trace's walk).
+__device__ __forceinline__ GraphAccum graph_sums(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
+                                                 V3<float> y) {
+    GraphAccum G{0.f, 0.f, 0.f, 0.f};
     const float yy = dot(y, y);
     for (uint64_t m = mask; m; m &= m - 1) {
         const int b = __builtin_ctzll(m);
-        GraphAccum G{gx, gy, gz, q};
         graph_bump_f32(B[2 * b], B[2 * b + 1], p, y, yy, G);
-        gx = G.gx;
-        gy = G.gy;
-        gz = G.gz;
-        q = G.q;
     }
-    const V3<float> g = mk(gx, gy, gz);
+    return G;
+}
+
+// S: the sums at (p, y) from graph_sums.
+template <bool ACC>
+__device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, uint64_t mask, V3<float> p, V3<float> y,
+                                          const GraphAccum &S, V3<float> ab, V3<float> &pb, V3<float> &yb,
+                                          ThetaBar &T) {
+    const float yy = dot(y, y);
+    const float q = S.q;
+    const V3<float> g = mk(S.gx, S.gy, S.gz);
     const float invD = 1.0f / (1.0f + dot(g, g));
     const float ga = dot(g, ab);
     // a = -(q / D) g:  gbar = -(q/D) abar + (2 q / D^2)(g . abar) g,  qbar = -(g . abar)/D
@@ -115,21 +121,27 @@ __device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, uint64_t
 template <bool ACC>
 __device__ __forceinline__ float rk4_vjp(const float4 *__restrict__ B, uint64_t mask, V3<float> p, V3<float> y,
                                          float sg, V3<float> &Xb, V3<float> &Vb, ThetaBar &T) {
-    Acc32<KIND_GRAPH, false> acc{B, mask, 0.f, 0.f, nullptr, nullptr};
+    // stage sums kept for the VJPs (the accelerations are finished from the
+    // same sums as in the trace, so the stages are the forward's bit for bit)
     const float c1 = 0.5f * sg;
     V3<float> P[4], Y[4], K[4];
+    GraphAccum G[4];
     P[0] = p;
     Y[0] = y;
-    acc(P[0], Y[0], K[0]);
+    G[0] = graph_sums(B, mask, P[0], Y[0]);
+    K[0] = graph_finish(G[0]);
     P[1] = axpy(c1, Y[0], p);
     Y[1] = axpy(c1, K[0], y);
-    acc(P[1], Y[1], K[1]);
+    G[1] = graph_sums(B, mask, P[1], Y[1]);
+    K[1] = graph_finish(G[1]);
     P[2] = axpy(c1, Y[1], p);
     Y[2] = axpy(c1, K[1], y);
-    acc(P[2], Y[2], K[2]);
+    G[2] = graph_sums(B, mask, P[2], Y[2]);
+    K[2] = graph_finish(G[2]);
     P[3] = axpy(sg, Y[2], p);
     Y[3] = axpy(sg, K[2], y);
-    acc(P[3], Y[3], K[3]);
+    G[3] = graph_sums(B, mask, P[3], Y[3]);
+    K[3] = graph_finish(G[3]);
     const float h6 = sg * (1.0f / 6.0f);
     const V3<float> sx = Y[0] + 2.0f * (Y[1] + Y[2]) + Y[3];
     const V3<float> sv = K[0] + 2.0f * (K[1] + K[2]) + K[3];
@@ -145,7 +157,7 @@ __device__ __forceinline__ float rk4_vjp(const float4 *__restrict__ B, uint64_t 
 #pragma unroll
     for (int i = 3; i >= 0; --i) {
         V3<float> Pb = mk(0.f, 0.f, 0.f), Ybi = mk(0.f, 0.f, 0.f);
-        graph_vjp<ACC>(B, mask, P[i], Y[i], Kb[i], Pb, Ybi, T);
+        graph_vjp<ACC>(B, mask, P[i], Y[i], G[i], Kb[i], Pb, Ybi, T);
         Yb[i] = Yb[i] + Ybi;
         pb = pb + Pb;
         if (i > 0) {
