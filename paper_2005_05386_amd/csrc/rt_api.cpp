@@ -779,9 +779,9 @@ static rt_status mlp_check(rt_ctx *c, int n_nets, int batch, const void *w, void
 
 rt_status rt_mlp_fwd(rt_ctx *c, int n_nets, int batch, const uint16_t *w_bf16, const float *params, const float *x,
                      float *y, void *work, size_t work_bytes, void *stream) {
+    if (c && (!params || !x || !y)) return fail(c, RT_EINVAL, "rt_mlp_fwd: NULL argument");
     rt_status st = mlp_check(c, n_nets, batch, w_bf16, work, work_bytes, "rt_mlp_fwd");
     if (st != RT_OK) return st;
-    if (!params || !x || !y) return fail(c, RT_EINVAL, "rt_mlp_fwd: NULL argument");
     rti::MlpWork w;
     rti::mlp_work_carve(work, n_nets, batch, w);
     hipError_t e = rti::mlp_forward(n_nets, batch, (const __bf16 *)w_bf16, params, x, y, w, true, (hipStream_t)stream);
@@ -849,9 +849,9 @@ rt_status rt_mlp_fwd_grouped(rt_ctx *c, int n_nets, const int32_t *rows, const u
 
 rt_status rt_mlp_bwd(rt_ctx *c, int n_nets, int batch, const uint16_t *w_bf16, const float *params, const float *dy,
                      float *grad, void *work, size_t work_bytes, void *stream) {
+    if (c && (!params || !dy || !grad)) return fail(c, RT_EINVAL, "rt_mlp_bwd: NULL argument");
     rt_status st = mlp_check(c, n_nets, batch, w_bf16, work, work_bytes, "rt_mlp_bwd");
     if (st != RT_OK) return st;
-    if (!params || !dy || !grad) return fail(c, RT_EINVAL, "rt_mlp_bwd: NULL argument");
     rti::MlpWork w;
     rti::mlp_work_carve(work, n_nets, batch, w);
     hipError_t e =

@@ -123,3 +123,60 @@ def test_create_errors():
     assert rt.lib().rt_last_error(None)
     assert not h.value
     rt.lib().rt_destroy(None)
+
+
+def test_surrogate_and_mlp_entry_points_validate():
+    """Argument checks of the surrogate and MLP entry points, host-only
+    context (no device work is ever launched)."""
+    rt = _rt()
+    tr = rt.Tracer(-1)
+    L = rt.lib()
+    wl = W.get("single_bump_64")
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    cam, rule = wl["camera"], wl["rule"]
+    # surrogate traces need networks, the graph metric, RK4, one set
+    with pytest.raises(rt.RtError) as e:
+        tr.trace_raw(cam, dict(rule, flags=rt.FLAG_SURROGATE), 10, (16, 16, 16, 16, 0), 0)
+    assert e.value.status == rt.RT_ESTATE
+    with pytest.raises(rt.RtError) as e:
+        tr.trace_raw(cam, dict(rule, kind=W.RK45, flags=rt.FLAG_SURROGATE), 10, (16, 16, 16, 16, 0), 0)
+    assert e.value.status == rt.RT_EUNSUPPORTED
+    with pytest.raises(rt.RtError) as e:
+        tr.trace_raw(cam, dict(rule, flags=8), 10, (16, 16, 16, 16, 0), 0)
+    assert e.value.status == rt.RT_EINVAL
+    P = C.c_void_p(16)
+    one = np.ones(4, np.float32)
+    nob = np.zeros(1, np.int32)
+    # load: bad sizes first, then the host-only state
+    assert L.rt_surrogate_load(tr._h, 65, P, P, one.ctypes.data, P, 2, P, 1, nob.ctypes.data, 1, 1e-3) == rt.RT_EINVAL
+    assert L.rt_surrogate_load(tr._h, 1, P, P, one.ctypes.data, P, 1, P, 1, nob.ctypes.data, 1, 1e-3) == rt.RT_EINVAL
+    assert L.rt_surrogate_load(tr._h, 1, P, P, one.ctypes.data, P, 2, P, 1, nob.ctypes.data, 1, 0.0) == rt.RT_EINVAL
+    bad_nob = np.array([3], np.int32)
+    assert L.rt_surrogate_load(tr._h, 1, P, P, one.ctypes.data, P, 2, P, 1, bad_nob.ctypes.data, 1,
+                               1e-3) == rt.RT_EINVAL
+    neg = -one
+    assert L.rt_surrogate_load(tr._h, 1, P, P, neg.ctypes.data, P, 2, P, 1, nob.ctypes.data, 1, 1e-3) == rt.RT_EINVAL
+    assert L.rt_surrogate_load(tr._h, 1, P, P, one.ctypes.data, P, 2, P, 1, nob.ctypes.data, 1, 1e-3) == rt.RT_ESTATE
+    assert L.rt_surrogate_load(tr._h, 0, None, None, None, None, 2, None, 1, None, 0, 1.0) == rt.RT_OK
+    # data generation and calibration
+    k = np.array([1.0], np.float32)
+    assert L.rt_surrogate_gen(tr._h, 1, k.ctypes.data, one.ctypes.data, 16, 0.0, 0, 1, P, P, P, None) == rt.RT_EINVAL
+    assert L.rt_surrogate_gen(tr._h, 1, k.ctypes.data, one.ctypes.data, 16, 0.01, 3, 1, P, P, P, None) == rt.RT_EINVAL
+    assert L.rt_surrogate_gen(tr._h, 1, k.ctypes.data, neg.ctypes.data, 16, 0.01, 0, 1, P, P, P,
+                              None) == rt.RT_EINVAL
+    assert L.rt_surrogate_gen(tr._h, 1, k.ctypes.data, one.ctypes.data, 16, 0.01, 0, 1, P, P, P, None) == rt.RT_ESTATE
+    assert L.rt_surrogate_calibrate(tr._h, 1, 16, P, P, P, one.ctypes.data, 0, P, None) == rt.RT_EINVAL
+    assert L.rt_surrogate_calibrate(tr._h, 1, 16, P, P, P, one.ctypes.data, 8, P, None) == rt.RT_ESTATE
+    # MLP entry points
+    rows = np.array([3, -1], np.int32)
+    assert L.rt_mlp_fwd_grouped(tr._h, 2, rows.ctypes.data, P, P, P, P, None) == rt.RT_EINVAL
+    assert L.rt_mlp_fwd_grouped(tr._h, 65, rows.ctypes.data, P, P, P, P, None) == rt.RT_EINVAL
+    assert L.rt_mlp_work_bytes(0, 5) == 0 and L.rt_mlp_work_bytes(2, 5) > 0
+    assert L.rt_mlp_fwd(tr._h, 2, 5, P, P, P, P, P, 0, None) == rt.RT_EINVAL       # workspace too small
+    nb = L.rt_mlp_work_bytes(2, 5)
+    assert L.rt_mlp_fwd(tr._h, 2, 5, P, P, P, P, P, nb, None) == rt.RT_ESTATE
+    assert L.rt_mlp_bwd(tr._h, 2, 5, P, None, P, P, P, nb, None) == rt.RT_EINVAL
+    assert L.rt_adamw_step(tr._h, P, P, P, P, P, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0, 0, None) == rt.RT_EINVAL
+    assert L.rt_adamw_step(tr._h, P, P, P, P, P, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0, 1, None) == rt.RT_ESTATE
+    assert L.rt_mse_grad(tr._h, P, P, P, 10, 0, P, None) == rt.RT_EINVAL
