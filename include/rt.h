@@ -355,6 +355,27 @@ rt_status rt_adamw_step(rt_ctx *ctx, float *params, uint16_t *w_bf16, float *m, 
 rt_status rt_surrogate_gen(rt_ctx *ctx, int n_shapes, const float *kappa, const float *scale, int n_per_shape,
                            float h, int mode, uint64_t seed, float *x, float *y, float *aux, void *hip_stream);
 
+/* The whole training loop of the surrogate networks in one call (the
+ * sequence rt_surrogate_gen -> rt_mlp_fwd -> rt_mse_grad -> rt_mlp_bwd ->
+ * rt_adamw_step, n_steps times, enqueued from the host without
+ * synchronising).  Every step uses batch fresh crossings per shape (mode 0
+ * or 2 of rt_surrogate_gen, step h), drawn 16 steps at a time with seed
+ * seed + 1000003 (c + 1) for the c-th group of 16 steps; step s (1-based) uses the
+ * learning rate lr s / warmup for s <= warmup, then a cosine decay from lr
+ * to lr_min.  kappa, scale: host [n_nets].  params (FP32 master), w_bf16,
+ * adam_m, adam_v: device [n_nets][RT_MLP_PARAMS], updated in place.
+ * work: at least rt_surrogate_train_bytes(n_nets, batch) bytes of device
+ * memory.  loss_log: device float[n_log][64] or NULL: for every step s
+ * with s % log_every == 0 (s <= n_steps), row s / log_every - 1 receives
+ * the 64 partial sums of squares of that step (their sum / (batch n_nets)
+ * is the mean loss per network). */
+size_t rt_surrogate_train_bytes(int n_nets, int batch);
+rt_status rt_surrogate_train(rt_ctx *ctx, int n_nets, const float *kappa, const float *scale, int batch, int n_steps,
+                             float h, int mode, uint64_t seed, float lr, float lr_min, int warmup, float beta1,
+                             float beta2, float eps, float weight_decay, float *params, uint16_t *w_bf16,
+                             float *adam_m, float *adam_v, void *work, size_t work_bytes, float *loss_log,
+                             int log_every, void *hip_stream);
+
 /* Calibration of the surrogate's error bounds: for predictions `pred` and
  * targets `target` (scaled residuals as produced by rt_surrogate_gen, both
  * [n_shapes][n_per_shape][6], inputs x as produced there), the maximum over

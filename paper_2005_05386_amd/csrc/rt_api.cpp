@@ -920,6 +920,100 @@ rt_status rt_surrogate_gen(rt_ctx *c, int n_shapes, const float *kappa, const fl
     return RT_OK;
 }
 
+// Training batches are generated TRAIN_CHUNK steps at a time (one launch
+// with enough crossings to fill the GPU).
+static constexpr int TRAIN_CHUNK = 16;
+
+size_t rt_surrogate_train_bytes(int n_nets, int batch) {
+    if (n_nets < 1 || batch < 1) return 0;
+    const size_t nb = (size_t)n_nets * batch;
+    const size_t nc = nb * TRAIN_CHUNK;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    // x, y, aux of a chunk, pred, dy, grad, loss partials, then the MLP workspace
+    return al(nc * 6 * 4) * 2 + al(nc * 4 * 4) + al(nb * 6 * 4) * 2 + al((size_t)n_nets * RT_MLP_PARAMS * 4) +
+           al(64 * 4) + al(rti::mlp_work_bytes(n_nets, batch));
+}
+
+rt_status rt_surrogate_train(rt_ctx *c, int n_nets, const float *kappa, const float *scale, int batch, int n_steps,
+                             float h, int mode, uint64_t seed, float lr, float lr_min, int warmup, float b1, float b2,
+                             float eps, float wd, float *params, uint16_t *w_bf16, float *adam_m, float *adam_v,
+                             void *work, size_t work_bytes, float *loss_log, int log_every, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (n_nets < 1 || n_nets > 4096 || batch < 1 || (int64_t)n_nets * batch > (1LL << 26) || n_steps < 1)
+        return fail(c, RT_EINVAL, "rt_surrogate_train: bad sizes");
+    if (!kappa || !scale || !params || !w_bf16 || !adam_m || !adam_v || !work)
+        return fail(c, RT_EINVAL, "rt_surrogate_train: NULL argument");
+    if (!(h >= 1e-3f && h <= 0.5f) || (mode != 0 && mode != 2) || warmup < 0 || !(lr > 0.f) || !(lr_min >= 0.f) ||
+        !finite(lr) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f) || !finite(wd))
+        return fail(c, RT_EINVAL, "rt_surrogate_train: bad hyper-parameters");
+    if (loss_log && log_every < 1) return fail(c, RT_EINVAL, "rt_surrogate_train: log_every must be >= 1");
+    if (work_bytes < rt_surrogate_train_bytes(n_nets, batch))
+        return fail(c, RT_EINVAL, "rt_surrogate_train: workspace too small");
+    float kmax = 0.f;
+    for (int i = 0; i < n_nets; ++i) {
+        if (!finite(kappa[i]) || std::fabs(kappa[i]) > 100.f || !(scale[i] > 0.f) || !finite(scale[i]))
+            return fail(c, RT_EINVAL, "rt_surrogate_train: bad kappa or scale");
+        kmax = std::max(kmax, std::fabs(kappa[i]));
+    }
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_surrogate_train: host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    rt_status st = sync_last(c);
+    if (st != RT_OK) return st;
+    std::vector<float> ks(2 * (size_t)n_nets);
+    for (int i = 0; i < n_nets; ++i) {
+        ks[i] = kappa[i];
+        ks[n_nets + i] = scale[i];
+    }
+    if ((st = upload(c, &c->d_gen_ks, &c->gen_ks_bytes, ks.data(), ks.size() * sizeof(float))) != RT_OK) return st;
+    const float *dk = (const float *)c->d_gen_ks;
+    const size_t nb = (size_t)n_nets * batch;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *p = (char *)work;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += al(bytes);
+        return r;
+    };
+    const size_t nc = nb * TRAIN_CHUNK;
+    float *X = (float *)take(nc * 6 * 4), *Y = (float *)take(nc * 6 * 4), *AUX = (float *)take(nc * 4 * 4);
+    float *PRED = (float *)take(nb * 6 * 4), *DY = (float *)take(nb * 6 * 4);
+    float *G = (float *)take((size_t)n_nets * RT_MLP_PARAMS * 4), *PART = (float *)take(64 * 4);
+    rti::MlpWork w;
+    rti::mlp_work_carve(take(rti::mlp_work_bytes(n_nets, batch)), n_nets, batch, w);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t np = (size_t)n_nets * RT_MLP_PARAMS;
+    for (int step = 1; step <= n_steps; ++step) {
+        float lr_t;
+        if (step <= warmup) {
+            lr_t = lr * (float)step / (float)warmup;
+        } else {
+            const double q = (double)(step - warmup) / (double)std::max(1, n_steps - warmup);
+            lr_t = (float)(lr_min + 0.5 * (lr - lr_min) * (1.0 + std::cos(M_PI * q)));
+        }
+        float *part = (loss_log && step % log_every == 0) ? loss_log + (size_t)(step / log_every - 1) * 64 : PART;
+        const int j = (step - 1) % TRAIN_CHUNK;
+        if (j == 0) {
+            // crossings of the next TRAIN_CHUNK steps, step-major
+            const uint64_t chunk = (uint64_t)(step - 1) / TRAIN_CHUNK;
+            if ((e = rti::launch_cross_gen(dk, dk + n_nets, n_nets, batch * TRAIN_CHUNK, h, mode,
+                                           seed + 1000003ull * (chunk + 1), X, Y, AUX, kmax, s, batch)) != hipSuccess)
+                return hip_fail(c, e, "kernel launch (surrogate training data)");
+        }
+        const float *Xs = X + (size_t)j * nb * 6, *Ys = Y + (size_t)j * nb * 6;
+        if ((e = rti::mlp_forward(n_nets, batch, (const __bf16 *)w_bf16, params, Xs, PRED, w, true, s)) !=
+                hipSuccess ||
+            (e = rti::launch_mse_grad(PRED, Ys, DY, (int64_t)nb * 6, batch, part, 64, s)) != hipSuccess ||
+            (e = rti::mlp_backward(n_nets, batch, (const __bf16 *)w_bf16, params, DY, G, w, s)) != hipSuccess ||
+            (e = rti::launch_adamw(params, (__bf16 *)w_bf16, adam_m, adam_v, G, (int64_t)np, lr_t, b1, b2, eps, wd,
+                                   step, s)) != hipSuccess)
+            return hip_fail(c, e, "kernel launch (surrogate training)");
+    }
+    c->last_stream = s;
+    c->traced = true;
+    return RT_OK;
+}
+
 rt_status rt_surrogate_calibrate(rt_ctx *c, int n_shapes, int n_per, const float *x, const float *pred,
                                  const float *target, const float *scale, int n_bins, float *err, void *stream) {
     if (!c) return RT_EINVAL;

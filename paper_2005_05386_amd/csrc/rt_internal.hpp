@@ -191,7 +191,8 @@ constexpr int64_t OFF_W1 = 0, OFF_B1 = OFF_W1 + MLP_H * MLP_IN, OFF_W2 = OFF_B1 
 struct MlpWork {
     float *xf;        // [n][B][6] inputs (FP32 first layer)
     float *z[3];      // [n][B][256] pre-activations
-    __bf16 *h[3];     // [n][B][256] activations
+    __bf16 *h[3];     // [n][B][256] activations (bf16, high part)
+    __bf16 *hl[3];    // [n][B][256] low parts: h - hi, rounded to bf16
     __bf16 *dyb;      // [n][B][6]
     float *dzf[2];    // [n][B][256]
     __bf16 *dzb[2];   // [n][B][256]
@@ -212,8 +213,11 @@ hipError_t launch_to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t s);
 hipError_t launch_mse_grad(const float *y, const float *t, float *dy, int64_t n, int batch, float *part, int nblk,
                            hipStream_t s);
 
+// step_batch > 0: outputs laid out [n_per / step_batch][n_shapes][step_batch]
+// (n_per a multiple of step_batch), one contiguous training batch per step.
 hipError_t launch_cross_gen(const float *kappa, const float *scale, int n_shapes, int n_per, float h, int mode,
-                            uint64_t seed, float *X, float *Y, float *AUX, float kappa_max, hipStream_t s);
+                            uint64_t seed, float *X, float *Y, float *AUX, float kappa_max, hipStream_t s,
+                            int step_batch = 0);
 hipError_t launch_cross_cal(const float *X, const float *P, const float *Y, const float *scale, int n_shapes,
                             int n_per, int n_bins, float *err, hipStream_t s);
 // Crossing stage after pass `pass`: group by network, fused MLP forward,

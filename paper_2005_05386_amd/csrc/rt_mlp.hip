@@ -126,9 +126,10 @@ __global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G) {
 
 // First layer in FP32: thread o of a 256-thread block computes unit o of
 // z1 = W1 x + b1 for up to 64 rows of network blockIdx.y; h1 = silu(z1) is
-// stored in bf16 for the next product, z1 (and x) for a backward pass.
+// stored split in two bf16 parts (hi, lo) for the next product, z1 (and x)
+// for a backward pass.
 __global__ __launch_bounds__(256) void k_l1_fwd(const float *__restrict__ params, const float *__restrict__ X, int B,
-                                                float *__restrict__ Z, __bf16 *__restrict__ H,
+                                                float *__restrict__ Z, __bf16 *__restrict__ H, __bf16 *__restrict__ HL,
                                                 float *__restrict__ Xkeep) {
     const int g = blockIdx.y, o = threadIdx.x;
     const int m0 = blockIdx.x * 64;
@@ -148,7 +149,10 @@ __global__ __launch_bounds__(256) void k_l1_fwd(const float *__restrict__ params
         z = fmaf(w4, x[4], z);
         z = fmaf(w5, x[5], z);
         if (Z) Z[r * rti::MLP_H + o] = z;
-        H[r * rti::MLP_H + o] = (__bf16)silu(z);
+        const float h = silu(z);
+        const __bf16 hh = (__bf16)h;
+        H[r * rti::MLP_H + o] = hh;
+        HL[r * rti::MLP_H + o] = (__bf16)(h - (float)hh);
         if (Xkeep && o < 6) Xkeep[r * 6 + o] = x[o];
     }
 }
@@ -264,25 +268,27 @@ __global__ __launch_bounds__(256) void k_l4_bwd(const float *__restrict__ params
     }
 }
 
-__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
-    hi = (__bf16)v;
-    lo = (__bf16)(v - (float)hi);
-}
-
 // Forward product of a hidden layer in split bf16: for network blockIdx.z,
-// z[m][n] = b[n] + sum_k silu(Zin[m][k]) W[n][k] over K = N = 256 (W from
-// the FP32 master), then Zout = z (FP32) and H = bf16(silu(z)) for the
-// backward.  Tiles as k_gemm; both operands are split while staged to LDS.
-__global__ __launch_bounds__(256) void k_gemm_x3(const float *__restrict__ Zin, const float *__restrict__ params,
-                                                 int64_t offW, int64_t offB, int B, float *__restrict__ Zout,
-                                                 __bf16 *__restrict__ H) {
-    __shared__ __bf16 Ah[64][32 + 8], Al[64][32 + 8];
-    __shared__ __bf16 Bh[64][32 + 8], Bl[64][32 + 8];  // transposed: [n][k]
+// z[m][n] = b[n] + sum_k h[m][k] W[n][k] over K = N = 256, with h given as
+// its two bf16 parts (Hh, Hl, written by the previous layer) and W split
+// from the FP32 master while staged; then Zout = z (FP32) and the parts of
+// silu(z) for the next layer and the backward.  A 64x64 tile per block, 4
+// waves of 2x2 16x16x32 tiles; LDS rows of 40 bf16 (80 bytes) so that every
+// stage write and fragment read is one 16-byte access.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(256) void k_gemm_x3(const __bf16 *__restrict__ Hh, const __bf16 *__restrict__ Hl,
+                                                 const float *__restrict__ params, int64_t offW, int64_t offB, int B,
+                                                 float *__restrict__ Zout, __bf16 *__restrict__ Oh,
+                                                 __bf16 *__restrict__ Ol) {
+    __shared__ __attribute__((aligned(16))) __bf16 Ah[64][40], Al[64][40];
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[64][40], Bl[64][40];  // [n][k]
     const int g = blockIdx.z;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     if (m0 >= B) return;
     const int64_t K = rti::MLP_H;
-    const float *__restrict__ Z = Zin + (int64_t)g * B * K;
+    const __bf16 *__restrict__ Xh = Hh + (int64_t)g * B * K;
+    const __bf16 *__restrict__ Xl = Hl + (int64_t)g * B * K;
     const float *__restrict__ W = params + (int64_t)g * rti::MLP_P + offW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -291,35 +297,43 @@ __global__ __launch_bounds__(256) void k_gemm_x3(const float *__restrict__ Zin, 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const __bf16 zero = (__bf16)0.0f;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        {
-            const int r = tid >> 2, kc = (tid & 3) * 8;
-            const int m = m0 + r, n = n0 + r;
+    const int r = tid >> 2, kc = (tid & 3) * 8;
+    const int m = m0 + r, n = n0 + r;
+    bf16x8v zero8;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = k0 + kc + i;
-                if (m < B) {
-                    split_bf16(silu(Z[(int64_t)m * K + k]), Ah[r][kc + i], Al[r][kc + i]);
-                } else {
-                    Ah[r][kc + i] = zero;
-                    Al[r][kc + i] = zero;
-                }
-                split_bf16(W[(int64_t)n * K + k], Bh[r][kc + i], Bl[r][kc + i]);
+    for (int e = 0; e < 8; ++e) zero8[e] = (__bf16)0.0f;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        // stage: thread t takes 8 consecutive k of row t/4 of each operand
+        if (m < B) {
+            *(bf16x8v *)&Ah[r][kc] = *(const bf16x8v *)(Xh + (int64_t)m * K + k0 + kc);
+            *(bf16x8v *)&Al[r][kc] = *(const bf16x8v *)(Xl + (int64_t)m * K + k0 + kc);
+        } else {
+            *(bf16x8v *)&Ah[r][kc] = zero8;
+            *(bf16x8v *)&Al[r][kc] = zero8;
+        }
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(W + (int64_t)n * K + k0 + kc);
+            const float4 u0 = src[0], u1 = src[1];
+            const float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+            bf16x8v hi, lo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const __bf16 t = (__bf16)v[e];
+                hi[e] = t;
+                lo[e] = (__bf16)(v[e] - (float)t);
             }
+            *(bf16x8v *)&Bh[r][kc] = hi;
+            *(bf16x8v *)&Bl[r][kc] = lo;
         }
         __syncthreads();
         const int kq = (lane >> 4) * 8;
         bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                ah[i][e] = Ah[wm + 16 * i + (lane & 15)][kq + e];
-                al[i][e] = Al[wm + 16 * i + (lane & 15)][kq + e];
-                bh[i][e] = Bh[wn + 16 * i + (lane & 15)][kq + e];
-                bl[i][e] = Bl[wn + 16 * i + (lane & 15)][kq + e];
-            }
+            ah[i] = *(const bf16x8 *)&Ah[wm + 16 * i + (lane & 15)][kq];
+            al[i] = *(const bf16x8 *)&Al[wm + 16 * i + (lane & 15)][kq];
+            bh[i] = *(const bf16x8 *)&Bh[wn + 16 * i + (lane & 15)][kq];
+            bl[i] = *(const bf16x8 *)&Bl[wn + 16 * i + (lane & 15)][kq];
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -338,13 +352,16 @@ __global__ __launch_bounds__(256) void k_gemm_x3(const float *__restrict__ Zin, 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + e;
-                const int n = n0 + wn + 16 * j + (lane & 15);
-                if (m >= B) continue;
-                const int64_t o = ((int64_t)g * B + m) * K + n;
-                const float z = acc[i][j][e] + bias[n];
+                const int mm = m0 + wm + 16 * i + (lane >> 4) * 4 + e;
+                const int nn = n0 + wn + 16 * j + (lane & 15);
+                if (mm >= B) continue;
+                const int64_t o = ((int64_t)g * B + mm) * K + nn;
+                const float z = acc[i][j][e] + bias[nn];
                 Zout[o] = z;
-                H[o] = (__bf16)silu(z);
+                const float h = silu(z);
+                const __bf16 hh = (__bf16)h;
+                Oh[o] = hh;
+                Ol[o] = (__bf16)(h - (float)hh);
             }
 }
 
@@ -454,7 +471,7 @@ namespace rti {
 size_t mlp_work_bytes(int n_nets, int batch) {
     size_t nb = (size_t)n_nets * batch;
     size_t nch = ((size_t)batch + 255) / 256;
-    return nb * MLP_IN * 4 + nb * MLP_OUT * 2 + nb * MLP_H * (3 * 4 + 3 * 2 + 2 * 4 + 2 * 2) +
+    return nb * MLP_IN * 4 + nb * MLP_OUT * 2 + nb * MLP_H * (3 * 4 + 6 * 2 + 2 * 4 + 2 * 2) +
            (size_t)n_nets * nch * MLP_H * 7 * 4 + 16 * 256;
 }
 
@@ -470,6 +487,7 @@ void mlp_work_carve(void *base, int n_nets, int batch, MlpWork &w) {
     w.xf = (float *)take(nb * MLP_IN * 4);
     for (int i = 0; i < 3; ++i) w.z[i] = (float *)take(nb * MLP_H * 4);
     for (int i = 0; i < 3; ++i) w.h[i] = (__bf16 *)take(nb * MLP_H * 2);
+    for (int i = 0; i < 3; ++i) w.hl[i] = (__bf16 *)take(nb * MLP_H * 2);
     w.dyb = (__bf16 *)take(nb * MLP_OUT * 2);
     for (int i = 0; i < 2; ++i) w.dzf[i] = (float *)take(nb * MLP_H * 4);
     for (int i = 0; i < 2; ++i) w.dzb[i] = (__bf16 *)take(nb * MLP_H * 2);
@@ -489,10 +507,13 @@ hipError_t mlp_forward(int n, int B, const __bf16 *wb, const float *params, cons
     // every layer's pre-activations go to z[l]: the next layer reads them
     (void)wb;
     (void)keep;
-    hipLaunchKernelGGL(k_l1_fwd, dim3((B + 63) / 64, n), dim3(256), 0, s, params, x, B, w.z[0], w.h[0], w.xf);
+    hipLaunchKernelGGL(k_l1_fwd, dim3((B + 63) / 64, n), dim3(256), 0, s, params, x, B, w.z[0], w.h[0], w.hl[0],
+                       w.xf);
     const dim3 grid((unsigned)(MLP_H / 64), (unsigned)((B + 63) / 64), (unsigned)n);
-    hipLaunchKernelGGL(k_gemm_x3, grid, dim3(256), 0, s, w.z[0], params, OFF_W2, OFF_B2, B, w.z[1], w.h[1]);
-    hipLaunchKernelGGL(k_gemm_x3, grid, dim3(256), 0, s, w.z[1], params, OFF_W3, OFF_B3, B, w.z[2], w.h[2]);
+    hipLaunchKernelGGL(k_gemm_x3, grid, dim3(256), 0, s, w.h[0], w.hl[0], params, OFF_W2, OFF_B2, B, w.z[1], w.h[1],
+                       w.hl[1]);
+    hipLaunchKernelGGL(k_gemm_x3, grid, dim3(256), 0, s, w.h[1], w.hl[1], params, OFF_W3, OFF_B3, B, w.z[2], w.h[2],
+                       w.hl[2]);
     hipLaunchKernelGGL(k_l4_fwd, dim3((B * 6 + 255) / 256, n), dim3(256), 0, s, params, w.z[2], B, y);
     return hipGetLastError();
 }

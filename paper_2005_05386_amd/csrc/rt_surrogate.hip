@@ -59,7 +59,7 @@ __device__ __forceinline__ void chord_baseline(float c, float s, V3<float> &uc, 
 __global__ __launch_bounds__(256) void k_cross_gen(const float *__restrict__ kappa, const float *__restrict__ scale,
                                                    int n_per, float h, int mode, uint64_t seed,
                                                    float *__restrict__ X, float *__restrict__ Y,
-                                                   float *__restrict__ AUX, int max_steps) {
+                                                   float *__restrict__ AUX, int max_steps, int step_batch) {
     const int sh = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_per) return;
@@ -128,7 +128,9 @@ __global__ __launch_bounds__(256) void k_cross_gen(const float *__restrict__ kap
     const V3<float> uo = (1.0f / 3.0f) * ue;
     const V3<float> vo = rsqrt_(dot(ye, ye)) * ye;
     const float inv = 1.0f / scale[sh];
-    const int64_t o = (int64_t)sh * n_per + i;
+    // layout [shape][sample], or step-major [i / step_batch][shape][i % step_batch]
+    const int64_t o = step_batch > 0 ? ((int64_t)(i / step_batch) * gridDim.y + sh) * step_batch + i % step_batch
+                                     : (int64_t)sh * n_per + i;
     float *x = X + 6 * o, *yv = Y + 6 * o, *aux = AUX + 4 * o;
     x[0] = 1.f;
     x[1] = 0.f;
@@ -479,13 +481,15 @@ __global__ __launch_bounds__(256) void k_xapply(const rti::TraceArgs A, const rt
 namespace rti {
 
 hipError_t launch_cross_gen(const float *kappa, const float *scale, int n_shapes, int n_per, float h, int mode,
-                            uint64_t seed, float *X, float *Y, float *AUX, float kappa_max, hipStream_t s) {
+                            uint64_t seed, float *X, float *Y, float *AUX, float kappa_max, hipStream_t s,
+                            int step_batch) {
     dim3 g((n_per + 255) / 256, n_shapes);
     // arc lengths inside the sphere grow with kappa (about 11 units at
     // kappa = 4, where rays wind around the bump): a generous bound; every
     // ray stops at its exit
     const int max_steps = (int)((20.0f + 10.0f * kappa_max) / h) + 16;
-    hipLaunchKernelGGL(k_cross_gen, g, dim3(256), 0, s, kappa, scale, n_per, h, mode, seed, X, Y, AUX, max_steps);
+    hipLaunchKernelGGL(k_cross_gen, g, dim3(256), 0, s, kappa, scale, n_per, h, mode, seed, X, Y, AUX, max_steps,
+                       step_batch);
     return hipGetLastError();
 }
 

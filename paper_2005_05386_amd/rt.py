@@ -28,7 +28,8 @@ FLAG_TIMING, FLAG_COUNT_WORK, FLAG_SURROGATE = 1, 2, 4
 EXPORTS = ["rt_abi_version", "rt_create", "rt_destroy", "rt_last_error", "rt_set_metric", "rt_set_scene",
            "rt_trace", "rt_sync", "rt_get_stats", "rt_tape_bytes", "rt_trace_fwd_ckpt", "rt_loss_l2",
            "rt_trace_bwd", "rt_mlp_work_bytes", "rt_mlp_fwd", "rt_mlp_fwd_grouped", "rt_mlp_bwd", "rt_mse_grad", "rt_adamw_step",
-           "rt_surrogate_gen", "rt_surrogate_calibrate", "rt_surrogate_load"]
+           "rt_surrogate_gen", "rt_surrogate_train_bytes", "rt_surrogate_train", "rt_surrogate_calibrate",
+           "rt_surrogate_load"]
 MLP_PARAMS = 134918
 
 
@@ -120,6 +121,12 @@ _lib.rt_surrogate_gen.argtypes = [_P, C.c_int, _P, _P, C.c_int, C.c_float, C.c_i
 _lib.rt_surrogate_gen.restype = C.c_int
 _lib.rt_mlp_fwd_grouped.argtypes = [_P, C.c_int, _P, _P, _P, _P, _P, _P]
 _lib.rt_mlp_fwd_grouped.restype = C.c_int
+_lib.rt_surrogate_train_bytes.argtypes = [C.c_int, C.c_int]
+_lib.rt_surrogate_train_bytes.restype = C.c_size_t
+_lib.rt_surrogate_train.argtypes = [_P, C.c_int, _P, _P, C.c_int, C.c_int, C.c_float, C.c_int, C.c_uint64, C.c_float,
+                                    C.c_float, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _P, _P, _P, _P,
+                                    _P, C.c_size_t, _P, C.c_int, _P]
+_lib.rt_surrogate_train.restype = C.c_int
 _lib.rt_surrogate_calibrate.argtypes = [_P, C.c_int, C.c_int, _P, _P, _P, _P, C.c_int, _P, _P]
 _lib.rt_surrogate_calibrate.restype = C.c_int
 _lib.rt_surrogate_load.argtypes = [_P, C.c_int, _P, _P, _P, _P, C.c_int, _P, C.c_int, _P, C.c_int, C.c_float]
@@ -368,6 +375,31 @@ class Tracer:
                                           C.c_void_p(y.data_ptr()), C.c_void_p(aux.data_ptr()),
                                           C.c_void_p(st.cuda_stream)))
         return x, y, aux
+
+    def surrogate_train(self, kappa, scale, params, w_bf16, m, v, batch, n_steps, h=0.01, mode=0, seed=0,
+                        lr=2e-3, lr_min=1e-5, warmup=200, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, log_every=500):
+        """Enqueue n_steps training steps of the networks (all in the
+        library); returns the loss log [n_steps // log_every, 64] partial
+        sums (a device tensor, valid after the stream's work)."""
+        import torch
+        k = np.ascontiguousarray(kappa, np.float32)
+        sc = np.ascontiguousarray(scale, np.float32)
+        n = len(k)
+        dev = torch.device("cuda", self.device)
+        nbytes = int(_lib.rt_surrogate_train_bytes(n, int(batch)))
+        work = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=dev)
+        n_log = int(n_steps) // int(log_every)
+        log = torch.zeros((max(n_log, 1), 64), dtype=torch.float32, device=dev)
+        st = torch.cuda.current_stream(self.device)
+        self._check(_lib.rt_surrogate_train(self._h, n, k.ctypes.data, sc.ctypes.data, int(batch), int(n_steps),
+                                            float(h), int(mode), int(seed), float(lr), float(lr_min), int(warmup),
+                                            float(b1), float(b2), float(eps), float(wd),
+                                            C.c_void_p(params.data_ptr()), C.c_void_p(w_bf16.data_ptr()),
+                                            C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()),
+                                            C.c_void_p(work.data_ptr()), C.c_size_t(work.numel() * 4),
+                                            C.c_void_p(log.data_ptr()) if n_log else None, int(log_every),
+                                            C.c_void_p(st.cuda_stream)))
+        return log[:n_log], work
 
     def surrogate_calibrate(self, x, pred, target, scale, n_bins):
         """Per-bin decoded error maxima [n, n_bins, 2] of pred against target."""

@@ -100,29 +100,20 @@ def train(tracer, kappa, samples=10_000_000, batch=1024, h=0.01, lr=2e-3, lr_min
     wb = params.to(torch.bfloat16)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
-    work = tracer.mlp_work(n, batch)
     steps = max(1, (samples + batch - 1) // batch)
-    losses = []
-    gen_s = 0.0
-    for step in range(1, steps + 1):
-        x, y, _ = tracer.surrogate_gen(kappa, scale, batch, h, mode=sampling, seed=seed + 1000003 * step)
-        pred = tracer.mlp_fwd(wb, params, x, work)
-        dy, part = tracer.mse_grad(pred, y, batch)
-        g = tracer.mlp_bwd(wb, params, dy, work)
-        if step <= warmup:
-            lr_t = lr * step / warmup
-        else:
-            q = (step - warmup) / max(1, steps - warmup)
-            lr_t = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * q))
-        tracer.adamw(params, wb, m, v, g, lr_t, step)
-        if step % log_every == 0 or step == steps:
-            # this step's loss per network (64 partial sums of squares)
-            loss = float(part.cpu().numpy().astype(np.float64).sum()) / (batch * n)
-            losses.append((step, loss))
-            if log:
-                log("surrogate step %d/%d loss/net %.3e lr %.2e" % (step, steps, loss, lr_t))
+    log_every = min(log_every, steps)
+    # the library runs the whole loop (data, forward, loss, backward, AdamW)
+    loss_log, _work = tracer.surrogate_train(kappa, scale, params, wb, m, v, batch, steps, h=h, mode=sampling,
+                                             seed=seed, lr=lr, lr_min=lr_min, warmup=warmup, log_every=log_every)
     tracer.sync()
     train_s = time.perf_counter() - t0
+    # loss per network of every logged step (64 partial sums of squares each)
+    sums = loss_log.cpu().numpy().astype(np.float64).sum(axis=1) / (batch * n)
+    losses = [((i + 1) * log_every, float(v_)) for i, v_ in enumerate(sums)]
+    if log:
+        for st_, l_ in losses:
+            log("surrogate step %d/%d loss/net %.3e" % (st_, steps, l_))
+    gen_s = 0.0
 
     # calibration on a cos-theta grid; the arc table comes from the same grid
     xg, yg, auxg = tracer.surrogate_gen(kappa, scale, n_cal, h, grid=True)
