@@ -180,3 +180,32 @@ def test_surrogate_and_mlp_entry_points_validate():
     assert L.rt_adamw_step(tr._h, P, P, P, P, P, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0, 0, None) == rt.RT_EINVAL
     assert L.rt_adamw_step(tr._h, P, P, P, P, P, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0, 1, None) == rt.RT_ESTATE
     assert L.rt_mse_grad(tr._h, P, P, P, 10, 0, P, None) == rt.RT_EINVAL
+
+
+def test_surrogate_train_validates():
+    rt = _rt()
+    tr = rt.Tracer(-1)
+    L = rt.lib()
+    P = C.c_void_p(16)
+    k = np.array([1.0, 0.5], np.float32)
+    sc = np.array([0.1, 0.2], np.float32)
+    nb = L.rt_surrogate_train_bytes(2, 64)
+    assert nb > 0 and L.rt_surrogate_train_bytes(0, 64) == 0
+
+    def call(**kw):
+        a = dict(n=2, kappa=k.ctypes.data, scale=sc.ctypes.data, batch=64, steps=10, h=0.01, mode=0, lr=1e-3,
+                 warm=5, work_bytes=nb, log=None, log_every=1)
+        a.update(kw)
+        return L.rt_surrogate_train(tr._h, a["n"], a["kappa"], a["scale"], a["batch"], a["steps"], a["h"],
+                                    a["mode"], 1, a["lr"], 1e-5, a["warm"], 0.9, 0.999, 1e-8, 0.0, P, P, P, P, P,
+                                    a["work_bytes"], a["log"], a["log_every"], None)
+    assert call(n=0) == rt.RT_EINVAL
+    assert call(steps=0) == rt.RT_EINVAL
+    assert call(mode=1) == rt.RT_EINVAL          # the grid is for calibration, not training
+    assert call(h=0.0) == rt.RT_EINVAL
+    assert call(lr=0.0) == rt.RT_EINVAL
+    assert call(work_bytes=nb - 1) == rt.RT_EINVAL
+    assert call(log=P, log_every=0) == rt.RT_EINVAL
+    bad = np.array([-0.1, 0.2], np.float32)
+    assert call(scale=bad.ctypes.data) == rt.RT_EINVAL
+    assert call() == rt.RT_ESTATE
