@@ -244,3 +244,22 @@ def test_surrogate_isolated_4k_sampled(env):
     rep = compare(out, ref, pix)
     say("vs oracle (sampled)", rep)
     assert_parity(rep, frac=0.998)
+
+
+def test_camera_inside_a_support_sphere(env, trained):
+    """Rays that start inside an eligible support sphere integrate out of it
+    (a ray parks only when its chord enters a sphere from outside); the
+    frame still matches the oracle."""
+    rt, surrogate, torch, tr = env
+    wl, model, net = trained
+    say("camera inside the support sphere of bump 0")
+    wl2 = dict(wl, camera=W.camera(48, 32, eye=(-1.5, 0.5, 1.3), vfov_deg=50.0))
+    tr.set_metric(wl2["metric"])
+    tr.set_scene(wl2["scene"])
+    surrogate.load(tr, model, net, tol=1e-3)
+    out, st = _trace(rt, tr, wl2, rt.FLAG_SURROGATE)
+    say("crossings %d accepted %d" % (st["crossings"], st["accepted"]))
+    ref = oracle.Oracle(wl2["metric"], wl2["scene"]).trace(wl2["camera"], wl2["rule"])
+    rep = compare(out, ref)
+    say(rep)
+    assert_parity(rep)
