@@ -126,10 +126,20 @@ def cpu_baseline(wl, budget_s):
         steps += int(r["steps"].sum())
         done += len(r["id"])
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over the next pixels of the sample
+    one, steps1, t1 = done, 0, time.perf_counter()
+    while one < len(pix) and time.perf_counter() - t1 < budget_s / 3:
+        r = orc.trace(cam, rule, pix[one:one + 16], nthreads=1)
+        steps1 += int(r["steps"].sum())
+        one += len(r["id"])
+    dt1 = time.perf_counter() - t1
     return {"value": done / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "ray_steps_per_s": steps / dt,
             "sample": "%d seeded pixels (seed 11) of the %dx%d frame, FP64, no culling, %.1f s" % (
-                done, cam["width"], cam["height"], dt)}
+                done, cam["width"], cam["height"], dt),
+            "single_thread": {"value": (one - done) / dt1, "ray_steps_per_s": steps1 / dt1,
+                              "sample": "the next %d pixels of the same sample, 1 thread, %.1f s" % (
+                                  one - done, dt1)}}
 
 
 def bench_adjoint(args, wl, torch, rt):
@@ -306,6 +316,79 @@ def bench_surrogate(args, wl, torch, rt):
     print(json.dumps(line), flush=True)
 
 
+def _finite(x):
+    """JSON has no infinity: an infinite error (an id mismatch among the
+    quantile's pixels) is written as null."""
+    return None if x == float("inf") else x
+
+
+EULER_H = (0.005, 0.0025, 0.00125, 0.000625, 0.0003125)
+RK4_H = (0.005, 0.00625, 0.008, 0.01, 0.0125, 0.016, 0.02, 0.025, 0.04, 0.05, 0.0625, 0.08, 0.1)
+
+
+def bench_euler(args, wl, torch, rt):
+    """The paper's explicit Euler march (Eq. 4.1) against RK4 at equal hit
+    error on the 1080p, 16-bump frame. The reference is the RK4 frame at
+    h = 0.005 (its own error is below 1e-6 there). For each Euler step the
+    frame is timed and its error taken (99.9th percentile over all pixels of
+    the hit error, an id mismatch counting as infinite); the RK4 frame at the
+    largest step whose error is no larger is the equal-error competitor.
+    Every step divides t_max = 20, so misses end at the same t."""
+    import numpy as np
+
+    import workloads as W_
+    cam = wl["camera"]
+    tr = rt.Tracer(0)
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    out = tr.alloc_outputs(cam)
+    n_rays = cam["width"] * cam["height"]
+    t_max = wl["rule"]["t_max"]
+
+    def run(kind, hh):
+        n = int(round(t_max / hh))
+        r = dict(wl["rule"], kind=kind, h=float(np.float32(hh)), max_steps=n, pass_steps=n)
+        for _ in range(max(1, args.warmup)):
+            tr.trace_into(cam, r, n, out)
+        ms, st, _ = _timed_frames(tr, cam, r, out, max(1, args.steps), torch)
+        return ms, st, rt.to_numpy(out)
+
+    _, _, ref = run(W_.RK4, 0.005)
+    rk4 = []
+    for hh in RK4_H:
+        ms, st, o = run(W_.RK4, hh)
+        e = _frame_error(o, ref)
+        rk4.append({"h": hh, "ms": ms, "ray_steps": st["ray_steps"], **e})
+        print("[bench] rk4 h=%g: %.2f ms %s" % (hh, ms, json.dumps(e)), flush=True)
+    eul = []
+    for hh in EULER_H:
+        ms, st, o = run(W_.EULER, hh)
+        e = _frame_error(o, ref)
+        ok = [r for r in rk4 if r["p999_err_all_pixels"] <= e["p999_err_all_pixels"]]
+        best = max(ok, key=lambda r: r["h"]) if ok else None
+        eul.append({"h": hh, "ms": ms, "ray_steps": st["ray_steps"], **e,
+                    "rk4_equal_error_h": best["h"] if best else None,
+                    "rk4_equal_error_ms": best["ms"] if best else None,
+                    "rk4_speedup_at_equal_error": (ms / best["ms"]) if best else None})
+        print("[bench] euler h=%g: %.2f ms %s, RK4 at equal error: %s" % (
+            hh, ms, json.dumps(e), json.dumps(best and {"h": best["h"], "ms": best["ms"]})), flush=True)
+    for r in rk4 + eul:
+        for k in ("p999_hit_err", "p999_err_all_pixels", "max_hit_err"):
+            r[k] = _finite(r[k])
+    head = eul[0]
+    line = {
+        "metric": "Euler (Eq. 4.1) vs RK4 at equal hit error (1080p, 16 bumps), rays/s of the Euler frame",
+        "value": n_rays / (head["ms"] / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"],
+                   "bumps": int(wl["metric"]["bumps"].shape[1]), "t_max": t_max,
+                   "reference": "RK4 h=0.005", "euler_h": list(EULER_H), "rk4_h": list(RK4_H)},
+        "euler": eul, "rk4": rk4,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +419,8 @@ def main():
         return bench_adjoint(args, wl, torch, rt)
     if args.workload.startswith("surrogate"):
         return bench_surrogate(args, wl, torch, rt)
+    if args.workload == "euler_vs_rk4_1080p":
+        return bench_euler(args, wl, torch, rt)
     cam, rule = wl["camera"], dict(wl["rule"])
     tr = rt.Tracer(0)
     tr.set_metric(wl["metric"])

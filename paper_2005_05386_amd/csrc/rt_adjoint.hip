@@ -65,8 +65,11 @@ __device__ __forceinline__ uint64_t cull_mask(const float4 *__restrict__ B, int 
 __device__ __forceinline__ GraphAccum graph_sums(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
                                                  V3<float> y) {
     GraphAccum G{0.f, 0.f, 0.f, 0.f};
+    if (!mask) return G;
     const float yy = dot(y, y);
-    for (uint64_t m = mask; m; m &= m - 1) {
+    const int b0 = __builtin_ctzll(mask);
+    graph_bump_f32<true>(B[2 * b0], B[2 * b0 + 1], p, y, yy, G);
+    for (uint64_t m = mask & (mask - 1); m; m &= m - 1) {
         const int b = __builtin_ctzll(m);
         graph_bump_f32(B[2 * b], B[2 * b + 1], p, y, yy, G);
     }

@@ -42,7 +42,7 @@ __device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(
 __device__ __forceinline__ double exp2_(double x) { return exp2(x); }
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
@@ -114,17 +114,27 @@ struct GraphAccum {
     float gx, gy, gz, q;
 };
 
+// FIRST: the sums start at this bump (the same values as accumulating onto
+// zeros, without the zero-initialisation).
+template <bool FIRST = false>
 __device__ __forceinline__ void graph_bump_f32(const float4 b0, const float4 b1, V3<float> p, V3<float> y,
                                                float yy, GraphAccum &A) {
     float dx = p.x - b0.x, dy = p.y - b0.y, dz = p.z - b0.z;
     float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     float e = exp2_(b0.w * r2);
     float w = (r2 <= b1.z) ? b1.x * e : 0.0f;
-    A.gx = fmaf(-w, dx, A.gx);
-    A.gy = fmaf(-w, dy, A.gy);
-    A.gz = fmaf(-w, dz, A.gz);
     float dv = fmaf(dz, y.z, fmaf(dy, y.y, dx * y.x));
-    A.q = fmaf(w, fmaf(b1.y, dv * dv, -yy), A.q);
+    if constexpr (FIRST) {
+        A.gx = -w * dx;
+        A.gy = -w * dy;
+        A.gz = -w * dz;
+        A.q = w * fmaf(b1.y, dv * dv, -yy);
+    } else {
+        A.gx = fmaf(-w, dx, A.gx);
+        A.gy = fmaf(-w, dy, A.gy);
+        A.gz = fmaf(-w, dz, A.gz);
+        A.q = fmaf(w, fmaf(b1.y, dv * dv, -yy), A.q);
+    }
 }
 
 __device__ __forceinline__ V3<float> graph_finish(const GraphAccum &A) {
@@ -140,13 +150,21 @@ __device__ __forceinline__ V3<float> graph_finish(const GraphAccum &A) {
 template <bool COUNT = false>
 __device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
                                                      V3<float> y, unsigned *n_in = nullptr) {
-    GraphAccum A{0.f, 0.f, 0.f, 0.f};
+    if (!mask) return mk(0.f, 0.f, 0.f);
+    GraphAccum A;
     float yy = dot(y, y);
     unsigned n = 0;
     auto in_cut = [&](float4 b0, float4 b1) {
         float dx = p.x - b0.x, dy = p.y - b0.y, dz = p.z - b0.z;
         return (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= b1.z) ? 1u : 0u;
     };
+    {
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const float4 b0 = B[2 * b], b1 = B[2 * b + 1];
+        graph_bump_f32<true>(b0, b1, p, y, yy, A);
+        if (COUNT) n += in_cut(b0, b1);
+    }
     while (mask) {
         const int b = __builtin_ctzll(mask);
         mask &= mask - 1;

@@ -70,7 +70,7 @@ __device__ __forceinline__ bool step_rk4(F &acc, V3<T> p, V3<T> y, T h, V3<T> &d
     // accumulated as the stages are produced.
     const T hh = T(0.5) * h;
     V3<T> P = p, Y = y;
-    V3<T> sx = mk(T(0), T(0), T(0)), sv = mk(T(0), T(0), T(0));
+    V3<T> sx, sv;
     bool ok = true;
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -79,9 +79,14 @@ __device__ __forceinline__ bool step_rk4(F &acc, V3<T> p, V3<T> y, T h, V3<T> &d
             k = *k1;  // first stage supplied by the caller
         else
             ok &= acc(P, Y, k);
-        const T w = (st == 0 || st == 3) ? T(1) : T(2);
-        sx = axpy(w, Y, sx);
-        sv = axpy(w, k, sv);
+        if (st == 0) {
+            sx = Y;
+            sv = k;
+        } else {
+            const T w = st == 3 ? T(1) : T(2);
+            sx = axpy(w, Y, sx);
+            sv = axpy(w, k, sv);
+        }
         const T c = st < 2 ? hh : h;
         P = axpy(c, Y, p);
         Y = axpy(c, k, y);
@@ -127,11 +132,15 @@ __device__ __forceinline__ bool step_dp5(F &acc, V3<T> p, V3<T> y, T h, V3<T> &A
     return ok;
 }
 
-// Knuth's TwoSum followed by a fast renormalisation: (hi, lo) += d.
+// (hi, lo) += d for a two-float value: Dekker's Fast2Sum of hi and d, its
+// rounding error folded into lo, then a Fast2Sum renormalisation so that
+// |lo| stays within half an ulp of hi.  The first Fast2Sum is exact when
+// hi's exponent is at least d's; otherwise (a coordinate within one step of
+// zero) the error term is off by at most about half an ulp of d, far below
+// the step's own truncation error.
 __device__ __forceinline__ void two_sum_add(float &hi, float &lo, float d) {
     float s = hi + d;
-    float bp = s - hi;
-    float e = (hi - (s - bp)) + (d - bp);
+    float e = d - (s - hi);
     float l = lo + e;
     float hn = s + l;
     lo = l - (hn - s);
@@ -145,8 +154,10 @@ __device__ __forceinline__ float box_dist2(float cx, float cy, float cz, const f
     return dx * dx + dy * dy + dz * dz;
 }
 
-__device__ __forceinline__ bool finite3(V3<float> v) {
-    return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z);
+// One test for six components: a NaN or infinity in any of them makes the
+// sum non-finite (as does a sum beyond the float range, a failed state too).
+__device__ __forceinline__ bool finite6(V3<float> a, V3<float> b) {
+    return __builtin_isfinite(((a.x + a.y) + (a.z + b.x)) + (b.y + b.z));
 }
 
 template <int KIND, bool COUNT> struct Acc32 {

@@ -106,7 +106,10 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
 // step chord enters the support sphere of an eligible bump stops on the
 // sphere (the partial step is committed, its fraction of h added to t) and
 // is queued for the crossing stage that runs after the pass.
-template <int KIND, int STEP, bool COUNT, bool SURR = false>
+// TAPE: differentiation forward (graph metric, RK4): checkpoints of the
+// state every ckpt_every steps; a separate instantiation, so that the plain
+// trace carries no per-step checkpoint test.
+template <int KIND, int STEP, bool COUNT, bool SURR = false, bool TAPE = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 ? 6 : 7, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                 st_bl += __popcll(bmask);
                 st_ol += __popcll(sm[0]) + __popcll(sm[1]) + __popcll(sm[2]) + __popcll(sm[3]) + __popcll(omask);
 
-                if (A.tape_ck && act && steps % A.ckpt_every == 0) {
+                if (TAPE && act && steps % A.ckpt_every == 0) {
                     float *ck = A.tape_ck + ((((int64_t)(id >> 6) * A.n_ckpt + steps / A.ckpt_every) * 9) * 64 + (id & 63));
                     ck[0 * 64] = xh.x;
                     ck[1 * 64] = xh.y;
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                     } else {
                         ok = step_euler<float>(acc, p, y, A.h, dx, dv);
                     }
-                    bool done_fail = !ok || !finite3(dx) || !finite3(dv);
+                    bool done_fail = !ok || !finite6(dx, dv);
                     bool done_miss = false;
                     if (!done_fail && accepted) {
                         if (COUNT) c_obj += lane_objs;
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                         write_out(A, qbase + pix, xh + xl,
                                   STEP == STEP_RK45 ? th + tl : (float)steps * A.h + (SURR ? th + tl : 0.f), y,
                                   done_fail ? -2 : -1, steps);
-                        if (A.tape_hit) A.tape_hit[(int64_t)(qbase + pix) * rti::TAPE_REC + 11] = __int_as_float(-1);
+                        if (TAPE) A.tape_hit[(int64_t)(qbase + pix) * rti::TAPE_REC + 11] = __int_as_float(-1);
                     }
                     if (done_fail || done_miss || hit) alive = false;
                 }
@@ -780,14 +783,14 @@ __global__ void k_reset(int *ctr, int n_words, unsigned long long *stats) {
     if (blockIdx.x == 0 && threadIdx.x < rti::ST_N) stats[threadIdx.x] = 0;
 }
 
-template <int KIND, int STEP, bool SURR>
+template <int KIND, int STEP, bool SURR, bool TAPE = false>
 hipError_t launch_pass(const TraceArgs &a, const rti::DeviceData &d, int p, int grid, hipStream_t s) {
     if (a.count)
-        hipLaunchKernelGGL((k_trace_pass<KIND, STEP, true, SURR>), dim3(grid), dim3(256), 0, s, a, p, d.bump_f,
-                           d.sph_f, d.pln_f, d.tor_f);
+        hipLaunchKernelGGL((k_trace_pass<KIND, STEP, true, SURR, TAPE>), dim3(grid), dim3(256), 0, s, a, p,
+                           d.bump_f, d.sph_f, d.pln_f, d.tor_f);
     else
-        hipLaunchKernelGGL((k_trace_pass<KIND, STEP, false, SURR>), dim3(grid), dim3(256), 0, s, a, p, d.bump_f,
-                           d.sph_f, d.pln_f, d.tor_f);
+        hipLaunchKernelGGL((k_trace_pass<KIND, STEP, false, SURR, TAPE>), dim3(grid), dim3(256), 0, s, a, p,
+                           d.bump_f, d.sph_f, d.pln_f, d.tor_f);
     return hipGetLastError();
 }
 
@@ -810,6 +813,12 @@ hipError_t launch_kind_step(const TraceArgs &a, const rti::DeviceData &d, int n_
         }
         hipError_t e;
         if constexpr (KIND == KIND_GRAPH && STEP == STEP_RK4) {
+            if (a.tape_ck) {
+                e = launch_pass<KIND, STEP, false, true>(a, d, p, grid, s);
+                if (e != hipSuccess) return e;
+                if (ev) (void)hipEventRecord(ev[2 + p], s);
+                continue;
+            }
             if (a.surr) {
                 e = launch_pass<KIND, STEP, true>(a, d, p, grid, s);
                 if (e != hipSuccess) return e;
@@ -871,6 +880,8 @@ hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, i
     if (e != hipSuccess) return e;
     if (ev) (void)hipEventRecord(ev[1], s);
     const int step = a.step_kind;
+    // checkpoint tapes and learned crossings exist for the graph metric with RK4 only
+    if ((a.tape_ck || a.surr) && !(a.kind == KIND_GRAPH && step == STEP_RK4)) return hipErrorInvalidValue;
     switch (a.kind) {
     case KIND_EUCLID: RT_DISPATCH(KIND_EUCLID, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_GRAPH: RT_DISPATCH(KIND_GRAPH, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)

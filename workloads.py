@@ -175,10 +175,12 @@ def single_bump_64(width=64, height=64):
 
 def bumps16_1080p(width=1920, height=1080, kind=RK4):
     # one pass (no compaction): measured fastest for this frame
-    r = (rule(RK4, h=0.005, max_steps=4000, t_max=20.0, pass_steps=4000) if kind == RK4 else
-         rule(RK45, h=0.005, max_steps=4000, t_max=20.0, rtol=1e-6, atol=1e-6,
-              h_min=1e-6, h_max=0.02, pass_steps=4000))
-    return dict(name="bumps16_1080p" + ("" if kind == RK4 else "_rk45"),
+    if kind == RK45:
+        r = rule(RK45, h=0.005, max_steps=4000, t_max=20.0, rtol=1e-6, atol=1e-6,
+                 h_min=1e-6, h_max=0.02, pass_steps=4000)
+    else:
+        r = rule(kind, h=0.005, max_steps=4000, t_max=20.0, pass_steps=4000)
+    return dict(name="bumps16_1080p" + {RK4: "", RK45: "_rk45", EULER: "_euler"}[kind],
                 camera=camera(width, height),
                 metric=metric(GRAPH_GAUSS, random_bumps(16, seed=0)),
                 scene=scene(spheres=random_spheres(64, seed=1),
@@ -243,6 +245,8 @@ WORKLOADS = {
     "single_bump_64": single_bump_64,
     "bumps16_1080p": bumps16_1080p,
     "bumps16_1080p_rk45": lambda **kw: bumps16_1080p(kind=RK45, **kw),
+    "bumps16_1080p_euler": lambda **kw: bumps16_1080p(kind=EULER, **kw),
+    "euler_vs_rk4_1080p": lambda **kw: bumps16_1080p(kind=EULER, **kw),
     "twist_4k": twist_4k,
     "adjoint_64x512": adjoint_64x512,
     "surrogate_64_4k": surrogate_64_4k,
