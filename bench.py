@@ -34,9 +34,15 @@ FLOPS = {
     "graph_bump": 27,        # one bump inside its cut sphere (incl. exp2)
     "twist_eval": 208,       # J, D^2 phi[y,y], Sherman-Morrison solve (incl. 6 transcendentals)
     "ztwist_eval": 40,
-    "rk4_step": 109,         # stage states, combination, TwoSum position update, chord length
-    "euler_step": 35,
-    "dp5_attempt": 460,      # 6 stages' states, 5th-order update, embedded error, control
+    # RK4: step 74 (3 stage states 36, stage sums 30, h/2 and h/6 scaling 8), x_hi + x_lo 3,
+    # chord length 5, two-float position update 21 (7 per coordinate), velocity update 3
+    "rk4_step": 106,
+    # Euler: h y and h a 6, x_hi + x_lo 3, chord length 5, two-float update 21, velocity update 3
+    "euler_step": 38,
+    # DP5(4): stage states 280 (6 positions with their h^2 terms, 6 velocities), 5th-order
+    # increments 66, embedded error 77, h^2 1; error norm and step control 58; x_hi + x_lo,
+    # chord length, two-float position and time updates, velocity update 39
+    "dp5_attempt": 521,
     "obj_test": 20,          # one segment-object test
 }
 

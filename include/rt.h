@@ -223,10 +223,10 @@ typedef struct rt_stats {
     uint64_t rays;          /* rays launched */
     uint64_t ray_steps;     /* accepted integration steps, all rays */
     uint64_t attempts;      /* RK45 trial steps incl. rejected; = ray_steps otherwise */
-    uint64_t wave_iters;    /* wave-wide step iterations */
-    uint64_t lane_iters;    /* active lanes summed over wave iterations */
-    uint64_t bump_list_sum; /* culled bump-list length summed over wave iterations */
-    uint64_t obj_list_sum;  /* culled object-list length summed over wave iterations */
+    uint64_t wave_iters;    /* COUNT_WORK: wave-wide step iterations */
+    uint64_t lane_iters;    /* COUNT_WORK: active lanes summed over wave iterations */
+    uint64_t bump_list_sum; /* COUNT_WORK: culled bump-list length summed over wave iterations */
+    uint64_t obj_list_sum;  /* COUNT_WORK: culled object-list length summed over wave iterations */
     uint64_t refined;       /* hits refined in FP64 */
     uint64_t acc_evals;     /* COUNT_WORK: lane acceleration evaluations */
     uint64_t bump_evals;    /* COUNT_WORK: lane bump terms with |x - c| inside the cut */

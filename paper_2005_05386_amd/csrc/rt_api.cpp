@@ -248,6 +248,8 @@ rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
         bd[8 * i + 3] = b.cz;
         bd[8 * i + 4] = b.sigma;
         bd[8 * i + 5] = cut * cut;
+        bd[8 * i + 6] = 1.0 / (s * s);
+        bd[8 * i + 7] = (double)b.a * bd[8 * i + 6];
     }
     if (!c->host_only) {
         rt_status st = sync_last(c);

@@ -97,8 +97,8 @@ __device__ __forceinline__ int mbcnt64(uint64_t m) {
 // ------------------------------------------------------ metric parameters
 // Graph metric, one bump, packed for single precision (two float4):
 //   B0 = (cx, cy, cz, nk)   nk = -log2(e) / (2 sigma^2)  so exp(-r^2/2s^2) = exp2(nk r^2)
-//   B1 = (as, s, cut2, 0)   as = a / sigma^2, s = 1 / sigma^2, cut2 = (cull sigma)^2
-// and in double: (a, cx, cy, cz, sigma, cut2, 0, 0).
+//   B1 = (as, s, cut2, sigma)   as = a / sigma^2, s = 1 / sigma^2, cut2 = (cull sigma)^2
+// and in double: (a, cx, cy, cz, sigma, cut2, s, as).
 struct MetricArgs {
     int kind, n_sets, n_bumps;
     float twist_amp, twist_theta0;
@@ -194,11 +194,11 @@ __device__ __forceinline__ V3<double> graph_accel_f64(const double *__restrict__
         int b = __builtin_ctzll(mask);
         mask &= mask - 1;
         const double *pb = B + 8 * b;
-        double s = 1.0 / (pb[4] * pb[4]);
+        double s = pb[6];
         double dx = p.x - pb[1], dy = p.y - pb[2], dz = p.z - pb[3];
         double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 > pb[5]) continue;
-        double w = pb[0] * s * exp(-0.5 * r2 * s);
+        double w = pb[7] * exp(-0.5 * r2 * s);
         gx -= w * dx;
         gy -= w * dy;
         gz -= w * dz;

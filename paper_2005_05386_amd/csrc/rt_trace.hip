@@ -296,10 +296,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                         }
                     }
                 }
-                st_wave++;
-                st_lane += __popcll(am);
-                st_bl += __popcll(bmask);
-                st_ol += __popcll(sm[0]) + __popcll(sm[1]) + __popcll(sm[2]) + __popcll(sm[3]) + __popcll(omask);
+                // wave statistics (work counting only; the lane count is also DP5's attempt count)
+                if (COUNT || STEP == STEP_RK45) st_lane += __popcll(am);
+                if (COUNT) {
+                    st_wave++;
+                    st_bl += __popcll(bmask);
+                    st_ol += __popcll(sm[0]) + __popcll(sm[1]) + __popcll(sm[2]) + __popcll(sm[3]) + __popcll(omask);
+                }
 
                 if (TAPE && act && steps % A.ckpt_every == 0) {
                     float *ck = A.tape_ck + ((((int64_t)(id >> 6) * A.n_ckpt + steps / A.ckpt_every) * 9) * 64 + (id & 63));
@@ -572,12 +575,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
     if (lane == 0) {
         if (st_rays) atomicAdd(A.stats + rti::ST_RAYS, st_rays);
         atomicAdd(A.stats + rti::ST_STEPS, st_steps);
-        atomicAdd(A.stats + rti::ST_WAVE_ITERS, st_wave);
-        atomicAdd(A.stats + rti::ST_LANE_ITERS, st_lane);
-        atomicAdd(A.stats + rti::ST_BUMP_LIST, st_bl);
-        atomicAdd(A.stats + rti::ST_OBJ_LIST, st_ol);
         atomicAdd(A.stats + rti::ST_ATTEMPTS, STEP == STEP_RK45 ? st_lane : st_steps);
         if (COUNT) {
+            atomicAdd(A.stats + rti::ST_WAVE_ITERS, st_wave);
+            atomicAdd(A.stats + rti::ST_LANE_ITERS, st_lane);
+            atomicAdd(A.stats + rti::ST_BUMP_LIST, st_bl);
+            atomicAdd(A.stats + rti::ST_OBJ_LIST, st_ol);
             atomicAdd(A.stats + rti::ST_ACC_EVALS, st_ev);
             atomicAdd(A.stats + rti::ST_BUMP_EVALS, st_be);
             atomicAdd(A.stats + rti::ST_OBJ_TESTS, st_ot);
