@@ -67,11 +67,16 @@ __device__ __forceinline__ GraphAccum graph_sums(const float4 *__restrict__ B, u
     GraphAccum G{0.f, 0.f, 0.f, 0.f};
     if (!mask) return G;
     const float yy = dot(y, y);
-    const int b0 = __builtin_ctzll(mask);
-    graph_bump_f32<true>(B[2 * b0], B[2 * b0 + 1], p, y, yy, G);
-    for (uint64_t m = mask & (mask - 1); m; m &= m - 1) {
-        const int b = __builtin_ctzll(m);
-        graph_bump_f32(B[2 * b], B[2 * b + 1], p, y, yy, G);
+    float4 c0, c1;
+    int b = __builtin_ctzll(mask);
+    mask &= ~(1ull << b);
+    bump_at(B, b, c0, c1);
+    graph_bump_f32<true>(c0, c1, p, y, yy, G);
+    while (mask) {
+        b = __builtin_ctzll(mask);
+        mask &= ~(1ull << b);
+        bump_at(B, b, c0, c1);
+        graph_bump_f32(c0, c1, p, y, yy, G);
     }
     return G;
 }
@@ -89,9 +94,11 @@ __device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, uint64_t
     // a = -(q / D) g:  gbar = -(q/D) abar + (2 q / D^2)(g . abar) g,  qbar = -(g . abar)/D
     const float qbar = -ga * invD;
     const V3<float> gbar = axpy(2.0f * q * ga * invD * invD, g, (-q * invD) * ab);
-    for (uint64_t m = mask; m; m &= m - 1) {
+    for (uint64_t m = mask; m;) {
         const int b = __builtin_ctzll(m);
-        const float4 b0 = B[2 * b], b1 = B[2 * b + 1];
+        m &= ~(1ull << b);
+        float4 b0, b1;
+        bump_at(B, b, b0, b1);
         const V3<float> d = mk(p.x - b0.x, p.y - b0.y, p.z - b0.z);
         const float r2 = dot(d, d);
         if (!(r2 <= b1.z)) continue;

@@ -143,10 +143,17 @@ __device__ __forceinline__ V3<float> graph_finish(const GraphAccum &A) {
     return {c * A.gx, c * A.gy, c * A.gz};
 }
 
-// Walk a wave-uniform bump mask; bump data by scalar loads, two bumps per
-// iteration so that both bumps' loads are in flight before the first wait.
-// The accumulation order (increasing bump index) is unchanged.  COUNT adds
-// the number of bumps inside their cut sphere at p to *n_in.
+// Walk a wave-uniform bump mask in increasing index order; bump data by
+// scalar loads at a 32-bit byte offset from B, the bit cleared in place, so
+// that each bump costs a handful of scalar instructions next to its vector
+// work.  COUNT adds the number of bumps inside their cut sphere at p to
+// *n_in.
+__device__ __forceinline__ void bump_at(const float4 *__restrict__ B, int b, float4 &b0, float4 &b1) {
+    const float4 *q = (const float4 *)((const char *)B + ((unsigned)b << 5));
+    b0 = q[0];
+    b1 = q[1];
+}
+
 template <bool COUNT = false>
 __device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
                                                      V3<float> y, unsigned *n_in = nullptr) {
@@ -160,26 +167,19 @@ __device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ 
     };
     {
         const int b = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        const float4 b0 = B[2 * b], b1 = B[2 * b + 1];
+        mask &= ~(1ull << b);
+        float4 b0, b1;
+        bump_at(B, b, b0, b1);
         graph_bump_f32<true>(b0, b1, p, y, yy, A);
         if (COUNT) n += in_cut(b0, b1);
     }
     while (mask) {
         const int b = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        if (mask) {
-            const int c = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const float4 b0 = B[2 * b], b1 = B[2 * b + 1], c0 = B[2 * c], c1 = B[2 * c + 1];
-            graph_bump_f32(b0, b1, p, y, yy, A);
-            graph_bump_f32(c0, c1, p, y, yy, A);
-            if (COUNT) n += in_cut(b0, b1) + in_cut(c0, c1);
-        } else {
-            const float4 b0 = B[2 * b], b1 = B[2 * b + 1];
-            graph_bump_f32(b0, b1, p, y, yy, A);
-            if (COUNT) n += in_cut(b0, b1);
-        }
+        mask &= ~(1ull << b);
+        float4 b0, b1;
+        bump_at(B, b, b0, b1);
+        graph_bump_f32(b0, b1, p, y, yy, A);
+        if (COUNT) n += in_cut(b0, b1);
     }
     if (COUNT) *n_in += n;
     return graph_finish(A);
