@@ -172,7 +172,7 @@ typedef struct rt_step_rule {
     float t_max;       /* > 0; RK4/Euler rays also stop at max_steps */
     int cull_every;    /* K: steps between per-wave re-culls of bumps/objects, 1..256 (16) */
     int pass_steps;    /* S: steps per launch before surviving rays are compacted, >= 16 (256) */
-    int bisect_iters;  /* FP64 bisection halvings for the hit, 0..60 (32) */
+    int bisect_iters;  /* FP64 bisection halvings for the hit, 0..60 (24: h 2^-24 is below the float spacing of the hit) */
     int flags;         /* RT_FLAG_* bits, 0 for a plain trace */
 } rt_step_rule;
 

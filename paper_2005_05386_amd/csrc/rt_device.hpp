@@ -154,9 +154,14 @@ __device__ __forceinline__ void bump_at(const float4 *__restrict__ B, int b, flo
     b1 = q[1];
 }
 
-template <bool COUNT = false>
+// SREG: the caller's mask is held in scalar registers; a fresh scalar copy
+// per evaluation keeps the emptiness test a scalar branch instead of a lane
+// mask carried across the stages of a step (the compiler rejects the copy,
+// at build time, for a mask it cannot keep in scalar registers).
+template <bool COUNT = false, bool SREG = false>
 __device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
                                                      V3<float> y, unsigned *n_in = nullptr) {
+    if constexpr (SREG) __asm__("" : "+s"(mask));
     if (!mask) return mk(0.f, 0.f, 0.f);
     GraphAccum A;
     float yy = dot(y, y);

@@ -160,7 +160,8 @@ __device__ __forceinline__ bool finite6(V3<float> a, V3<float> b) {
     return __builtin_isfinite(((a.x + a.y) + (a.z + b.x)) + (b.y + b.z));
 }
 
-template <int KIND, bool COUNT> struct Acc32 {
+// SREG: the bump mask is wave-uniform and held in scalar registers.
+template <int KIND, bool COUNT, bool SREG = false> struct Acc32 {
     const float4 *__restrict__ B;
     uint64_t mask;
     float amp, th0;
@@ -168,7 +169,7 @@ template <int KIND, bool COUNT> struct Acc32 {
     __device__ __forceinline__ bool operator()(V3<float> p, V3<float> y, V3<float> &a) const {
         if (COUNT) *n_eval += 1;
         if constexpr (KIND == KIND_GRAPH) {
-            a = graph_accel_f32<COUNT>(B, mask, p, y, n_bump);
+            a = graph_accel_f32<COUNT, SREG>(B, mask, p, y, n_bump);
             return true;
         } else if constexpr (KIND == KIND_TWIST) {
             return twist_accel<float>(amp, th0, p, y, a);

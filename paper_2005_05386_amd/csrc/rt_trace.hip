@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                     ck[7 * 64] = y.y;
                     ck[8 * 64] = y.z;
                 }
-                Acc32<KIND, COUNT> acc{Bs, bmask, A.twist_amp, A.twist_theta0, &c_eval, &c_bump};
+                Acc32<KIND, COUNT, true> acc{Bs, bmask, A.twist_amp, A.twist_theta0, &c_eval, &c_bump};
                 // The step is computed, its chord tested against the scene on
                 // the state before the step, and only then committed: a hit
                 // records that pre-step state without keeping copies of it.
@@ -376,46 +376,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                     bool done_miss = false;
                     if (!done_fail && accepted) {
                         if (COUNT) c_obj += lane_objs;
-                        // ---- segment versus scene, chord [x, x + dx]
-                        float DD = dot(dx, dx);
+                        // ---- segment versus scene, chord [x, x + dx] (a scalar branch:
+                        // most wave iterations list no object)
+                        if ((sm[0] | sm[1] | sm[2] | sm[3] | omask) != 0) {
+                            const float DD = dot(dx, dx);
 #pragma unroll
-                        for (int w = 0; w < 4; ++w) {
-                            uint64_t m = sm[w];
+                            for (int w = 0; w < 4; ++w) {
+                                uint64_t m = sm[w];
+                                while (m) {
+                                    int b = __builtin_ctzll(m);
+                                    m &= m - 1;
+                                    int idx = 64 * w + b;
+                                    float4 s = SPH[idx];
+                                    V3<float> o = mk((xh.x - s.x) + xl.x, (xh.y - s.y) + xl.y, (xh.z - s.z) + xl.z);
+                                    float sc = sphere_chord(s, o, dx, DD);
+                                    if (sc < hit_s) {
+                                        hit_s = sc;
+                                        hit_id = idx;
+                                    }
+                                }
+                            }
+                            uint64_t m = omask;
                             while (m) {
                                 int b = __builtin_ctzll(m);
                                 m &= m - 1;
-                                int idx = 64 * w + b;
-                                float4 s = SPH[idx];
-                                V3<float> o = mk((xh.x - s.x) + xl.x, (xh.y - s.y) + xl.y, (xh.z - s.z) + xl.z);
-                                float sc = sphere_chord(s, o, dx, DD);
-                                if (sc < hit_s) {
-                                    hit_s = sc;
-                                    hit_id = idx;
+                                float F0, F1;
+                                int oid;
+                                if (b < 8) {
+                                    float4 pl = PLN[b];
+                                    F0 = pl.x * p.x + pl.y * p.y + pl.z * p.z - pl.w;
+                                    F1 = F0 + (pl.x * dx.x + pl.y * dx.y + pl.z * dx.z);
+                                    oid = ns + b;
+                                } else {
+                                    const float *tp = TOR + 8 * (b - 8);
+                                    F0 = torus_sdf<float>(tp, p);
+                                    F1 = torus_sdf<float>(tp, p + dx);
+                                    oid = ns + np + (b - 8);
                                 }
-                            }
-                        }
-                        uint64_t m = omask;
-                        while (m) {
-                            int b = __builtin_ctzll(m);
-                            m &= m - 1;
-                            float F0, F1;
-                            int oid;
-                            if (b < 8) {
-                                float4 pl = PLN[b];
-                                F0 = pl.x * p.x + pl.y * p.y + pl.z * p.z - pl.w;
-                                F1 = F0 + (pl.x * dx.x + pl.y * dx.y + pl.z * dx.z);
-                                oid = ns + b;
-                            } else {
-                                const float *tp = TOR + 8 * (b - 8);
-                                F0 = torus_sdf<float>(tp, p);
-                                F1 = torus_sdf<float>(tp, p + dx);
-                                oid = ns + np + (b - 8);
-                            }
-                            if ((F0 > 0.f) != (F1 > 0.f)) {
-                                float sc = fminf(fmaxf(F0 / (F0 - F1), 0.f), 1.f);
-                                if (sc < hit_s) {
-                                    hit_s = sc;
-                                    hit_id = oid;
+                                if ((F0 > 0.f) != (F1 > 0.f)) {
+                                    float sc = fminf(fmaxf(F0 / (F0 - F1), 0.f), 1.f);
+                                    if (sc < hit_s) {
+                                        hit_s = sc;
+                                        hit_id = oid;
+                                    }
                                 }
                             }
                         }
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                                 const V3<float> on = o + dx;
                                 if (b != skip && o2 >= c0.w && dot(on, on) < c0.w) {
                                     // smaller root of |o + s dx|^2 = R^2
-                                    const float B = dot(o, dx), C = o2 - c0.w;
+                                    const float B = dot(o, dx), C = o2 - c0.w, DD = dot(dx, dx);
                                     const float disc = fmaxf(B * B - DD * C, 0.f);
                                     const float sr = fminf(fmaxf((-B - sqrtf(disc)) / DD, 0.f), 1.f);
                                     if (sr < ent_s) {

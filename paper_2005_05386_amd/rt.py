@@ -150,7 +150,7 @@ def camera_struct(cam):
 def rule_struct(r):
     return rt_step_rule(int(r["kind"]), float(r["h"]), float(r.get("rtol", 1e-6)), float(r.get("atol", 1e-6)),
                         float(r.get("h_min", 1e-6)), float(r.get("h_max", r["h"])), float(r["t_max"]),
-                        int(r.get("cull_every", 16)), int(r.get("pass_steps", 256)), int(r.get("bisect_iters", 32)),
+                        int(r.get("cull_every", 16)), int(r.get("pass_steps", 256)), int(r.get("bisect_iters", 24)),
                         int(r.get("flags", 0)))
 
 

@@ -132,7 +132,7 @@ def empty8():
 
 def rule(kind=RK4, h=0.01, max_steps=1000, t_max=None, rtol=1e-6, atol=1e-6,
          h_min=1e-6, h_max=0.02, cull_every=16, pass_steps=256,
-         bisect_iters=32):
+         bisect_iters=24):
     if t_max is None:
         t_max = float(np.float32(h) * max_steps) if kind != RK45 else 20.0
     return dict(kind=int(kind), h=float(np.float32(h)), max_steps=int(max_steps),
