@@ -17,7 +17,11 @@ Pinning status (what fixes each function to something other than itself):
                                     single-bump quadrature   -- pinned
   pullback acceleration (Eq. 5.8)   generic Christoffel symbols; geodesics are
                                     preimages of straight lines
-                                    (closed form for the z-twist) -- pinned
+                                    (closed form for the z-twist) -- pinned;
+                                    for the composed local deformations
+                                    (Sec. 6.2) also the map and its Jacobian
+                                    against an independent evaluation and
+                                    finite differences        -- pinned
   RK4 / DP5 / Euler                 step-convergence orders, g(y,y)
                                     conservation, DP5 order conditions,
                                     quadrature hits           -- pinned
@@ -36,7 +40,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rt_oracle.c")
 _LIB = os.path.join(_HERE, "_rt_oracle.so")
 
-EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST = 0, 1, 2, 3
+EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST, PULLBACK_DEFORM = 0, 1, 2, 3, 4
 RK4, RK45, EULER = 0, 1, 2
 
 
@@ -53,7 +57,8 @@ def build(force=True):
 
 class _Metric(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_bumps", C.c_int), ("bumps", C.POINTER(C.c_double)),
-                ("twist_amp", C.c_double), ("twist_theta0", C.c_double)]
+                ("twist_amp", C.c_double), ("twist_theta0", C.c_double),
+                ("n_deforms", C.c_int), ("deforms", C.POINTER(C.c_double))]
 
 
 class _Scene(C.Structure):
@@ -117,8 +122,16 @@ class Oracle:
                 b = b[set_index]
             b = b.astype(np.float64)
         self._bumps = np.ascontiguousarray(b.reshape(-1, 5))
+        dfm = metric.get("deforms")
+        if dfm is None:
+            dfm = np.zeros((0, 10))
+        dfm = np.asarray(dfm, np.float32)
+        if dfm.ndim == 3:
+            dfm = dfm[set_index]
+        self._deforms = np.ascontiguousarray(dfm.astype(np.float64).reshape(-1, 10))
         self.m = _Metric(int(metric["kind"]), int(self._bumps.shape[0]), _dptr(self._bumps),
-                         float(metric.get("twist_amp", 0.4)), float(metric.get("twist_theta0", 1.2)))
+                         float(metric.get("twist_amp", 0.4)), float(metric.get("twist_theta0", 1.2)),
+                         int(self._deforms.shape[0]), _dptr(self._deforms))
         self._sp = np.ascontiguousarray(np.asarray(scene["spheres"], np.float32).astype(np.float64).reshape(-1, 4))
         self._pl = np.ascontiguousarray(np.asarray(scene["planes"], np.float32).astype(np.float64).reshape(-1, 4))
         self._to = np.ascontiguousarray(np.asarray(scene["tori"], np.float32).astype(np.float64).reshape(-1, 8))

@@ -15,6 +15,8 @@
  *   - Gamma for diffeomorphism pullbacks (Sec. 5.2, Thm 5.1 / Eq. 5.7,
  *     flow Eq. 5.8 read with index k on the left and right), the Jacobian
  *     and second derivatives of the map taken with hyper-dual numbers;
+ *     the maps include compositions of local deformations (Sec. 6.2,
+ *     Eqs. 6.1 and 6.2), differentiated as one map;
  *   - ray marching: the integration polygon, each segment tested against
  *     the scene (Sec. 4.1).  Integrators: the paper's explicit Euler
  *     (Eq. 4.1), classical RK4 and Dormand-Prince 5(4) (the Runge-Kutta
@@ -145,6 +147,24 @@ static hd hd_sqrt(hd a)
  *                                                sin z x + cos z y, z). */
 static void phi_hd(const orc_metric *m, const hd x[3], hd out[3])
 {
+    if (m->kind == ORC_PULLBACK_DEFORM) {
+        /* Phi = Phi_1 o Phi_2 o ... o Phi_k (Sec. 6.2): Phi_k acts first.
+         * Phi_i(p) = p + f_i(p) v_i (Eq. 6.2), f_i the Gaussian of Eq. 6.1
+         * with amplitude a, centre c and spreads sx, sy, sz. */
+        hd q[3] = {x[0], x[1], x[2]};
+        for (int i = m->n_deforms - 1; i >= 0; i--) {
+            const double *P = m->deforms + 10 * i;
+            hd e = hd_c(0.0);
+            for (int k = 0; k < 3; k++) {
+                hd d = hd_sub(q[k], hd_c(P[1 + k]));
+                e = hd_add(e, hd_scale(hd_mul(d, d), -1.0 / (2.0 * P[4 + k] * P[4 + k])));
+            }
+            hd f = hd_scale(hd_exp(e), P[0]);
+            for (int k = 0; k < 3; k++) q[k] = hd_add(q[k], hd_scale(f, P[7 + k]));
+        }
+        for (int k = 0; k < 3; k++) out[k] = q[k];
+        return;
+    }
     if (m->kind == ORC_PULLBACK_ZTWIST) {
         hd c = hd_cos(x[2]), s = hd_sin(x[2]);
         out[0] = hd_sub(hd_mul(c, x[0]), hd_mul(s, x[1]));
@@ -239,6 +259,7 @@ int orc_accel(const orc_metric *m, const double x[3], const double y[3], double 
         return 1;
     case ORC_PULLBACK_TWIST:
     case ORC_PULLBACK_ZTWIST:
+    case ORC_PULLBACK_DEFORM:
         return pullback_accel(m, x, y, a);
     }
     return 0;
@@ -253,7 +274,7 @@ void orc_metric_tensor(const orc_metric *m, const double x[3], double g[9])
         graph_derivs(m, x, gr, H);
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++) g[3 * i + j] = (i == j ? 1.0 : 0.0) + gr[i] * gr[j];
-    } else if (m->kind == ORC_PULLBACK_TWIST || m->kind == ORC_PULLBACK_ZTWIST) {
+    } else if (m->kind == ORC_PULLBACK_TWIST || m->kind == ORC_PULLBACK_ZTWIST || m->kind == ORC_PULLBACK_DEFORM) {
         double J[9];
         pullback_jacobian(m, x, J);
         for (int i = 0; i < 3; i++)

@@ -16,6 +16,7 @@
 #define ORC_GRAPH_GAUSS 1
 #define ORC_PULLBACK_TWIST 2
 #define ORC_PULLBACK_ZTWIST 3
+#define ORC_PULLBACK_DEFORM 4
 
 #define ORC_RK4 0
 #define ORC_RK45 1
@@ -26,6 +27,8 @@ typedef struct {
     int n_bumps;
     const double *bumps; /* [n_bumps][5] a, cx, cy, cz, sigma */
     double twist_amp, twist_theta0;
+    int n_deforms;
+    const double *deforms; /* [n_deforms][10] a, cx, cy, cz, sx, sy, sz, vx, vy, vz */
 } orc_metric;
 
 typedef struct {

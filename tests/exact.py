@@ -133,6 +133,17 @@ def ztwist_inv(X):
     return np.stack([c * X[..., 0] + s * X[..., 1], -s * X[..., 0] + c * X[..., 1], X[..., 2]], axis=-1)
 
 
+def deform_phi(x, deforms):
+    """Phi = Phi_1 o ... o Phi_k, Phi_i(p) = p + f_i(p) v_i (Sec. 6.2,
+    Eqs. 6.1-6.2); rows (a, cx, cy, cz, sx, sy, sz, vx, vy, vz), Phi_k
+    applied first (complex-safe)."""
+    q = [x[0], x[1], x[2]]
+    for a, cx, cy, cz, sx, sy, sz, vx, vy, vz in np.asarray(deforms, np.float64).reshape(-1, 10)[::-1]:
+        f = a * np.exp(-0.5 * (((q[0] - cx) / sx) ** 2 + ((q[1] - cy) / sy) ** 2 + ((q[2] - cz) / sz) ** 2))
+        q = [q[0] + f * vx, q[1] + f * vy, q[2] + f * vz]
+    return np.array(q)
+
+
 def cs_grad(fun, x, h=1e-30):
     """Complex-step gradient of a scalar function (exact to rounding)."""
     g = np.zeros(3)

@@ -122,12 +122,25 @@ def test_sign_invariance_is_bitwise():
 
 
 # ------------------------------------------------------ pullback algebra
-@pytest.mark.parametrize("kind", [W.PULLBACK_TWIST, W.PULLBACK_ZTWIST])
+# Strong local deformations around the origin (six of them, overlapping, so
+# that the order of the composition matters).
+DEFORMS = W.random_deforms(6, seed=21, box=0.8, spread=(0.4, 0.9), kappa=(0.4, 0.8))
+
+
+def _pullback(kind):
+    if kind == W.PULLBACK_DEFORM:
+        return W.metric(kind, deforms=DEFORMS), lambda z: exact.deform_phi(z, DEFORMS)
+    return W.metric(kind), (exact.twist_phi if kind == W.PULLBACK_TWIST else exact.ztwist_phi)
+
+
+PULLBACKS = [W.PULLBACK_TWIST, W.PULLBACK_ZTWIST, W.PULLBACK_DEFORM]
+
+
+@pytest.mark.parametrize("kind", PULLBACKS)
 def test_pullback_accel_matches_generic_christoffel(kind):
     """Thm 5.1 / Eq. 5.8 equals the generic symbols of g = J^T J."""
-    m = W.metric(kind)
+    m, phi = _pullback(kind)
     orc = oracle.Oracle(m, W.scene())
-    phi = exact.twist_phi if kind == W.PULLBACK_TWIST else exact.ztwist_phi
     x, y = _rand_points(30, 7, box=1.5)
     worst = 0.0
     for q in range(len(x)):
@@ -141,9 +154,8 @@ def test_pullback_accel_matches_generic_christoffel(kind):
 
 
 def _straight_line_residual(kind, h, n, seed=11):
-    m = W.metric(kind)
+    m, phi = _pullback(kind)
     orc = oracle.Oracle(m, W.scene())
-    phi = exact.twist_phi if kind == W.PULLBACK_TWIST else exact.ztwist_phi
     rng = np.random.default_rng(seed)
     worst = 0.0
     for _ in range(4):
@@ -162,13 +174,40 @@ def _straight_line_residual(kind, h, n, seed=11):
     return worst
 
 
-@pytest.mark.parametrize("kind", [W.PULLBACK_TWIST, W.PULLBACK_ZTWIST])
+@pytest.mark.parametrize("kind", PULLBACKS)
 def test_pullback_geodesics_are_preimages_of_lines(kind):
     """phi(x(t)) = phi(p) + t J(p) v; RK4 error O(h^4)."""
     e1 = _straight_line_residual(kind, 0.02, 150)
     e2 = _straight_line_residual(kind, 0.01, 300)
     assert e1 < 1e-5, e1
     assert 10.0 < e1 / e2 < 24.0, (e1, e2)
+
+
+def test_deform_composition_order_matters():
+    """The pins above would fail for the reversed composition: the two
+    orders give different maps for these deformations."""
+    x = np.array([0.1, -0.2, 0.15])
+    fwd = exact.deform_phi(x, DEFORMS)
+    rev = exact.deform_phi(x, DEFORMS[::-1])
+    assert np.abs(fwd - rev).max() > 1e-2
+    orc = oracle.Oracle(W.metric(W.PULLBACK_DEFORM, deforms=DEFORMS), W.scene())
+    J = exact.cs_jac(lambda z: exact.deform_phi(z, DEFORMS), x)
+    assert np.allclose(orc.metric_tensor(x), J.T @ J, rtol=1e-12, atol=1e-12)
+
+
+def test_deform_diffeomorphism_margin():
+    """Each Phi_i of the generator satisfies |a| |v/s| exp(-1/2) = kappa < 1,
+    the condition for 1 + grad f . v > 0 everywhere; check it by brute force
+    on a grid around each centre."""
+    for a, cx, cy, cz, sx, sy, sz, vx, vy, vz in DEFORMS.astype(np.float64):
+        g = np.linspace(-3, 3, 41)
+        X, Y, Z = np.meshgrid(g * sx, g * sy, g * sz, indexing="ij")
+        f = a * np.exp(-0.5 * ((X / sx) ** 2 + (Y / sy) ** 2 + (Z / sz) ** 2))
+        gv = -f * (X / sx ** 2 * vx + Y / sy ** 2 * vy + Z / sz ** 2 * vz)
+        kap = abs(a) * np.sqrt((vx / sx) ** 2 + (vy / sy) ** 2 + (vz / sz) ** 2) * np.exp(-0.5)
+        assert kap < 0.95
+        assert (1.0 + gv).min() > 0.0
+        assert np.isclose(np.abs(gv).max(), kap, rtol=0.05)
 
 
 def test_ztwist_closed_form_geodesic():
