@@ -34,6 +34,13 @@ FLOPS = {
     "graph_bump": 27,        # one bump inside its cut sphere (incl. exp2)
     "twist_eval": 208,       # J, D^2 phi[y,y], Sherman-Morrison solve (incl. 6 transcendentals)
     "ztwist_eval": 40,
+    # composed local deformations: per evaluation the 3x3 solve by the adjugate
+    # (cofactors 27, determinant 5, reciprocal 1, product 15, scale 3); per
+    # deformation inside its cut: d, S d, d.S d 11, exponent 2, f 1, grad f 3,
+    # S d . u 5, u.S u 8, second-order term 3, grad f . w and . u 11, grad f^T M 15,
+    # updates of w, u, q 18, M 18
+    "deform_eval": 51,
+    "deform_term": 95,
     # RK4: step 74 (3 stage states 36, stage sums 30, h/2 and h/6 scaling 8), x_hi + x_lo 3,
     # chord length 5, two-float position update 21 (7 per coordinate), velocity update 3
     "rk4_step": 106,
@@ -103,6 +110,8 @@ def algorithmic_flops(kind, step, st):
         f = FLOPS["twist_eval"] * ev
     elif kind == 3:
         f = FLOPS["ztwist_eval"] * ev
+    elif kind == 4:
+        f = FLOPS["deform_eval"] * ev + FLOPS["deform_term"] * st["bump_evals"]
     else:
         f = 0
     if step == 0:
@@ -476,6 +485,7 @@ def main():
         "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"],
                    "n_sets": tr.n_sets, "step_rule": ["RK4", "RK45", "Euler"][rule["kind"]], "h": rule["h"],
                    "max_steps": ms_steps, "bumps": int(wl["metric"]["bumps"].shape[1]),
+                   "deforms": int(wl["metric"]["deforms"].shape[1]) if "deforms" in wl["metric"] else 0,
                    "spheres": int(len(wl["scene"]["spheres"]))},
         "ray_steps_per_s": work["ray_steps"] / (ms / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 2
+#define RT_ABI_VERSION 3
 
 typedef enum rt_status {
     RT_OK = 0,
@@ -86,12 +86,27 @@ const char *rt_last_error(const rt_ctx *ctx);
  * RT_METRIC_PULLBACK_ZTWIST  pull-back of the z-twist of Sec. 5.2,
  *                            Phi(x,y,z) = (cos z x - sin z y,
  *                                          sin z x + cos z y, z).
+ * RT_METRIC_PULLBACK_DEFORM  pull-back g = J^T J (Eq. 5.6) of a composition
+ *                            Phi = Phi_1 o Phi_2 o ... o Phi_k of local
+ *                            deformations (Sec. 6.2, "Composing
+ *                            diffeomorphisms"; Phi_k acts first), each
+ *                            Phi_i(p) = p + f_i(p) v_i (Eq. 6.2) with f_i
+ *                            the anisotropic Gaussian of Eq. 6.1.  The
+ *                            Jacobian is the chain-rule product and
+ *                            D^2 Phi[y, y] is propagated through the chain
+ *                            with the pushed-forward velocity (the Hessian
+ *                            composition formula of Sec. 6.2 contracted
+ *                            with y); flow Eq. 5.8.  Each Phi_i must be a
+ *                            diffeomorphism, which holds iff
+ *                            |a| |(vx/sx, vy/sy, vz/sz)| exp(-1/2) < 1;
+ *                            rt_set_metric requires <= 0.95.
  */
 typedef enum rt_metric_kind {
     RT_METRIC_EUCLID = 0,
     RT_METRIC_GRAPH_GAUSS = 1,
     RT_METRIC_PULLBACK_TWIST = 2,
-    RT_METRIC_PULLBACK_ZTWIST = 3
+    RT_METRIC_PULLBACK_ZTWIST = 3,
+    RT_METRIC_PULLBACK_DEFORM = 4
 } rt_metric_kind;
 
 typedef struct rt_bump {
@@ -99,6 +114,13 @@ typedef struct rt_bump {
     float cx, cy, cz; /* centre */
     float sigma;      /* spread, > 0 */
 } rt_bump;
+
+typedef struct rt_deform {
+    float a;          /* amplitude of f_i */
+    float cx, cy, cz; /* centre */
+    float sx, sy, sz; /* spreads along x, y, z, > 0 */
+    float vx, vy, vz; /* deformation direction v_i (its length scales the displacement) */
+} rt_deform;
 
 typedef struct rt_metric {
     int kind;            /* rt_metric_kind */
@@ -108,7 +130,11 @@ typedef struct rt_metric {
     float twist_amp;     /* PULLBACK_TWIST amplitude (0.4 in the 4K workload), 0 <= amp <= 1 */
     float twist_theta0;  /* PULLBACK_TWIST peak angle (1.2), |theta0| <= 1.5 */
     float cull_sigmas;   /* a bump is ignored where |x - c| > cull_sigmas * sigma;
-                            >= 4, 6 recommended (exp(-18) is below FP32 resolution) */
+                            >= 4, 6 recommended (exp(-18) is below FP32 resolution);
+                            for a deformation, where sum_j ((x_j - c_j) / s_j)^2
+                            > cull_sigmas^2 (there Phi_i is the identity) */
+    int n_deforms;              /* deformations per set, 1..64 (PULLBACK_DEFORM only) */
+    const rt_deform *deforms;   /* host, [n_sets][n_deforms], row-major, Phi_1 first */
 } rt_metric;
 
 /* Copy and validate the metric: finite values, sigma > 0, sizes in range.

@@ -29,6 +29,9 @@ struct rt_ctx {
     int kind = 0, n_sets = 1, n_bumps = 0;
     float amp = 0.f, th0 = 0.f, cull = 6.f;
     std::vector<rt_bump> bumps;
+    // PULLBACK_DEFORM: bound on the Euclidean speed of a g-unit velocity
+    // (may be infinite) and on the displacement |Phi(x) - x|
+    double deform_vmax = 1.0, deform_disp = 0.0;
     // scene (host copy)
     bool has_scene = false;
     std::vector<rt_sphere> sph;
@@ -202,13 +205,129 @@ static rt_status upload(rt_ctx *c, void **dst, size_t *cap, const void *src, siz
     return RT_OK;
 }
 
+// Composition of local deformations (Sec. 6.2).  Device tables, per
+// deformation (Phi_1 first):
+//   float: (cx, cy, cz, a), (1/sx^2, 1/sy^2, 1/sz^2, 0), (vx, vy, vz, cut2),
+//          ((rb - cull_sigmas * max spread) / min spread, |a| |v|, 1 / min spread, 0)
+//   double: cx, cy, cz, a, 1/sx^2, 1/sy^2, 1/sz^2, cut2, vx, vy, vz, 0
+// cut2 = cull_sigmas^2 bounds the spread-scaled squared distance at which
+// Phi_i acts.  rb is the radius of a ball about c in the coordinates of the
+// ray that contains every point p whose image under the deformations applied
+// before Phi_i (Phi_{i+1} ... Phi_k) falls where Phi_i acts: Phi_j moves
+// points by at most |a_j| |v_j|, and only inside its own ball, so each
+// earlier deformation whose ball meets the current one widens it by that
+// much.  Two bounds limit how far a ray moves in a culling window of
+// duration T.  A g-unit velocity has Euclidean speed at most
+// 1 / sigma_min(J), sigma_min(J_j) >= 1 - |a_j| |v_j| exp(-1/2) / min spread,
+// and a point lies only in balls that meet each other, so the product of
+// 1 / (1 - kappa_j) over the balls meeting one ball bounds the speed.  And a
+// geodesic is the preimage of a unit-speed straight line (Sec. 5.2), so it
+// moves at most T + 2 max |Phi(x) - x|, the displacement being at most the
+// sum of |a_j| |v_j| over the balls meeting one ball.
+static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
+    const int nd = m->n_deforms;
+    if (nd < 1 || nd > MAX_BUMPS) return fail(c, RT_EINVAL, "rt_set_metric: n_deforms must be in 1..64");
+    if (!m->deforms) return fail(c, RT_EINVAL, "rt_set_metric: deforms is NULL");
+    if (!finite(m->cull_sigmas) || m->cull_sigmas < 4.0f)
+        return fail(c, RT_EINVAL, "rt_set_metric: cull_sigmas must be finite and >= 4");
+    const size_t n = (size_t)m->n_sets * nd;
+    const double e_half = std::exp(-0.5);
+    for (size_t i = 0; i < n; ++i) {
+        const rt_deform &d = m->deforms[i];
+        const float v[10] = {d.a, d.cx, d.cy, d.cz, d.sx, d.sy, d.sz, d.vx, d.vy, d.vz};
+        for (float x : v)
+            if (!finite(x)) return fail(c, RT_EINVAL, "rt_set_metric: non-finite deformation parameter at " + std::to_string(i));
+        if (!(d.sx > 0.f && d.sy > 0.f && d.sz > 0.f))
+            return fail(c, RT_EINVAL, "rt_set_metric: spreads must be > 0 at deformation " + std::to_string(i));
+        const double q = (double)d.vx * d.vx / ((double)d.sx * d.sx) + (double)d.vy * d.vy / ((double)d.sy * d.sy) +
+                         (double)d.vz * d.vz / ((double)d.sz * d.sz);
+        if (std::fabs((double)d.a) * std::sqrt(q) * e_half > 0.95)
+            return fail(c, RT_EINVAL, "rt_set_metric: deformation " + std::to_string(i) +
+                                          " is not a diffeomorphism with margin (need |a| |v/s| exp(-1/2) <= 0.95)");
+    }
+    const double cut = m->cull_sigmas;
+    std::vector<float> bf(n * 16, 0.f);
+    std::vector<double> bd(n * 12, 0.0);
+    double vmax = 1.0, disp = 0.0;
+    for (int set = 0; set < m->n_sets; ++set) {
+        const rt_deform *D = m->deforms + (size_t)set * nd;
+        std::vector<double> R(nd), delta(nd), rb(nd), kap(nd);
+        for (int i = 0; i < nd; ++i) {
+            const rt_deform &d = D[i];
+            const double smax = std::max(d.sx, std::max(d.sy, d.sz)), smin = std::min(d.sx, std::min(d.sy, d.sz));
+            const double vn = std::sqrt((double)d.vx * d.vx + (double)d.vy * d.vy + (double)d.vz * d.vz);
+            R[i] = cut * smax;
+            delta[i] = std::fabs((double)d.a) * vn;
+            kap[i] = delta[i] * e_half / smin;
+        }
+        auto dist = [&](int i, int j) {
+            const double dx = (double)D[i].cx - D[j].cx, dy = (double)D[i].cy - D[j].cy, dz = (double)D[i].cz - D[j].cz;
+            return std::sqrt(dx * dx + dy * dy + dz * dz);
+        };
+        for (int i = 0; i < nd; ++i) {
+            double r = R[i];
+            for (int j = i + 1; j < nd; ++j)
+                if (dist(i, j) <= r + R[j] + delta[j]) r += delta[j];
+            rb[i] = r;
+        }
+        for (int i = 0; i < nd; ++i) {
+            double P = 1.0, S = 0.0;
+            for (int j = 0; j < nd; ++j)
+                if (dist(i, j) <= rb[i] + rb[j]) {
+                    P = kap[j] < 1.0 ? P / (1.0 - kap[j]) : INFINITY;
+                    S += delta[j];
+                }
+            vmax = std::max(vmax, P);
+            disp = std::max(disp, S);
+        }
+        for (int i = 0; i < nd; ++i) {
+            const rt_deform &d = D[i];
+            const size_t o = ((size_t)set * nd + i);
+            const double s[3] = {1.0 / ((double)d.sx * d.sx), 1.0 / ((double)d.sy * d.sy), 1.0 / ((double)d.sz * d.sz)};
+            const double smin = std::min(d.sx, std::min(d.sy, d.sz));
+            // slack and displacement rounded up so that the float tests stay conservative
+            const float f[16] = {d.cx, d.cy, d.cz, d.a, (float)s[0], (float)s[1], (float)s[2], 0.f,
+                                 d.vx, d.vy, d.vz, (float)(cut * cut),
+                                 (float)((rb[i] - R[i]) / smin * (1.0 + 1e-6)), (float)(delta[i] * (1.0 + 1e-6)),
+                                 (float)(1.0 / smin * (1.0 + 1e-6)), 0.f};
+            const double g[12] = {d.cx, d.cy, d.cz, d.a, s[0], s[1], s[2], cut * cut, d.vx, d.vy, d.vz, 0.0};
+            std::copy(f, f + 16, bf.begin() + o * 16);
+            std::copy(g, g + 12, bd.begin() + o * 12);
+        }
+    }
+    if (!c->host_only) {
+        rt_status st = sync_last(c);
+        if (st != RT_OK) return st;
+        hipSetDevice(c->device);
+        if ((st = upload(c, &c->d_bump_f, &c->bump_f_bytes, bf.data(), bf.size() * sizeof(float))) != RT_OK) return st;
+        if ((st = upload(c, &c->d_bump_d, &c->bump_d_bytes, bd.data(), bd.size() * sizeof(double))) != RT_OK) return st;
+        c->dd.bump_f = (const float4 *)c->d_bump_f;
+        c->dd.bump_d = (const double *)c->d_bump_d;
+    }
+    c->kind = m->kind;
+    c->n_sets = m->n_sets;
+    c->n_bumps = nd;  // parameter records per set
+    c->amp = 0.f;
+    c->th0 = 0.f;
+    c->cull = m->cull_sigmas;
+    c->bumps.clear();
+    c->deform_vmax = vmax;
+    c->deform_disp = disp;
+    c->has_metric = true;
+    c->surr_sb_dirty = true;
+    c->adj_valid = false;
+    c->err.clear();
+    return RT_OK;
+}
+
 rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
     if (!c) return RT_EINVAL;
     if (!m) return fail(c, RT_EINVAL, "rt_set_metric: metric is NULL");
-    if (m->kind < RT_METRIC_EUCLID || m->kind > RT_METRIC_PULLBACK_ZTWIST)
+    if (m->kind < RT_METRIC_EUCLID || m->kind > RT_METRIC_PULLBACK_DEFORM)
         return fail(c, RT_EUNSUPPORTED, "rt_set_metric: unknown metric kind " + std::to_string(m->kind));
     if (m->n_sets < 1 || m->n_sets > MAX_SETS)
         return fail(c, RT_EINVAL, "rt_set_metric: n_sets must be in 1..64");
+    if (m->kind == RT_METRIC_PULLBACK_DEFORM) return set_deform_metric(c, m);
     int nb = m->kind == RT_METRIC_GRAPH_GAUSS ? m->n_bumps : 0;
     if (nb < 0 || nb > MAX_BUMPS) return fail(c, RT_EINVAL, "rt_set_metric: n_bumps must be in 0..64");
     if (nb > 0 && !m->bumps) return fail(c, RT_EINVAL, "rt_set_metric: bumps is NULL");
@@ -584,9 +703,16 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     // (g = I + grad f grad f^T), and for the twist, whose Jacobian has
     // smallest singular value >= 1 (vmax carries a 5% safety factor there).
     // The z-twist has g < I away from its axis and is not culled.
-    float vmax = c->kind == RT_METRIC_PULLBACK_TWIST ? 1.05f : 1.0f;
-    a.cull_margin = c->kind == RT_METRIC_PULLBACK_ZTWIST ? -1.0f
-                                                         : (float)((r->cull_every + 1) * (double)a.h_max * vmax * 1.02 + 1e-4);
+    // A composition of local deformations takes the smaller of its two
+    // bounds (see set_deform_metric).
+    double vmax = c->kind == RT_METRIC_PULLBACK_TWIST ? 1.05 : 1.0;
+    double margin = (r->cull_every + 1) * (double)a.h_max * vmax * 1.02 + 1e-4;
+    if (c->kind == RT_METRIC_PULLBACK_DEFORM)
+        margin = std::min((r->cull_every + 1) * (double)a.h_max * c->deform_vmax * 1.02,
+                          (r->cull_every + 1) * (double)a.h_max * 1.02 + 2.0 * c->deform_disp) + 1e-4;
+    a.cull_margin = c->kind == RT_METRIC_PULLBACK_ZTWIST ? -1.0f : (float)margin;
+    a.cull_base = (float)((r->cull_every + 1) * (double)a.h_max * 1.02 + 1e-4);
+    a.cull_disp = (float)(c->deform_disp * (1.0 + 1e-6));
     a.st = c->d_st;
     a.ids[0] = c->d_ids[0];
     a.ids[1] = c->d_ids[1];

@@ -12,7 +12,7 @@
 
 namespace rtd {
 
-enum { KIND_EUCLID = 0, KIND_GRAPH = 1, KIND_TWIST = 2, KIND_ZTWIST = 3 };
+enum { KIND_EUCLID = 0, KIND_GRAPH = 1, KIND_TWIST = 2, KIND_ZTWIST = 3, KIND_DEFORM = 4 };
 enum { STEP_RK4 = 0, STEP_RK45 = 1, STEP_EULER = 2 };
 
 constexpr int MAX_BUMPS = 64;
@@ -309,6 +309,115 @@ template <class T> __device__ __forceinline__ T ztwist_gdd(V3<T> x, V3<T> d) {
     T j1 = c * d.x - s * d.y + (-s * x.x - c * x.y) * d.z;
     T j2 = s * d.x + c * d.y + (c * x.x - s * x.y) * d.z;
     return j1 * j1 + j2 * j2 + d.z * d.z;
+}
+
+// ---------------------------------------------- composed local deformations
+// Phi = Phi_1 o ... o Phi_k (Sec. 6.2, "Composing diffeomorphisms"),
+// Phi_i(q) = q + f_i(q) v_i (Eq. 6.2), f_i = a exp(-d^T S d / 2) with
+// d = q - c and S = diag(1/sx^2, 1/sy^2, 1/sz^2) (Eq. 6.1).  Walking the
+// chain from Phi_k (applied first) to Phi_1 with the point q, the pushed-
+// forward velocity u = J(Phi_[i+1,k]) y and w = D^2 Phi_[i+1,k][y, y]:
+//   grad f = -f S d,   u^T H(f) u = f ((S d . u)^2 - u^T S u)
+//   w <- w + v (grad f . w + u^T H(f) u)   (= J_i w + D^2 Phi_i[u, u])
+//   u <- u + v (grad f . u),   q <- q + f v,   M <- M + v (grad f^T M)
+// leaves M = J(Phi) (the chain rule product) and w = D^2 Phi[y, y]: the
+// Hessian composition formula of Sec. 6.2 contracted with y on both sides.
+// Then y' = -M^-1 w (Eq. 5.8).  Where the spread-scaled squared distance
+// exceeds cut2, Phi_i is the identity (f = 0), so every lane's result is
+// the same for any superset mask.  Bit i of the mask is Phi_{i+1}.
+// Parameters: float, four float4 per deformation
+// (cx, cy, cz, a), (1/sx^2, 1/sy^2, 1/sz^2, 0), (vx, vy, vz, cut2),
+// (slack / min spread, |a| |v|, 1 / min spread, 0) with slack the largest
+// displacement of a point by the deformations applied before this one where
+// they can bring it into this one's region;
+// double, twelve values (cx, cy, cz, a, 1/sx^2, 1/sy^2, 1/sz^2, cut2, vx, vy, vz, 0).
+template <class T> struct Deform {
+    V3<T> c, s, v;
+    T a, cut2;
+};
+__device__ __forceinline__ Deform<float> deform_at(const float4 *__restrict__ B, int i) {
+    const float4 *q = (const float4 *)((const char *)B + (unsigned)i * 64u);
+    const float4 d0 = q[0], d1 = q[1], d2 = q[2];
+    return {mk(d0.x, d0.y, d0.z), mk(d1.x, d1.y, d1.z), mk(d2.x, d2.y, d2.z), d0.w, d2.w};
+}
+__device__ __forceinline__ Deform<double> deform_at(const double *__restrict__ B, int i) {
+    const double *q = B + 12 * i;
+    return {mk(q[0], q[1], q[2]), mk(q[4], q[5], q[6]), mk(q[8], q[9], q[10]), q[3], q[7]};
+}
+
+// Lower bound on the spread-scaled distance rho from the points where the
+// deformation at P (four float4) is evaluated, for ray points in the box
+// [lo, hi], to its centre: the box distance along each axis scaled by
+// 1/spread (rounded down by 1e-5), less the displacement of the earlier
+// deformations in spread units: the smaller of the static slack and disp.
+__device__ __forceinline__ float deform_box_rho(const float4 *__restrict__ P, const float lo[3], const float hi[3],
+                                                float disp) {
+    const float4 d0 = P[0], d1 = P[1], d3 = P[3];
+    const float ex = fmaxf(fmaxf(lo[0] - d0.x, d0.x - hi[0]), 0.0f);
+    const float ey = fmaxf(fmaxf(lo[1] - d0.y, d0.y - hi[1]), 0.0f);
+    const float ez = fmaxf(fmaxf(lo[2] - d0.z, d0.z - hi[2]), 0.0f);
+    const float sd2 = ex * ex * d1.x + ey * ey * d1.y + ez * ez * d1.z;
+    return fmaxf(sqrt_(sd2) * 0.99999f - fminf(d3.x, disp * d3.z), 0.0f);
+}
+
+// One deformation of the chain; returns f (0 outside the cut).  WAVE: when
+// no active lane of the wave is inside the cut, the whole wave skips the
+// update, which is the identity there.
+template <class T, bool WAVE = false>
+__device__ __forceinline__ T deform_apply(const Deform<T> &D, V3<T> &q, V3<T> &u, V3<T> &w, T M[9]) {
+    const V3<T> d = mk(q.x - D.c.x, q.y - D.c.y, q.z - D.c.z);
+    const V3<T> Sd = mk(D.s.x * d.x, D.s.y * d.y, D.s.z * d.z);
+    const T r2 = dot(d, Sd);
+    if (WAVE && ballot(r2 <= D.cut2) == 0) return T(0);
+    const T f = r2 <= D.cut2 ? D.a * exp2_(T(-0.5) * log2e_<T>() * r2) : T(0);
+    const V3<T> g = (-f) * Sd;
+    const T su = dot(Sd, u);
+    const T uSu = D.s.x * u.x * u.x + D.s.y * u.y * u.y + D.s.z * u.z * u.z;
+    const T cw = dot(g, w) + f * (su * su - uSu);
+    const T cu = dot(g, u);
+    const T m0 = g.x * M[0] + g.y * M[3] + g.z * M[6];
+    const T m1 = g.x * M[1] + g.y * M[4] + g.z * M[7];
+    const T m2 = g.x * M[2] + g.y * M[5] + g.z * M[8];
+    w = axpy(cw, D.v, w);
+    u = axpy(cu, D.v, u);
+    q = axpy(f, D.v, q);
+    M[0] += D.v.x * m0; M[1] += D.v.x * m1; M[2] += D.v.x * m2;
+    M[3] += D.v.y * m0; M[4] += D.v.y * m1; M[5] += D.v.y * m2;
+    M[6] += D.v.z * m0; M[7] += D.v.z * m1; M[8] += D.v.z * m2;
+    return f;
+}
+
+template <class T, bool COUNT = false, class PB>
+__device__ __forceinline__ bool deform_accel(PB B, uint64_t mask, V3<T> p, V3<T> y, V3<T> &acc,
+                                             unsigned *n_in = nullptr) {
+    V3<T> q = p, u = y, w = mk(T(0), T(0), T(0));
+    T M[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
+    unsigned n = 0;
+    while (mask) {
+        const int i = 63 - __builtin_clzll(mask);
+        mask &= ~(1ull << i);
+        const T f = deform_apply<T, sizeof(T) == 4>(deform_at(B, i), q, u, w, M);
+        if (COUNT) n += f != T(0) ? 1u : 0u;
+    }
+    if (COUNT) *n_in += n;
+    // M a = -w by the adjugate
+    const T c0 = M[4] * M[8] - M[5] * M[7], c1 = M[2] * M[7] - M[1] * M[8], c2 = M[1] * M[5] - M[2] * M[4];
+    const T c3 = M[5] * M[6] - M[3] * M[8], c4 = M[0] * M[8] - M[2] * M[6], c5 = M[2] * M[3] - M[0] * M[5];
+    const T c6 = M[3] * M[7] - M[4] * M[6], c7 = M[1] * M[6] - M[0] * M[7], c8 = M[0] * M[4] - M[1] * M[3];
+    const T det = M[0] * c0 + M[1] * c3 + M[2] * c6;
+    if (!(det > T(1e-12))) return false;
+    const T id = -rcp_(det);
+    acc = mk(id * (c0 * w.x + c1 * w.y + c2 * w.z), id * (c3 * w.x + c4 * w.y + c5 * w.z),
+             id * (c6 * w.x + c7 * w.y + c8 * w.z));
+    return true;
+}
+
+// |J d|^2 for the chain of the first n deformations (initial speed normalisation).
+template <class T, class PB> __device__ __forceinline__ T deform_gdd(PB B, int n, V3<T> p, V3<T> d) {
+    V3<T> q = p, u = d, w = mk(T(0), T(0), T(0));
+    T M[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
+    for (int i = n - 1; i >= 0; --i) (void)deform_apply(deform_at(B, i), q, u, w, M);
+    return dot(u, u);
 }
 
 // ------------------------------------------------------------------- scene

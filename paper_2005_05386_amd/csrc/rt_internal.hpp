@@ -82,6 +82,8 @@ struct TraceArgs {
     float h, rtol, atol, h_min, h_max, t_max;
     int max_steps, K, S, bisect_iters;
     float cull_margin;  // < 0: no culling
+    float cull_base;    // composed deformations: window motion without displacement, (K+1) h_max 1.02 + 1e-4
+    float cull_disp;    // composed deformations: bound on |Phi(x) - x| over all x
     int count;          // instrumented variant
     // buffers
     float *st;             // ray state, Q_NFIELDS x cap

@@ -176,6 +176,8 @@ template <int KIND, bool COUNT, bool SREG = false> struct Acc32 {
         } else if constexpr (KIND == KIND_ZTWIST) {
             a = ztwist_accel<float>(p, y);
             return true;
+        } else if constexpr (KIND == KIND_DEFORM) {
+            return deform_accel<float, COUNT>(B, mask, p, y, a, n_bump);
         } else {
             a = mk(0.f, 0.f, 0.f);
             return true;

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
         const int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
         const int pi = tx * 8 + (ln & 7), pj = ty * 8 + (ln >> 3);
         if (pi >= A.width || pj >= A.height) continue;
-        const float4 *__restrict__ Bs = BF + (int64_t)set * A.n_bumps * 2;
+        const float4 *__restrict__ Bs = BF + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
         float su = (2.0f * ((float)pi + 0.5f) / (float)A.width - 1.0f) * A.tan_half * A.aspect;
         float sv = (1.0f - 2.0f * ((float)pj + 0.5f) / (float)A.height) * A.tan_half;
         V3<float> d = mk(su * A.right[0] + sv * A.up[0] + A.fwd[0], su * A.right[1] + sv * A.up[1] + A.fwd[1],
@@ -74,6 +74,8 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
             gdd = twist_gdd<float>(A.twist_amp, A.twist_theta0, e, d);
         } else if constexpr (KIND == KIND_ZTWIST) {
             gdd = ztwist_gdd<float>(e, d);
+        } else if constexpr (KIND == KIND_DEFORM) {
+            gdd = deform_gdd<float>(Bs, A.n_bumps, e, d);
         } else {
             gdd = dot(d, d);
         }
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
             const int pi = tx * 8 + (tl_lane & 7), pj = ty * 8 + (tl_lane >> 3);
             if (pass == 0) valid = pi < A.width && pj < A.height;
             const int pix = pj * A.width + pi;
-            const float4 *__restrict__ Bs = BF + (int64_t)set * n_bumps * 2;
+            const float4 *__restrict__ Bs = BF + (int64_t)set * n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
             const unsigned qbase = (unsigned)set * (unsigned)HW;
 
             V3<float> xh, xl, y;
@@ -227,17 +229,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                             emask = ballot(lane < n_bumps && __float_as_int(A.surr_sb[2 * lane + 1].y) >= 0);
                     } else {
                         const float inf = __builtin_huge_valf();
+                        const float pmn[3] = {wave_min(act ? p.x : inf), wave_min(act ? p.y : inf),
+                                              wave_min(act ? p.z : inf)};
+                        const float pmx[3] = {wave_max(act ? p.x : -inf), wave_max(act ? p.y : -inf),
+                                              wave_max(act ? p.z : -inf)};
+                        float m = A.cull_margin;
+                        float disp = A.cull_disp;  // DEFORM: bound on |Phi(x) - x| in the window
+                        if constexpr (KIND == KIND_DEFORM) {
+                            // A geodesic is the preimage of a unit-speed line, so in the
+                            // window it moves at most T + 2 max |Phi(x) - x|.  Deformation i
+                            // moves a point q by |f_i(q)| |v_i| <= |a_i| |v_i| exp(-rho^2 / 2),
+                            // rho the spread-scaled distance from q to c_i, and q is within
+                            // the chain's displacement of the ray's point.  So a margin and
+                            // a displacement bound that hold give, through the deformations
+                            // near the box, a displacement bound and a margin that hold too;
+                            // two rounds tighten both.
+#pragma unroll
+                            for (int round = 0; round < 2; ++round) {
+                                const float lo0[3] = {pmn[0] - m, pmn[1] - m, pmn[2] - m};
+                                const float hi0[3] = {pmx[0] + m, pmx[1] + m, pmx[2] + m};
+                                float dl = 0.f;
+                                if (lane < n_bumps) {
+                                    const float rho = deform_box_rho(Bs + 4 * lane, lo0, hi0, disp);
+                                    if (rho * rho <= Bs[4 * lane + 2].w * 1.00001f)
+                                        dl = Bs[4 * lane + 3].y * exp2_(-0.5f * 1.44269504f * rho * rho);
+                                }
+#pragma unroll
+                                for (int o = 32; o >= 1; o >>= 1) dl += __shfl_xor(dl, o);
+                                dl = __builtin_bit_cast(float, uniform_i(__builtin_bit_cast(int, dl))) * 1.001f;
+                                disp = fminf(disp, dl);
+                                m = fminf(m, A.cull_base + 2.0f * disp);
+                            }
+                        }
                         float lo[3], hi[3];
-                        lo[0] = wave_min(act ? p.x : inf) - A.cull_margin;
-                        lo[1] = wave_min(act ? p.y : inf) - A.cull_margin;
-                        lo[2] = wave_min(act ? p.z : inf) - A.cull_margin;
-                        hi[0] = wave_max(act ? p.x : -inf) + A.cull_margin;
-                        hi[1] = wave_max(act ? p.y : -inf) + A.cull_margin;
-                        hi[2] = wave_max(act ? p.z : -inf) + A.cull_margin;
+                        lo[0] = pmn[0] - m;
+                        lo[1] = pmn[1] - m;
+                        lo[2] = pmn[2] - m;
+                        hi[0] = pmx[0] + m;
+                        hi[1] = pmx[1] + m;
+                        hi[2] = pmx[2] + m;
                         bool need = false;
                         if (KIND == KIND_GRAPH && lane < n_bumps) {
                             float4 b0 = Bs[2 * lane], b1 = Bs[2 * lane + 1];
                             need = box_dist2(b0.x, b0.y, b0.z, lo, hi) <= b1.z;
+                        } else if (KIND == KIND_DEFORM && lane < n_bumps) {
+                            // the ball (in ray coordinates) where the deformation can act
+                            const float rho = deform_box_rho(Bs + 4 * lane, lo, hi, disp);
+                            need = rho * rho <= Bs[4 * lane + 2].w * 1.00001f;
                         }
                         bmask = ballot(need);
 #pragma unroll
@@ -624,7 +662,7 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
         double tk_lo = r3.w;
         uint64_t mask = (uint64_t)(uint32_t)__float_as_int(r4.x) | ((uint64_t)(uint32_t)__float_as_int(r4.y) << 32);
         int set = oi / HW;
-        const double *Bs = BD + (int64_t)set * A.n_bumps * 8;
+        const double *Bs = BD + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 12 : 8);
         double amp = A.twist_amp, th0 = A.twist_theta0;
         auto acc = [&](V3<double> p, V3<double> v, V3<double> &a) -> bool {
             if constexpr (KIND == KIND_GRAPH) {
@@ -635,6 +673,8 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
             } else if constexpr (KIND == KIND_ZTWIST) {
                 a = ztwist_accel<double>(p, v);
                 return true;
+            } else if constexpr (KIND == KIND_DEFORM) {
+                return deform_accel<double>(Bs, mask, p, v, a);
             } else {
                 a = mk(0.0, 0.0, 0.0);
                 return true;
@@ -858,7 +898,7 @@ template <int KIND, int STEP> int occ() {
 namespace rti {
 
 bool supported(int kind, int step) {
-    return kind >= 0 && kind <= 3 && step >= 0 && step <= 2;
+    return kind >= 0 && kind <= 4 && step >= 0 && step <= 2;
 }
 
 #define RT_DISPATCH(KIND, FN, ...)                                                 \
@@ -873,7 +913,8 @@ int trace_blocks_per_cu(int kind, int step) {
     case KIND_EUCLID: RT_DISPATCH(KIND_EUCLID, occ)
     case KIND_GRAPH: RT_DISPATCH(KIND_GRAPH, occ)
     case KIND_TWIST: RT_DISPATCH(KIND_TWIST, occ)
-    default: RT_DISPATCH(KIND_ZTWIST, occ)
+    case KIND_ZTWIST: RT_DISPATCH(KIND_ZTWIST, occ)
+    default: RT_DISPATCH(KIND_DEFORM, occ)
     }
 }
 
@@ -892,7 +933,8 @@ hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, i
     case KIND_EUCLID: RT_DISPATCH(KIND_EUCLID, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_GRAPH: RT_DISPATCH(KIND_GRAPH, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_TWIST: RT_DISPATCH(KIND_TWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
-    default: RT_DISPATCH(KIND_ZTWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    case KIND_ZTWIST: RT_DISPATCH(KIND_ZTWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    default: RT_DISPATCH(KIND_DEFORM, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     }
 }
 

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED, RT_ESTATE = 0, -1, -2, -3, -4, -5
-EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST = 0, 1, 2, 3
+EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST, PULLBACK_DEFORM = 0, 1, 2, 3, 4
 RK4, RK45, EULER = 0, 1, 2
 FLAG_TIMING, FLAG_COUNT_WORK, FLAG_SURROGATE = 1, 2, 4
 
@@ -45,7 +45,8 @@ class rt_bump(C.Structure):
 
 class rt_metric(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_sets", C.c_int), ("n_bumps", C.c_int), ("bumps", C.c_void_p),
-                ("twist_amp", C.c_float), ("twist_theta0", C.c_float), ("cull_sigmas", C.c_float)]
+                ("twist_amp", C.c_float), ("twist_theta0", C.c_float), ("cull_sigmas", C.c_float),
+                ("n_deforms", C.c_int), ("deforms", C.c_void_p)]
 
 
 class rt_scene(C.Structure):
@@ -180,13 +181,18 @@ class Tracer:
             raise RtError(st, _lib.rt_last_error(self._h).decode())
 
     def set_metric(self, metric):
-        b = np.ascontiguousarray(np.asarray(metric["bumps"], np.float32))
+        b = np.ascontiguousarray(np.asarray(metric.get("bumps", np.zeros((1, 0, 5))), np.float32))
         if b.ndim == 2:
             b = b[None]
         n_sets, n_bumps = b.shape[0], b.shape[1]
+        d = metric.get("deforms")
+        d = np.zeros((1, 0, 10), np.float32) if d is None else np.asarray(d, np.float32)
+        d = np.ascontiguousarray(d[None] if d.ndim == 2 else d)
+        if int(metric["kind"]) == PULLBACK_DEFORM:
+            n_sets = d.shape[0]
         m = rt_metric(int(metric["kind"]), int(n_sets), int(n_bumps), b.ctypes.data if b.size else None,
                       float(metric.get("twist_amp", 0.4)), float(metric.get("twist_theta0", 1.2)),
-                      float(metric.get("cull_sigmas", 6.0)))
+                      float(metric.get("cull_sigmas", 6.0)), int(d.shape[1]), d.ctypes.data if d.size else None)
         self._check(_lib.rt_set_metric(self._h, C.byref(m)))
         self.n_sets = n_sets
 

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(rt.lib(), n), n
     assert sorted(rt.EXPORTS) == names
-    assert rt.abi_version() == 2
+    assert rt.abi_version() == 3
 
 
 def test_host_only_context_validates():
@@ -107,6 +107,23 @@ def test_metric_and_scene_validation():
     with pytest.raises(rt.RtError) as e:
         tr.set_scene(W.scene(spheres=sp))
     assert e.value.status == rt.RT_EINVAL
+    # composed local deformations: accepted as generated, rejected when a
+    # deformation is not a diffeomorphism with margin, has a zero spread or
+    # a non-finite value, or the count is out of range
+    d = W.random_deforms(5, 0)
+    tr.set_metric(W.metric(W.PULLBACK_DEFORM, deforms=d))
+    for mod in [lambda x: x.__setitem__((0, 0), 50.0 * x[0, 0]),
+                lambda x: x.__setitem__((1, 5), 0.0),
+                lambda x: x.__setitem__((2, 8), np.nan)]:
+        dd = d.copy()
+        mod(dd)
+        with pytest.raises(rt.RtError) as e:
+            tr.set_metric(W.metric(W.PULLBACK_DEFORM, deforms=dd))
+        assert e.value.status == rt.RT_EINVAL
+    for n in (0, 65):
+        with pytest.raises(rt.RtError) as e:
+            tr.set_metric(W.metric(W.PULLBACK_DEFORM, deforms=W.random_deforms(n, 0).reshape(n, 10)))
+        assert e.value.status == rt.RT_EINVAL
     # trace before a scene is set
     tr2 = rt.Tracer(-1)
     tr2.set_metric(W.metric(W.GRAPH_GAUSS, b))

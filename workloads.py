@@ -47,6 +47,7 @@ EUCLID = 0
 GRAPH_GAUSS = 1
 PULLBACK_TWIST = 2
 PULLBACK_ZTWIST = 3
+PULLBACK_DEFORM = 4
 
 # Step rules.
 RK4 = 0
@@ -142,16 +143,40 @@ def rule(kind=RK4, h=0.01, max_steps=1000, t_max=None, rtol=1e-6, atol=1e-6,
                 pass_steps=int(pass_steps), bisect_iters=int(bisect_iters))
 
 
-def metric(kind, bumps=None, twist_amp=0.4, twist_theta0=1.2, cull_sigmas=6.0):
+def metric(kind, bumps=None, twist_amp=0.4, twist_theta0=1.2, cull_sigmas=6.0, deforms=None):
     if bumps is None:
         bumps = np.zeros((1, 0, 5), np.float32)
     bumps = f32(bumps)
     if bumps.ndim == 2:
         bumps = bumps[None]
-    return dict(kind=int(kind), bumps=bumps,
-                twist_amp=float(np.float32(twist_amp)),
-                twist_theta0=float(np.float32(twist_theta0)),
-                cull_sigmas=float(np.float32(cull_sigmas)))
+    m = dict(kind=int(kind), bumps=bumps,
+             twist_amp=float(np.float32(twist_amp)),
+             twist_theta0=float(np.float32(twist_theta0)),
+             cull_sigmas=float(np.float32(cull_sigmas)))
+    if deforms is not None:
+        d = f32(deforms)
+        m["deforms"] = d[None] if d.ndim == 2 else d
+    return m
+
+
+def random_deforms(n, seed, box=3.0, amp=(0.4, 1.0), spread=(0.15, 0.35), kappa=(0.1, 0.4)):
+    """Local deformations Phi_i(p) = p + f_i(p) v_i with anisotropic
+    Gaussians f_i: rows (a, cx, cy, cz, sx, sy, sz, vx, vy, vz).  Draw
+    order: centres U[-box, box]^3 (n, 3); spreads U(spread)^3 (n, 3);
+    |a| U(amp) (n); sign of a (n); direction on the unit sphere (n, 3,
+    normalised normals); kappa U(kappa) (n).  |v| is set so that
+    |a| |v/s| exp(-1/2) = kappa: each Phi_i is a diffeomorphism with margin
+    1 - kappa."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-box, box, size=(n, 3))
+    s = rng.uniform(spread[0], spread[1], size=(n, 3))
+    a = rng.uniform(amp[0], amp[1], size=n) * np.where(rng.uniform(size=n) < 0.5, -1.0, 1.0)
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    k = rng.uniform(kappa[0], kappa[1], size=n)
+    vn = k / (np.abs(a) * np.linalg.norm(u / s, axis=1) * np.exp(-0.5))
+    v = u * vn[:, None]
+    return f32(np.concatenate([a[:, None], c, s, v], axis=1))
 
 
 def scene(spheres=None, planes=None, tori=None):
@@ -194,6 +219,16 @@ def twist_4k(width=3840, height=2160):
                 metric=metric(PULLBACK_TWIST, twist_amp=0.4, twist_theta0=1.2),
                 scene=scene(spheres=random_spheres(256, seed=1)),
                 rule=rule(RK4, h=0.005, max_steps=4000, t_max=20.0))
+
+
+def deform16_1080p(width=1920, height=1080):
+    """The composition Phi_1 o ... o Phi_16 of local deformations (Sec. 6.2)
+    in the bumps16 scene, RK4 as the headline workload."""
+    base = bumps16_1080p(width, height)
+    return dict(name="deform16_1080p", camera=base["camera"],
+                metric=metric(PULLBACK_DEFORM, deforms=random_deforms(16, seed=5)),
+                scene=base["scene"],
+                rule=rule(RK4, h=0.005, max_steps=4000, t_max=20.0, pass_steps=4000))
 
 
 def adjoint_sets(n_sets=64, n_bumps=8):
@@ -248,6 +283,7 @@ WORKLOADS = {
     "bumps16_1080p_euler": lambda **kw: bumps16_1080p(kind=EULER, **kw),
     "euler_vs_rk4_1080p": lambda **kw: bumps16_1080p(kind=EULER, **kw),
     "twist_4k": twist_4k,
+    "deform16_1080p": deform16_1080p,
     "adjoint_64x512": adjoint_64x512,
     "surrogate_64_4k": surrogate_64_4k,
     "surrogate_isolated_4k": surrogate_isolated_4k,
