@@ -12,8 +12,8 @@ Pinning status (what fixes each function to something other than itself):
   camera + chord test + bisection   flat-space analytic hits (sphere, plane,
                                     torus quartic)          -- pinned
   graph acceleration (Eq. 5.4)      generic Christoffel symbols (Eq. 3.4)
-                                    from finite differences of g; det g
-                                    = 1 + |grad f|^2; f -> -f invariance;
+  (isotropic and anisotropic        from finite differences of g; det g
+  bumps, the Sec. 5.1 quadratic)    = 1 + |grad f|^2; f -> -f invariance;
                                     single-bump quadrature   -- pinned
   pullback acceleration (Eq. 5.8)   generic Christoffel symbols; geodesics are
                                     preimages of straight lines
@@ -40,7 +40,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rt_oracle.c")
 _LIB = os.path.join(_HERE, "_rt_oracle.so")
 
-EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST, PULLBACK_DEFORM = 0, 1, 2, 3, 4
+EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST, PULLBACK_DEFORM, GRAPH_ANISO, GRAPH_QUADRIC = 0, 1, 2, 3, 4, 5, 6
 RK4, RK45, EULER = 0, 1, 2
 
 
@@ -58,7 +58,8 @@ def build(force=True):
 class _Metric(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_bumps", C.c_int), ("bumps", C.POINTER(C.c_double)),
                 ("twist_amp", C.c_double), ("twist_theta0", C.c_double),
-                ("n_deforms", C.c_int), ("deforms", C.POINTER(C.c_double))]
+                ("n_deforms", C.c_int), ("deforms", C.POINTER(C.c_double)),
+                ("n_abumps", C.c_int), ("abumps", C.POINTER(C.c_double)), ("quadric", C.c_double * 3)]
 
 
 class _Scene(C.Structure):
@@ -129,9 +130,16 @@ class Oracle:
         if dfm.ndim == 3:
             dfm = dfm[set_index]
         self._deforms = np.ascontiguousarray(dfm.astype(np.float64).reshape(-1, 10))
+        ab = metric.get("abumps")
+        ab = np.zeros((0, 7)) if ab is None else np.asarray(ab, np.float32)
+        if ab.ndim == 3:
+            ab = ab[set_index]
+        self._abumps = np.ascontiguousarray(ab.astype(np.float64).reshape(-1, 7))
+        q = [float(np.float32(x)) for x in metric.get("quadric", (0.0, 0.0, 0.0))]
         self.m = _Metric(int(metric["kind"]), int(self._bumps.shape[0]), _dptr(self._bumps),
                          float(metric.get("twist_amp", 0.4)), float(metric.get("twist_theta0", 1.2)),
-                         int(self._deforms.shape[0]), _dptr(self._deforms))
+                         int(self._deforms.shape[0]), _dptr(self._deforms),
+                         int(self._abumps.shape[0]), _dptr(self._abumps), (C.c_double * 3)(*q))
         self._sp = np.ascontiguousarray(np.asarray(scene["spheres"], np.float32).astype(np.float64).reshape(-1, 4))
         self._pl = np.ascontiguousarray(np.asarray(scene["planes"], np.float32).astype(np.float64).reshape(-1, 4))
         self._to = np.ascontiguousarray(np.asarray(scene["tori"], np.float32).astype(np.float64).reshape(-1, 8))

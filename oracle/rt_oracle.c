@@ -76,6 +76,32 @@ static void graph_derivs(const orc_metric *m, const double x[3], double grad[3],
 {
     memset(grad, 0, 3 * sizeof(double));
     memset(hess, 0, 9 * sizeof(double));
+    if (m->kind == ORC_GRAPH_QUADRIC) {
+        /* f = sum_i q_i x_i^2: f_i = 2 q_i x_i, f_ij = 2 q_i delta_ij (Sec. 5.1 example) */
+        for (int i = 0; i < 3; i++) {
+            grad[i] = 2.0 * m->quadric[i] * x[i];
+            hess[3 * i + i] = 2.0 * m->quadric[i];
+        }
+        return;
+    }
+    if (m->kind == ORC_GRAPH_ANISO) {
+        /* f = sum_b a_b exp(-sum_i (x_i - c_i)^2 / (2 s_i^2)) (Eq. 6.1, three spreads):
+         * f_i = -(d_i / s_i^2) f_b, f_ij = (d_i d_j / (s_i^2 s_j^2) - delta_ij / s_i^2) f_b */
+        for (int b = 0; b < m->n_abumps; b++) {
+            const double *p = m->abumps + 7 * b;
+            double d[3] = {x[0] - p[1], x[1] - p[2], x[2] - p[3]};
+            double s2[3] = {p[4] * p[4], p[5] * p[5], p[6] * p[6]};
+            double e = 0.0;
+            for (int i = 0; i < 3; i++) e += d[i] * d[i] / s2[i];
+            double fb = p[0] * exp(-0.5 * e);
+            for (int i = 0; i < 3; i++) {
+                grad[i] += -d[i] / s2[i] * fb;
+                for (int j = 0; j < 3; j++)
+                    hess[3 * i + j] += (d[i] * d[j] / (s2[i] * s2[j]) - (i == j ? 1.0 / s2[i] : 0.0)) * fb;
+            }
+        }
+        return;
+    }
     for (int b = 0; b < m->n_bumps; b++) {
         const double *p = m->bumps + 5 * b;
         double a = p[0], sg = p[4];
@@ -255,6 +281,8 @@ int orc_accel(const orc_metric *m, const double x[3], const double y[3], double 
         a[0] = a[1] = a[2] = 0.0;
         return 1;
     case ORC_GRAPH_GAUSS:
+    case ORC_GRAPH_ANISO:
+    case ORC_GRAPH_QUADRIC:
         graph_accel(m, x, y, a);
         return 1;
     case ORC_PULLBACK_TWIST:
@@ -269,7 +297,7 @@ int orc_accel(const orc_metric *m, const double x[3], const double y[3], double 
  * pullbacks (g_ij = sum_k d_i x_k d_j x_k). */
 void orc_metric_tensor(const orc_metric *m, const double x[3], double g[9])
 {
-    if (m->kind == ORC_GRAPH_GAUSS) {
+    if (m->kind == ORC_GRAPH_GAUSS || m->kind == ORC_GRAPH_ANISO || m->kind == ORC_GRAPH_QUADRIC) {
         double gr[3], H[9];
         graph_derivs(m, x, gr, H);
         for (int i = 0; i < 3; i++)

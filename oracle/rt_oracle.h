@@ -17,6 +17,8 @@
 #define ORC_PULLBACK_TWIST 2
 #define ORC_PULLBACK_ZTWIST 3
 #define ORC_PULLBACK_DEFORM 4
+#define ORC_GRAPH_ANISO 5
+#define ORC_GRAPH_QUADRIC 6
 
 #define ORC_RK4 0
 #define ORC_RK45 1
@@ -29,6 +31,9 @@ typedef struct {
     double twist_amp, twist_theta0;
     int n_deforms;
     const double *deforms; /* [n_deforms][10] a, cx, cy, cz, sx, sy, sz, vx, vy, vz */
+    int n_abumps;
+    const double *abumps;  /* [n_abumps][7] a, cx, cy, cz, sx, sy, sz */
+    double quadric[3];     /* f = q0 x^2 + q1 y^2 + q2 z^2 */
 } orc_metric;
 
 typedef struct {

@@ -111,6 +111,19 @@ def gauss_f(bumps, x):
     return f
 
 
+def gauss_aniso_f(abumps, x):
+    """f = sum a exp(-sum_i (x_i - c_i)^2 / (2 s_i^2)) (Eq. 6.1), complex-safe."""
+    f = 0.0
+    for a, cx, cy, cz, sx, sy, sz in np.asarray(abumps, np.float64).reshape(-1, 7):
+        f = f + a * np.exp(-0.5 * (((x[0] - cx) / sx) ** 2 + ((x[1] - cy) / sy) ** 2 + ((x[2] - cz) / sz) ** 2))
+    return f
+
+
+def quadric_f(q, x):
+    """f = q0 x^2 + q1 y^2 + q2 z^2 (the example of Sec. 5.1 is (1, 1, -1))."""
+    return q[0] * x[0] ** 2 + q[1] * x[1] ** 2 + q[2] * x[2] ** 2
+
+
 def twist_phi(x, amp=float(np.float32(0.4)), th0=float(np.float32(1.2))):
     """phi(x) = x + amp tanh|x| R_z(th0 exp(-|x|^2)) x (complex-safe)."""
     r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2]
@@ -164,9 +177,9 @@ def cs_jac(fun, x, h=1e-30):
     return J
 
 
-def graph_g(bumps, x):
-    """Eq. 5.2: g = I + grad f grad f^T."""
-    gr = cs_grad(lambda z: gauss_f(bumps, z), x)
+def graph_g(bumps, x, f=None):
+    """Eq. 5.2: g = I + grad f grad f^T (f: the isotropic bump sum unless given)."""
+    gr = cs_grad(f if f is not None else (lambda z: gauss_f(bumps, z)), x)
     return np.eye(3) + np.outer(gr, gr)
 
 

@@ -94,6 +94,67 @@ def test_graph_accel_matches_generic_christoffel(name):
     assert worst < 2e-7, worst
 
 
+def _graph2(kind):
+    """Metric, scalar function f and sample points for the anisotropic and
+    quadric graph kinds."""
+    if kind == W.GRAPH_ANISO:
+        ab = W.random_abumps(16, seed=0)
+        x = ab[np.arange(40) % 16, 1:4].astype(np.float64) + 0.3 * np.random.default_rng(6).normal(size=(40, 3))
+        return W.metric(kind, abumps=ab), (lambda z: exact.gauss_aniso_f(ab, z)), x
+    q = (1.0, 1.0, -1.0)
+    return W.metric(kind, quadric=q), (lambda z: exact.quadric_f(q, z)), _rand_points(40, 8, box=1.5)[0]
+
+
+@pytest.mark.parametrize("kind", [W.GRAPH_ANISO, W.GRAPH_QUADRIC])
+def test_graph2_accel_matches_generic_christoffel(kind):
+    """Eq. 5.4 for anisotropic Gaussian sums and the quadratic of Sec. 5.1
+    equals the generic symbols of g = I + grad f grad f^T, with grad f by
+    complex step from an independent f; det g = 1 + |grad f|^2."""
+    m, f, x = _graph2(kind)
+    orc = oracle.Oracle(m, W.scene())
+    y = np.random.default_rng(9).normal(size=(len(x), 3))
+    worst = 0.0
+    for q in range(len(x)):
+        a, ok = orc.accel(x[q], y[q])
+        assert ok
+        ref = exact.generic_accel(lambda z: exact.graph_g(None, z, f), x[q], y[q])
+        worst = max(worst, np.abs(a - ref).max() / max(1e-3, np.abs(ref).max()))
+        g = orc.metric_tensor(x[q])
+        gr = exact.cs_grad(f, x[q])
+        assert abs(np.linalg.det(g) - (1.0 + gr @ gr)) < 1e-10 * (1.0 + gr @ gr)
+    assert worst < 2e-7, worst
+
+
+def test_aniso_with_equal_spreads_is_isotropic():
+    """Three equal spreads reduce Eq. 6.1 to the isotropic bump: the two
+    oracle kinds agree to rounding."""
+    b = W.random_bumps(8, seed=2).astype(np.float64)
+    ab = np.concatenate([b[:, :4], np.repeat(b[:, 4:5], 3, axis=1)], axis=1)
+    o1 = oracle.Oracle(W.metric(W.GRAPH_GAUSS, b), W.scene())
+    o2 = oracle.Oracle(W.metric(W.GRAPH_ANISO, abumps=ab), W.scene())
+    x, y = _rand_points(30, 10, box=1.5)
+    for q in range(len(x)):
+        a1, _ = o1.accel(x[q], y[q])
+        a2, _ = o2.accel(x[q], y[q])
+        assert np.allclose(a1, a2, rtol=1e-12, atol=1e-15)
+
+
+def test_graph2_sign_invariance_is_bitwise():
+    """f -> -f leaves g, hence every traced ray, unchanged bit for bit."""
+    for kind in (W.GRAPH_ANISO, W.GRAPH_QUADRIC):
+        wl = W.with_size(W.get("abumps16_1080p" if kind == W.GRAPH_ANISO else "quadric_1080p"), 24, 14)
+        m2 = dict(wl["metric"])
+        if kind == W.GRAPH_ANISO:
+            m2["abumps"] = wl["metric"]["abumps"].copy()
+            m2["abumps"][..., 0] *= -1
+        else:
+            m2["quadric"] = [-q for q in wl["metric"]["quadric"]]
+        r1 = oracle.Oracle(wl["metric"], wl["scene"]).trace(wl["camera"], wl["rule"])
+        r2 = oracle.Oracle(m2, wl["scene"]).trace(wl["camera"], wl["rule"])
+        for k in ("hit", "t", "dir", "id", "steps"):
+            assert np.array_equal(r1[k], r2[k]), (kind, k)
+
+
 def test_graph_det_g_volume_element():
     """det g = 1 + |grad f|^2 (Sec. 5.1)."""
     wl = W.get("bumps16_1080p")

@@ -48,6 +48,8 @@ GRAPH_GAUSS = 1
 PULLBACK_TWIST = 2
 PULLBACK_ZTWIST = 3
 PULLBACK_DEFORM = 4
+GRAPH_ANISO = 5
+GRAPH_QUADRIC = 6
 
 # Step rules.
 RK4 = 0
@@ -143,7 +145,8 @@ def rule(kind=RK4, h=0.01, max_steps=1000, t_max=None, rtol=1e-6, atol=1e-6,
                 pass_steps=int(pass_steps), bisect_iters=int(bisect_iters))
 
 
-def metric(kind, bumps=None, twist_amp=0.4, twist_theta0=1.2, cull_sigmas=6.0, deforms=None):
+def metric(kind, bumps=None, twist_amp=0.4, twist_theta0=1.2, cull_sigmas=6.0, deforms=None, abumps=None,
+           quadric=None):
     if bumps is None:
         bumps = np.zeros((1, 0, 5), np.float32)
     bumps = f32(bumps)
@@ -156,7 +159,23 @@ def metric(kind, bumps=None, twist_amp=0.4, twist_theta0=1.2, cull_sigmas=6.0, d
     if deforms is not None:
         d = f32(deforms)
         m["deforms"] = d[None] if d.ndim == 2 else d
+    if abumps is not None:
+        d = f32(abumps)
+        m["abumps"] = d[None] if d.ndim == 2 else d
+    if quadric is not None:
+        m["quadric"] = [float(np.float32(q)) for q in quadric]
     return m
+
+
+def random_abumps(n, seed, box=2.0, amp=0.6, spread=(0.15, 0.5)):
+    """Anisotropic bumps (Eq. 6.1 with three spreads): rows (a, cx, cy, cz,
+    sx, sy, sz).  Draw order: centres U[-box, box]^3 (n, 3), amplitudes
+    U(-amp, amp) (n), spreads U(spread) (n, 3)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-box, box, size=(n, 3))
+    a = rng.uniform(-amp, amp, size=n)
+    s = rng.uniform(spread[0], spread[1], size=(n, 3))
+    return f32(np.concatenate([a[:, None], c, s], axis=1))
 
 
 def random_deforms(n, seed, box=3.0, amp=(0.4, 1.0), spread=(0.15, 0.35), kappa=(0.1, 0.4)):
@@ -231,6 +250,23 @@ def deform16_1080p(width=1920, height=1080):
                 rule=rule(RK4, h=0.005, max_steps=4000, t_max=20.0, pass_steps=4000))
 
 
+def abumps16_1080p(width=1920, height=1080):
+    """The headline frame with anisotropic bumps (three spreads each)."""
+    base = bumps16_1080p(width, height)
+    return dict(name="abumps16_1080p", camera=base["camera"],
+                metric=metric(GRAPH_ANISO, abumps=random_abumps(16, seed=0)),
+                scene=base["scene"], rule=base["rule"])
+
+
+def quadric_1080p(width=1920, height=1080):
+    """The graph of the paper's quadratic f = x^2 + y^2 - z^2 (Sec. 5.1),
+    camera inside the scene box looking +x (the paper's left view)."""
+    base = bumps16_1080p(width, height)
+    return dict(name="quadric_1080p", camera=camera(width, height, eye=(-1.0, 0.1, 0.2), forward=(1.0, 0.0, 0.0)),
+                metric=metric(GRAPH_QUADRIC, quadric=(1.0, 1.0, -1.0)),
+                scene=base["scene"], rule=base["rule"])
+
+
 def adjoint_sets(n_sets=64, n_bumps=8):
     """Per set b: bumps from the bumps16 distributions with seed 2+b; the
     target set perturbs them with seed 1000+b: a + N(0,0.05), c + N(0,0.1),
@@ -284,6 +320,8 @@ WORKLOADS = {
     "euler_vs_rk4_1080p": lambda **kw: bumps16_1080p(kind=EULER, **kw),
     "twist_4k": twist_4k,
     "deform16_1080p": deform16_1080p,
+    "abumps16_1080p": abumps16_1080p,
+    "quadric_1080p": quadric_1080p,
     "adjoint_64x512": adjoint_64x512,
     "surrogate_64_4k": surrogate_64_4k,
     "surrogate_isolated_4k": surrogate_isolated_4k,
