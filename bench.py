@@ -41,6 +41,12 @@ FLOPS = {
     # updates of w, u, q 18, M 18
     "deform_eval": 51,
     "deform_term": 95,
+    # anisotropic bumps: per evaluation 1 + |grad f|^2 6, reciprocal 1, scale 4; per bump
+    # inside its cut: d, S d, d.S d 11, exponent 2, w 1, grad f 6, S d . y 5, y.S y 8, q 4
+    "ganiso_eval": 11,
+    "ganiso_bump": 37,
+    # quadratic: grad f 6, y^T H y 9, 1 + |grad f|^2 6, reciprocal and scale 5
+    "gquad_eval": 26,
     # RK4: step 74 (3 stage states 36, stage sums 30, h/2 and h/6 scaling 8), x_hi + x_lo 3,
     # chord length 5, two-float position update 21 (7 per coordinate), velocity update 3
     "rk4_step": 106,
@@ -112,6 +118,10 @@ def algorithmic_flops(kind, step, st):
         f = FLOPS["ztwist_eval"] * ev
     elif kind == 4:
         f = FLOPS["deform_eval"] * ev + FLOPS["deform_term"] * st["bump_evals"]
+    elif kind == 5:
+        f = FLOPS["ganiso_eval"] * ev + FLOPS["ganiso_bump"] * st["bump_evals"]
+    elif kind == 6:
+        f = FLOPS["gquad_eval"] * ev
     else:
         f = 0
     if step == 0:
@@ -486,6 +496,7 @@ def main():
                    "n_sets": tr.n_sets, "step_rule": ["RK4", "RK45", "Euler"][rule["kind"]], "h": rule["h"],
                    "max_steps": ms_steps, "bumps": int(wl["metric"]["bumps"].shape[1]),
                    "deforms": int(wl["metric"]["deforms"].shape[1]) if "deforms" in wl["metric"] else 0,
+                   "anisotropic_bumps": int(wl["metric"]["abumps"].shape[1]) if "abumps" in wl["metric"] else 0,
                    "spheres": int(len(wl["scene"]["spheres"]))},
         "ray_steps_per_s": work["ray_steps"] / (ms / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

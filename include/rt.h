@@ -86,6 +86,13 @@ const char *rt_last_error(const rt_ctx *ctx);
  * RT_METRIC_PULLBACK_ZTWIST  pull-back of the z-twist of Sec. 5.2,
  *                            Phi(x,y,z) = (cos z x - sin z y,
  *                                          sin z x + cos z y, z).
+ * RT_METRIC_GRAPH_ANISO      as RT_METRIC_GRAPH_GAUSS, with the Gaussians of
+ *                            Eq. 6.1 in full: three spreads per bump,
+ *                            a exp(-sum_j (x_j - c_j)^2 / (2 s_j^2)).
+ * RT_METRIC_GRAPH_QUADRIC    the graph metric of the quadratic
+ *                            f = qx x^2 + qy y^2 + qz z^2; the paper's
+ *                            example of Sec. 5.1 is (qx, qy, qz) = (1, 1, -1).
+ *                            One parameter set.
  * RT_METRIC_PULLBACK_DEFORM  pull-back g = J^T J (Eq. 5.6) of a composition
  *                            Phi = Phi_1 o Phi_2 o ... o Phi_k of local
  *                            deformations (Sec. 6.2, "Composing
@@ -106,7 +113,9 @@ typedef enum rt_metric_kind {
     RT_METRIC_GRAPH_GAUSS = 1,
     RT_METRIC_PULLBACK_TWIST = 2,
     RT_METRIC_PULLBACK_ZTWIST = 3,
-    RT_METRIC_PULLBACK_DEFORM = 4
+    RT_METRIC_PULLBACK_DEFORM = 4,
+    RT_METRIC_GRAPH_ANISO = 5,
+    RT_METRIC_GRAPH_QUADRIC = 6
 } rt_metric_kind;
 
 typedef struct rt_bump {
@@ -122,6 +131,12 @@ typedef struct rt_deform {
     float vx, vy, vz; /* deformation direction v_i (its length scales the displacement) */
 } rt_deform;
 
+typedef struct rt_abump {
+    float a;          /* amplitude */
+    float cx, cy, cz; /* centre */
+    float sx, sy, sz; /* spreads along x, y, z, > 0 */
+} rt_abump;
+
 typedef struct rt_metric {
     int kind;            /* rt_metric_kind */
     int n_sets;          /* independent parameter sets traced side by side, 1..64 */
@@ -131,10 +146,14 @@ typedef struct rt_metric {
     float twist_theta0;  /* PULLBACK_TWIST peak angle (1.2), |theta0| <= 1.5 */
     float cull_sigmas;   /* a bump is ignored where |x - c| > cull_sigmas * sigma;
                             >= 4, 6 recommended (exp(-18) is below FP32 resolution);
-                            for a deformation, where sum_j ((x_j - c_j) / s_j)^2
-                            > cull_sigmas^2 (there Phi_i is the identity) */
+                            for a deformation or an anisotropic bump, where
+                            sum_j ((x_j - c_j) / s_j)^2 > cull_sigmas^2 (there
+                            Phi_i is the identity and the bump is zero) */
     int n_deforms;              /* deformations per set, 1..64 (PULLBACK_DEFORM only) */
     const rt_deform *deforms;   /* host, [n_sets][n_deforms], row-major, Phi_1 first */
+    int n_abumps;               /* anisotropic bumps per set, 0..64 (GRAPH_ANISO only) */
+    const rt_abump *abumps;     /* host, [n_sets][n_abumps], row-major */
+    float quadric[3];           /* GRAPH_QUADRIC coefficients (qx, qy, qz), |q| <= 100 */
 } rt_metric;
 
 /* Copy and validate the metric: finite values, sigma > 0, sizes in range.

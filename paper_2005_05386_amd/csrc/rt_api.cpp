@@ -320,14 +320,81 @@ static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
     return RT_OK;
 }
 
+// Graph metrics of anisotropic Gaussian sums and of the quadratic.  Device
+// tables: anisotropic bumps as (cx, cy, cz, a), (1/sx^2, 1/sy^2, 1/sz^2,
+// cull_sigmas^2) in float and the same eight values in double; the
+// quadratic as (qx, qy, qz, 0) in both.
+static rt_status set_graph2_metric(rt_ctx *c, const rt_metric *m) {
+    if (!finite(m->cull_sigmas) || m->cull_sigmas < 4.0f)
+        return fail(c, RT_EINVAL, "rt_set_metric: cull_sigmas must be finite and >= 4");
+    std::vector<float> bf;
+    std::vector<double> bd;
+    int nb = 0;
+    if (m->kind == RT_METRIC_GRAPH_ANISO) {
+        nb = m->n_abumps;
+        if (nb < 0 || nb > MAX_BUMPS) return fail(c, RT_EINVAL, "rt_set_metric: n_abumps must be in 0..64");
+        if (nb > 0 && !m->abumps) return fail(c, RT_EINVAL, "rt_set_metric: abumps is NULL");
+        const size_t n = (size_t)m->n_sets * nb;
+        for (size_t i = 0; i < n; ++i) {
+            const rt_abump &b = m->abumps[i];
+            const float v[7] = {b.a, b.cx, b.cy, b.cz, b.sx, b.sy, b.sz};
+            for (float x : v)
+                if (!finite(x)) return fail(c, RT_EINVAL, "rt_set_metric: non-finite bump parameter at " + std::to_string(i));
+            if (!(b.sx > 0.f && b.sy > 0.f && b.sz > 0.f))
+                return fail(c, RT_EINVAL, "rt_set_metric: spreads must be > 0 at bump " + std::to_string(i));
+        }
+        const double cut2 = (double)m->cull_sigmas * m->cull_sigmas;
+        bf.assign(std::max<size_t>(n, 1) * 8, 0.f);
+        bd.assign(std::max<size_t>(n, 1) * 8, 0.0);
+        for (size_t i = 0; i < n; ++i) {
+            const rt_abump &b = m->abumps[i];
+            const double s[3] = {1.0 / ((double)b.sx * b.sx), 1.0 / ((double)b.sy * b.sy), 1.0 / ((double)b.sz * b.sz)};
+            const double g[8] = {b.cx, b.cy, b.cz, b.a, s[0], s[1], s[2], cut2};
+            for (int k = 0; k < 8; ++k) {
+                bf[8 * i + k] = (float)g[k];
+                bd[8 * i + k] = g[k];
+            }
+        }
+    } else {
+        if (m->n_sets != 1) return fail(c, RT_EINVAL, "rt_set_metric: the quadric metric takes one parameter set");
+        for (int k = 0; k < 3; ++k)
+            if (!finite(m->quadric[k]) || std::fabs(m->quadric[k]) > 100.f)
+                return fail(c, RT_EINVAL, "rt_set_metric: quadric coefficients must be finite with |q| <= 100");
+        bf = {m->quadric[0], m->quadric[1], m->quadric[2], 0.f, 0.f, 0.f, 0.f, 0.f};
+        bd = {m->quadric[0], m->quadric[1], m->quadric[2], 0.0, 0.0, 0.0, 0.0, 0.0};
+    }
+    if (!c->host_only) {
+        rt_status st = sync_last(c);
+        if (st != RT_OK) return st;
+        hipSetDevice(c->device);
+        if ((st = upload(c, &c->d_bump_f, &c->bump_f_bytes, bf.data(), bf.size() * sizeof(float))) != RT_OK) return st;
+        if ((st = upload(c, &c->d_bump_d, &c->bump_d_bytes, bd.data(), bd.size() * sizeof(double))) != RT_OK) return st;
+        c->dd.bump_f = (const float4 *)c->d_bump_f;
+        c->dd.bump_d = (const double *)c->d_bump_d;
+    }
+    c->kind = m->kind;
+    c->n_sets = m->n_sets;
+    c->n_bumps = nb;
+    c->amp = 0.f;
+    c->th0 = 0.f;
+    c->cull = m->cull_sigmas;
+    c->bumps.clear();
+    c->has_metric = true;
+    c->surr_sb_dirty = true;
+    c->adj_valid = false;
+    c->err.clear();
+    return RT_OK;
+}
+
 rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
     if (!c) return RT_EINVAL;
     if (!m) return fail(c, RT_EINVAL, "rt_set_metric: metric is NULL");
-    if (m->kind < RT_METRIC_EUCLID || m->kind > RT_METRIC_PULLBACK_DEFORM)
+    if (m->kind < RT_METRIC_EUCLID || m->kind > RT_METRIC_GRAPH_QUADRIC)
         return fail(c, RT_EUNSUPPORTED, "rt_set_metric: unknown metric kind " + std::to_string(m->kind));
     if (m->n_sets < 1 || m->n_sets > MAX_SETS)
         return fail(c, RT_EINVAL, "rt_set_metric: n_sets must be in 1..64");
     if (m->kind == RT_METRIC_PULLBACK_DEFORM) return set_deform_metric(c, m);
+    if (m->kind == RT_METRIC_GRAPH_ANISO || m->kind == RT_METRIC_GRAPH_QUADRIC) return set_graph2_metric(c, m);
     int nb = m->kind == RT_METRIC_GRAPH_GAUSS ? m->n_bumps : 0;
     if (nb < 0 || nb > MAX_BUMPS) return fail(c, RT_EINVAL, "rt_set_metric: n_bumps must be in 0..64");
     if (nb > 0 && !m->bumps) return fail(c, RT_EINVAL, "rt_set_metric: bumps is NULL");

@@ -12,7 +12,7 @@
 
 namespace rtd {
 
-enum { KIND_EUCLID = 0, KIND_GRAPH = 1, KIND_TWIST = 2, KIND_ZTWIST = 3, KIND_DEFORM = 4 };
+enum { KIND_EUCLID = 0, KIND_GRAPH = 1, KIND_TWIST = 2, KIND_ZTWIST = 3, KIND_DEFORM = 4, KIND_GANISO = 5, KIND_GQUAD = 6 };
 enum { STEP_RK4 = 0, STEP_RK45 = 1, STEP_EULER = 2 };
 
 constexpr int MAX_BUMPS = 64;
@@ -190,6 +190,62 @@ __device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ 
     return graph_finish(A);
 }
 
+// Graph metric of a sum of anisotropic Gaussians (Eq. 6.1 with three
+// spreads): with d = x - c, S = diag(1/s^2) and w = a exp(-d^T S d / 2),
+//   grad f = -sum_b w_b S d_b,   y^T H y = sum_b w_b ((S d_b . y)^2 - y^T S_b y)
+// and y' = -grad f (y^T H y) / (1 + |grad f|^2) as for the isotropic kind.
+// Parameters: two float4 per bump, (cx, cy, cz, a), (1/sx^2, 1/sy^2, 1/sz^2,
+// cut2); double, eight values in the same order.  A bump contributes only
+// where d^T S d <= cut2 (per lane).
+template <class T> struct ABump {
+    V3<T> c, s;
+    T a, cut2;
+};
+__device__ __forceinline__ ABump<float> abump_at(const float4 *__restrict__ B, int i) {
+    const float4 *q = (const float4 *)((const char *)B + ((unsigned)i << 5));
+    const float4 b0 = q[0], b1 = q[1];
+    return {mk(b0.x, b0.y, b0.z), mk(b1.x, b1.y, b1.z), b0.w, b1.w};
+}
+__device__ __forceinline__ ABump<double> abump_at(const double *__restrict__ B, int i) {
+    const double *q = B + 8 * i;
+    return {mk(q[0], q[1], q[2]), mk(q[4], q[5], q[6]), q[3], q[7]};
+}
+
+template <class T, bool COUNT = false, class PB>
+__device__ __forceinline__ V3<T> graph_aniso_accel(PB B, uint64_t mask, V3<T> p, V3<T> y, unsigned *n_in = nullptr) {
+    T gx = T(0), gy = T(0), gz = T(0), q = T(0);
+    unsigned n = 0;
+    while (mask) {
+        const int b = __builtin_ctzll(mask);
+        mask &= ~(1ull << b);
+        const auto P = abump_at(B, b);
+        const V3<T> d = mk(p.x - P.c.x, p.y - P.c.y, p.z - P.c.z);
+        const V3<T> Sd = mk(P.s.x * d.x, P.s.y * d.y, P.s.z * d.z);
+        const T r2 = dot(d, Sd);
+        const T w = r2 <= P.cut2 ? P.a * exp2_(T(-0.5) * log2e_<T>() * r2) : T(0);
+        if (COUNT) n += r2 <= P.cut2 ? 1u : 0u;
+        gx -= w * Sd.x;
+        gy -= w * Sd.y;
+        gz -= w * Sd.z;
+        const T u = dot(Sd, y);
+        const T ySy = P.s.x * y.x * y.x + P.s.y * y.y * y.y + P.s.z * y.z * y.z;
+        q += w * (u * u - ySy);
+    }
+    if (COUNT) *n_in += n;
+    const T den = T(1) + gx * gx + gy * gy + gz * gz;
+    const T c = -q * rcp_(den);
+    return mk(c * gx, c * gy, c * gz);
+}
+
+// Graph metric of the quadratic f = qx x^2 + qy y^2 + qz z^2 (the example of
+// Sec. 5.1 is (1, 1, -1)): grad f = 2 q x, y^T H y = 2 sum_j q_j y_j^2.
+template <class T> __device__ __forceinline__ V3<T> graph_quad_accel(V3<T> q, V3<T> p, V3<T> y) {
+    const V3<T> g = mk(T(2) * q.x * p.x, T(2) * q.y * p.y, T(2) * q.z * p.z);
+    const T h = T(2) * (q.x * y.x * y.x + q.y * y.y * y.y + q.z * y.z * y.z);
+    const T c = -h * rcp_(T(1) + dot(g, g));
+    return c * g;
+}
+
 // Double precision version over a (per-lane) mask, same regrouping.
 __device__ __forceinline__ V3<double> graph_accel_f64(const double *__restrict__ B, uint64_t mask, V3<double> p,
                                                       V3<double> y) {
@@ -343,6 +399,16 @@ __device__ __forceinline__ Deform<float> deform_at(const float4 *__restrict__ B,
 __device__ __forceinline__ Deform<double> deform_at(const double *__restrict__ B, int i) {
     const double *q = B + 12 * i;
     return {mk(q[0], q[1], q[2]), mk(q[4], q[5], q[6]), mk(q[8], q[9], q[10]), q[3], q[7]};
+}
+
+// Spread-scaled distance from the box [lo, hi] to the centre of an
+// anisotropic bump (c, 1/s^2 as the first three values of the float4 pair),
+// rounded down by 1e-5.
+__device__ __forceinline__ float aniso_box_rho(float4 b0, float4 b1, const float lo[3], const float hi[3]) {
+    const float ex = fmaxf(fmaxf(lo[0] - b0.x, b0.x - hi[0]), 0.0f);
+    const float ey = fmaxf(fmaxf(lo[1] - b0.y, b0.y - hi[1]), 0.0f);
+    const float ez = fmaxf(fmaxf(lo[2] - b0.z, b0.z - hi[2]), 0.0f);
+    return sqrt_(ex * ex * b1.x + ey * ey * b1.y + ez * ez * b1.z) * 0.99999f;
 }
 
 // Lower bound on the spread-scaled distance rho from the points where the

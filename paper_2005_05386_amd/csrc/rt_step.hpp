@@ -178,6 +178,13 @@ template <int KIND, bool COUNT, bool SREG = false> struct Acc32 {
             return true;
         } else if constexpr (KIND == KIND_DEFORM) {
             return deform_accel<float, COUNT>(B, mask, p, y, a, n_bump);
+        } else if constexpr (KIND == KIND_GANISO) {
+            a = graph_aniso_accel<float, COUNT>(B, mask, p, y, n_bump);
+            return true;
+        } else if constexpr (KIND == KIND_GQUAD) {
+            const float4 q = B[0];
+            a = graph_quad_accel<float>(mk(q.x, q.y, q.z), p, y);
+            return true;
         } else {
             a = mk(0.f, 0.f, 0.f);
             return true;

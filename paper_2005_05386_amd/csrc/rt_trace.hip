@@ -76,6 +76,22 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
             gdd = ztwist_gdd<float>(e, d);
         } else if constexpr (KIND == KIND_DEFORM) {
             gdd = deform_gdd<float>(Bs, A.n_bumps, e, d);
+        } else if constexpr (KIND == KIND_GANISO) {
+            // g(d, d) = |d|^2 + (grad f . d)^2
+            float gd = 0.f;
+            for (int b = 0; b < A.n_bumps; ++b) {
+                const ABump<float> P = abump_at(Bs, b);
+                const V3<float> q = mk(e.x - P.c.x, e.y - P.c.y, e.z - P.c.z);
+                const V3<float> Sq = mk(P.s.x * q.x, P.s.y * q.y, P.s.z * q.z);
+                const float r2 = dot(q, Sq);
+                const float w = r2 <= P.cut2 ? P.a * exp2_(-0.5f * log2e_<float>() * r2) : 0.f;
+                gd -= w * dot(Sq, d);
+            }
+            gdd = dot(d, d) + gd * gd;
+        } else if constexpr (KIND == KIND_GQUAD) {
+            const float4 q = Bs[0];
+            const float gd = 2.f * (q.x * e.x * d.x + q.y * e.y * d.y + q.z * e.z * d.z);
+            gdd = dot(d, d) + gd * gd;
         } else {
             gdd = dot(d, d);
         }
@@ -272,6 +288,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                         if (KIND == KIND_GRAPH && lane < n_bumps) {
                             float4 b0 = Bs[2 * lane], b1 = Bs[2 * lane + 1];
                             need = box_dist2(b0.x, b0.y, b0.z, lo, hi) <= b1.z;
+                        } else if (KIND == KIND_GANISO && lane < n_bumps) {
+                            const float4 b0 = Bs[2 * lane], b1 = Bs[2 * lane + 1];
+                            const float rho = aniso_box_rho(b0, b1, lo, hi);
+                            need = rho * rho <= b1.w * 1.00001f;
                         } else if (KIND == KIND_DEFORM && lane < n_bumps) {
                             // the ball (in ray coordinates) where the deformation can act
                             const float rho = deform_box_rho(Bs + 4 * lane, lo, hi, disp);
@@ -675,6 +695,12 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
                 return true;
             } else if constexpr (KIND == KIND_DEFORM) {
                 return deform_accel<double>(Bs, mask, p, v, a);
+            } else if constexpr (KIND == KIND_GANISO) {
+                a = graph_aniso_accel<double>(Bs, mask, p, v);
+                return true;
+            } else if constexpr (KIND == KIND_GQUAD) {
+                a = graph_quad_accel<double>(mk(Bs[0], Bs[1], Bs[2]), p, v);
+                return true;
             } else {
                 a = mk(0.0, 0.0, 0.0);
                 return true;
@@ -898,7 +924,7 @@ template <int KIND, int STEP> int occ() {
 namespace rti {
 
 bool supported(int kind, int step) {
-    return kind >= 0 && kind <= 4 && step >= 0 && step <= 2;
+    return kind >= 0 && kind <= 6 && step >= 0 && step <= 2;
 }
 
 #define RT_DISPATCH(KIND, FN, ...)                                                 \
@@ -914,7 +940,9 @@ int trace_blocks_per_cu(int kind, int step) {
     case KIND_GRAPH: RT_DISPATCH(KIND_GRAPH, occ)
     case KIND_TWIST: RT_DISPATCH(KIND_TWIST, occ)
     case KIND_ZTWIST: RT_DISPATCH(KIND_ZTWIST, occ)
-    default: RT_DISPATCH(KIND_DEFORM, occ)
+    case KIND_DEFORM: RT_DISPATCH(KIND_DEFORM, occ)
+    case KIND_GANISO: RT_DISPATCH(KIND_GANISO, occ)
+    default: RT_DISPATCH(KIND_GQUAD, occ)
     }
 }
 
@@ -934,7 +962,9 @@ hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, i
     case KIND_GRAPH: RT_DISPATCH(KIND_GRAPH, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_TWIST: RT_DISPATCH(KIND_TWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_ZTWIST: RT_DISPATCH(KIND_ZTWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
-    default: RT_DISPATCH(KIND_DEFORM, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    case KIND_DEFORM: RT_DISPATCH(KIND_DEFORM, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    case KIND_GANISO: RT_DISPATCH(KIND_GANISO, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    default: RT_DISPATCH(KIND_GQUAD, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     }
 }
 

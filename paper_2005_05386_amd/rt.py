@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED, RT_ESTATE = 0, -1, -2, -3, -4, -5
-EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST, PULLBACK_DEFORM = 0, 1, 2, 3, 4
+EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST, PULLBACK_DEFORM, GRAPH_ANISO, GRAPH_QUADRIC = 0, 1, 2, 3, 4, 5, 6
 RK4, RK45, EULER = 0, 1, 2
 FLAG_TIMING, FLAG_COUNT_WORK, FLAG_SURROGATE = 1, 2, 4
 
@@ -46,7 +46,8 @@ class rt_bump(C.Structure):
 class rt_metric(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_sets", C.c_int), ("n_bumps", C.c_int), ("bumps", C.c_void_p),
                 ("twist_amp", C.c_float), ("twist_theta0", C.c_float), ("cull_sigmas", C.c_float),
-                ("n_deforms", C.c_int), ("deforms", C.c_void_p)]
+                ("n_deforms", C.c_int), ("deforms", C.c_void_p),
+                ("n_abumps", C.c_int), ("abumps", C.c_void_p), ("quadric", C.c_float * 3)]
 
 
 class rt_scene(C.Structure):
@@ -188,11 +189,20 @@ class Tracer:
         d = metric.get("deforms")
         d = np.zeros((1, 0, 10), np.float32) if d is None else np.asarray(d, np.float32)
         d = np.ascontiguousarray(d[None] if d.ndim == 2 else d)
+        ab = metric.get("abumps")
+        ab = np.zeros((1, 0, 7), np.float32) if ab is None else np.asarray(ab, np.float32)
+        ab = np.ascontiguousarray(ab[None] if ab.ndim == 2 else ab)
         if int(metric["kind"]) == PULLBACK_DEFORM:
             n_sets = d.shape[0]
+        if int(metric["kind"]) == GRAPH_ANISO:
+            n_sets = ab.shape[0]
+        if int(metric["kind"]) == GRAPH_QUADRIC:
+            n_sets = 1
+        q = [float(x) for x in metric.get("quadric", (0.0, 0.0, 0.0))]
         m = rt_metric(int(metric["kind"]), int(n_sets), int(n_bumps), b.ctypes.data if b.size else None,
                       float(metric.get("twist_amp", 0.4)), float(metric.get("twist_theta0", 1.2)),
-                      float(metric.get("cull_sigmas", 6.0)), int(d.shape[1]), d.ctypes.data if d.size else None)
+                      float(metric.get("cull_sigmas", 6.0)), int(d.shape[1]), d.ctypes.data if d.size else None,
+                      int(ab.shape[1]), ab.ctypes.data if ab.size else None, (C.c_float * 3)(*q))
         self._check(_lib.rt_set_metric(self._h, C.byref(m)))
         self.n_sets = n_sets
 

@@ -124,6 +124,20 @@ def test_metric_and_scene_validation():
         with pytest.raises(rt.RtError) as e:
             tr.set_metric(W.metric(W.PULLBACK_DEFORM, deforms=W.random_deforms(n, 0).reshape(n, 10)))
         assert e.value.status == rt.RT_EINVAL
+    # anisotropic bumps and the quadric
+    ab = W.random_abumps(4, 0)
+    tr.set_metric(W.metric(W.GRAPH_ANISO, abumps=ab))
+    for mod in [lambda x: x.__setitem__((0, 4), 0.0), lambda x: x.__setitem__((1, 6), -0.2),
+                lambda x: x.__setitem__((2, 1), np.inf)]:
+        bb = ab.copy()
+        mod(bb)
+        with pytest.raises(rt.RtError) as e:
+            tr.set_metric(W.metric(W.GRAPH_ANISO, abumps=bb))
+        assert e.value.status == rt.RT_EINVAL
+    tr.set_metric(W.metric(W.GRAPH_QUADRIC, quadric=(1.0, 1.0, -1.0)))
+    with pytest.raises(rt.RtError) as e:
+        tr.set_metric(W.metric(W.GRAPH_QUADRIC, quadric=(1.0, 200.0, -1.0)))
+    assert e.value.status == rt.RT_EINVAL
     # trace before a scene is set
     tr2 = rt.Tracer(-1)
     tr2.set_metric(W.metric(W.GRAPH_GAUSS, b))

@@ -297,3 +297,36 @@ def test_deform_deterministic_across_culling(rt, K, S):
     g = gpu_trace(rt, wl, rule=dict(wl["rule"], cull_every=K, pass_steps=S))
     for k in ("hit", "t", "id", "dir", "steps"):
         assert np.array_equal(ref[k], g[k]), k
+
+
+# ------------------ more graph metrics: anisotropic bumps, Sec. 5.1 quadratic
+@pytest.mark.parametrize("name", ["abumps16_1080p", "quadric_1080p"])
+def test_graph2_small_full_frame(rt, name):
+    say("%s 96x54 full frame" % name)
+    wl = W.with_size(W.get(name), 96, 54)
+    g = gpu_trace(rt, wl)
+    rep = compare(g, oracle_trace(wl))
+    say(rep)
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("name", ["abumps16_1080p", "quadric_1080p"])
+def test_graph2_1080p_sampled(rt, name):
+    say("%s full frame, 1000 sampled pixels" % name)
+    wl = W.get(name)
+    g = gpu_trace(rt, wl)
+    pix = W.pixel_sample(1920, 1080, 1000, seed=6)
+    rep = compare(g, oracle_trace(wl, pix), pix)
+    say(rep, g["_stats"])
+    assert_parity(rep)
+
+
+def test_aniso_deterministic_across_culling(rt):
+    """Per-lane ellipsoid cut: any superset bump list gives the same
+    arithmetic, so the frame is bitwise independent of the culling period."""
+    say("anisotropic bumps determinism K=4 S=64")
+    wl = W.with_size(W.get("abumps16_1080p"), 64, 40)
+    ref = gpu_trace(rt, wl)
+    g = gpu_trace(rt, wl, rule=dict(wl["rule"], cull_every=4, pass_steps=64))
+    for k in ("hit", "t", "id", "dir", "steps"):
+        assert np.array_equal(ref[k], g[k]), k
