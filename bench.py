@@ -414,6 +414,46 @@ def bench_euler(args, wl, torch, rt):
     print(json.dumps(line), flush=True)
 
 
+def bench_illum(args, wl, torch, rt):
+    """Direct Riemannian illumination of the traced 1080p frame by a point
+    light: shooting for the geodesic from every hit to the light, visibility
+    along it and the Lambert term in the metric (rt_illuminate).  The trace
+    is not timed; `value` is hit pixels shaded per second."""
+    import numpy as np
+
+    cam = wl["camera"]
+    tr = rt.Tracer(0)
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    out = tr.trace(cam, wl["rule"])
+    for _ in range(max(1, args.warmup)):
+        sh = tr.illuminate(cam, out, wl["light"])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        sh = tr.illuminate(cam, out, wl["light"])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    st = sh["status"].cpu().numpy()
+    n_hit = int((st != -3).sum())
+    line = {
+        "metric": "direct illumination: hit pixels shaded per second (1080p, 16 bumps, point light)",
+        "value": n_hit / (ms / 1e3), "unit": "pixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"],
+                   "light": list(wl["light"]["pos"]), "h": wl["light"]["h"], "tol": wl["light"]["tol"],
+                   "max_iters": wl["light"]["max_iters"]},
+        "pixels": {"hit": n_hit, "lit": int((st == 1).sum()), "shadowed": int((st == 0).sum()),
+                   "facing_away": int((st == 2).sum()), "no_geodesic": int((st == -1).sum())},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,6 +486,8 @@ def main():
         return bench_surrogate(args, wl, torch, rt)
     if args.workload == "euler_vs_rk4_1080p":
         return bench_euler(args, wl, torch, rt)
+    if "light" in wl:
+        return bench_illum(args, wl, torch, rt)
     cam, rule = wl["camera"], dict(wl["rule"])
     tr = rt.Tracer(0)
     tr.set_metric(wl["metric"])

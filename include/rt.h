@@ -289,6 +289,45 @@ typedef struct rt_stats {
 
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
 
+/* ---------------------------------------------------- direct illumination
+ * Riemannian illumination (Sec. 4): a surface point q is lit by a point
+ * light L through the geodesics joining q to L, with a Lambertian
+ * intensity that depends on the metric.  For every pixel of a trace that
+ * hit an object (traced->id >= 0), rt_illuminate finds a geodesic from the
+ * hit point q to L by shooting -- the g-unit direction v at q and the arc
+ * length T with gamma_{q,v}(T) = L, Newton's method from the straight
+ * segment, each shot an RK4 integration with step h -- then marches it
+ * against every object (crossings within 1e-3 of q ignored) and writes
+ *   shade  = grad F . v / sqrt(grad F^T g^-1 grad F) when lit, else 0:
+ *            the cosine between v and the metric normal g^-1 grad F of the
+ *            surface F = 0, both measured in g at q;
+ *   status = 1 lit, 0 the geodesic is blocked, 2 the surface faces away
+ *            (cosine <= 0), -1 no geodesic found within max_iters (or a
+ *            shot overran max_steps), -3 the pixel did not hit;
+ *   dir    = v (optional), len = T (optional).
+ * Several geodesics may join q and L; the one found is the one reached
+ * from the straight segment.  The paper describes this illumination but
+ * not how to compute it.  camera must be the traced camera; the metric and
+ * scene of the context are used.  Outputs are device arrays of
+ * n_sets * height * width entries (dir: 3 per entry). */
+typedef struct rt_light {
+    float pos[3];   /* point light */
+    float h;        /* RK4 step of the shots, (0, 0.1] */
+    float tol;      /* convergence: max-norm distance of gamma(T) to the light, > 0 */
+    int max_iters;  /* Newton iterations, 1..64 */
+    int max_steps;  /* steps per shot, 1..100000 */
+} rt_light;
+
+typedef struct rt_shading {
+    float *shade;     /* device, required */
+    int32_t *status;  /* device, required */
+    float *dir;       /* device, optional */
+    float *len;       /* device, optional */
+} rt_shading;
+
+rt_status rt_illuminate(rt_ctx *ctx, const rt_camera *camera, const rt_outputs *traced, const rt_light *light,
+                        const rt_shading *out, void *hip_stream);
+
 /* ------------------------------------------------------- differentiation
  * Gradients of a loss on the hit map with respect to every bump parameter
  * (a, cx, cy, cz, sigma) of every set: the discrete adjoint of the RK4

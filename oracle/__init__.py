@@ -99,6 +99,11 @@ def lib():
                                        C.POINTER(_Rule), C.c_int64, C.POINTER(C.c_int64), dp,
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32), C.c_int]
+        L.orc_shoot.argtypes = [C.POINTER(_Metric), dp, C.c_double, C.c_double, dp]
+        L.orc_shoot.restype = C.c_int
+        L.orc_geodesic_clear.argtypes = [C.POINTER(_Metric), C.POINTER(_Scene), dp, C.c_double, C.c_double,
+                                         C.c_double]
+        L.orc_geodesic_clear.restype = C.c_int
         L.orc_trajectory.argtypes = [C.POINTER(_Metric), C.POINTER(_Rule), dp, C.c_int, dp]
         L.orc_trajectory.restype = C.c_int
         _lib = L
@@ -173,6 +178,21 @@ class Oracle:
         r = _rule(rule)
         lib().orc_trajectory(C.byref(self.m), C.byref(r), _dptr(z0), int(n_steps), _dptr(out))
         return out
+
+    # ---- direct illumination
+    def shoot(self, q, v, T, h):
+        """End state (x, y) of the geodesic from (q, v) over arc length T
+        (RK4, step h, last step shortened)."""
+        z0 = np.ascontiguousarray(np.concatenate([q, v]), np.float64)
+        out = np.zeros(6)
+        ok = lib().orc_shoot(C.byref(self.m), _dptr(z0), float(T), float(h), _dptr(out))
+        return out, bool(ok)
+
+    def geodesic_clear(self, q, v, T, h, skip=1e-3):
+        """True when that geodesic crosses no object between skip and T."""
+        z0 = np.ascontiguousarray(np.concatenate([q, v]), np.float64)
+        return bool(lib().orc_geodesic_clear(C.byref(self.m), C.byref(self.s), _dptr(z0), float(T), float(h),
+                                             float(skip)))
 
     # ---- tracing
     def trace(self, camera, rule, pixels=None, nthreads=0):

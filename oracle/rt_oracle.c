@@ -455,6 +455,68 @@ static int chord_test(const orc_scene *s, const double x0[3], const double x1[3]
     return best;
 }
 
+/* ------------------------------------------------- direct illumination
+ * The geodesic from state z0 over arc length T: ceil(T / h) classical RK4
+ * steps, the last one shortened to end exactly at T. */
+int orc_shoot(const orc_metric *m, const double z0[6], double T, double h, double out[6])
+{
+    int n = (int)ceil(T / h);
+    if (n < 1) n = 1;
+    double z[6];
+    memcpy(z, z0, sizeof z);
+    for (int i = 0; i < n; i++) {
+        double hs = (i == n - 1) ? T - (n - 1) * h : h;
+        double zn[6];
+        if (!orc_step(m, ORC_RK4, z, hs, zn, NULL)) return 0;
+        memcpy(z, zn, sizeof z);
+    }
+    memcpy(out, z, sizeof z);
+    return 1;
+}
+
+/* Whether that geodesic crosses no object between arc length skip and T
+ * (Sec. 4, Riemannian illumination: a light reaches q along a geodesic
+ * that meets nothing on the way): every step's chord against every object,
+ * spheres by both roots of the quadratic, planes and tori by a sign change
+ * of the implicit function. */
+int orc_geodesic_clear(const orc_metric *m, const orc_scene *s, const double z0[6], double T, double h,
+                       double skip)
+{
+    int n = (int)ceil(T / h);
+    if (n < 1) n = 1;
+    double z[6], t = 0.0;
+    memcpy(z, z0, sizeof z);
+    int nobj = s->n_spheres + s->n_planes + s->n_tori;
+    for (int i = 0; i < n; i++) {
+        double hs = (i == n - 1) ? T - (n - 1) * h : h;
+        double zn[6];
+        if (!orc_step(m, ORC_RK4, z, hs, zn, NULL)) return 0;
+        double D[3] = {zn[0] - z[0], zn[1] - z[1], zn[2] - z[2]};
+        for (int id = 0; id < nobj; id++) {
+            if (id < s->n_spheres) {
+                const double *p = s->spheres + 4 * id;
+                double oc[3] = {z[0] - p[0], z[1] - p[1], z[2] - p[2]};
+                double A = dot3(D, D), B = dot3(D, oc), C = dot3(oc, oc) - p[3] * p[3];
+                double disc = B * B - A * C;
+                if (A <= 0.0 || disc < 0.0) continue;
+                double q = sqrt(disc);
+                double r[2] = {(-B - q) / A, (-B + q) / A};
+                for (int k = 0; k < 2; k++)
+                    if (r[k] >= 0.0 && r[k] <= 1.0 && t + r[k] * hs > skip) return 0;
+            } else {
+                double F0 = obj_F(s, id, z), F1 = obj_F(s, id, zn);
+                if ((F0 > 0.0) != (F1 > 0.0)) {
+                    double sc = F0 / (F0 - F1);
+                    if (t + sc * hs > skip) return 0;
+                }
+            }
+        }
+        memcpy(z, zn, sizeof z);
+        t += hs;
+    }
+    return 1;
+}
+
 /* --------------------------------------------------------------- tracing */
 static void finish(orc_result *res, const double z[6], double t, int id)
 {

@@ -79,6 +79,9 @@ int orc_trace_pixels(const orc_metric *m, const orc_scene *s, const orc_camera *
                      const orc_rule *r, int64_t n, const int64_t *pix,
                      double *out8, int32_t *ids, int32_t *steps,
                      int32_t *rejected, int nthreads);
+int orc_shoot(const orc_metric *m, const double z0[6], double T, double h, double out[6]);
+int orc_geodesic_clear(const orc_metric *m, const orc_scene *s, const double z0[6], double T, double h,
+                       double skip);
 int orc_trajectory(const orc_metric *m, const orc_rule *r, const double z0[6],
                    int n_steps, double *out /* [n_steps+1][6] */);
 #endif

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt.so")
-SOURCES = ["rt_trace.hip", "rt_adjoint.hip", "rt_mlp.hip", "rt_surrogate.hip", "rt_api.cpp"]
+SOURCES = ["rt_trace.hip", "rt_illum.hip", "rt_adjoint.hip", "rt_mlp.hip", "rt_surrogate.hip", "rt_api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

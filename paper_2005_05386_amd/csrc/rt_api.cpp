@@ -863,6 +863,58 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     return RT_OK;
 }
 
+rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *traced, const rt_light *L,
+                        const rt_shading *out, void *stream) {
+    if (!c) return RT_EINVAL;
+    if (!cam || !traced || !L || !out) return fail(c, RT_EINVAL, "rt_illuminate: NULL camera, traced outputs, light or output");
+    if (!c->has_metric || !c->has_scene) return fail(c, RT_ESTATE, "rt_illuminate: set the metric and the scene first");
+    if (cam->width < 1 || cam->height < 1) return fail(c, RT_EINVAL, "rt_illuminate: width and height must be >= 1");
+    if ((int64_t)cam->width * cam->height * c->n_sets > 2147483647LL)
+        return fail(c, RT_EINVAL, "rt_illuminate: width*height*n_sets exceeds 2^31-1");
+    if (!traced->hit || !traced->id) return fail(c, RT_EINVAL, "rt_illuminate: traced hit and id are required");
+    if (!out->shade || !out->status) return fail(c, RT_EINVAL, "rt_illuminate: shade and status are required");
+    for (int k = 0; k < 3; ++k)
+        if (!finite(L->pos[k])) return fail(c, RT_EINVAL, "rt_illuminate: non-finite light position");
+    if (!finite(L->h) || !(L->h > 0.f) || L->h > 0.1f) return fail(c, RT_EINVAL, "rt_illuminate: h must be in (0, 0.1]");
+    if (!finite(L->tol) || !(L->tol > 0.f)) return fail(c, RT_EINVAL, "rt_illuminate: tol must be finite and > 0");
+    if (L->max_iters < 1 || L->max_iters > 64) return fail(c, RT_EINVAL, "rt_illuminate: max_iters must be in 1..64");
+    if (L->max_steps < 1 || L->max_steps > 100000)
+        return fail(c, RT_EINVAL, "rt_illuminate: max_steps must be in 1..100000");
+    if (c->host_only) return fail(c, RT_ESTATE, "rt_illuminate: host-only context (created with device -1)");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    rti::IllumArgs a{};
+    a.kind = c->kind;
+    a.n_sets = c->n_sets;
+    a.n_bumps = c->n_bumps;
+    a.twist_amp = c->amp;
+    a.twist_theta0 = c->th0;
+    a.n_spheres = (int)c->sph.size();
+    a.n_planes = (int)c->pln.size();
+    a.n_tori = (int)c->tor.size();
+    a.width = cam->width;
+    a.height = cam->height;
+    a.hit = traced->hit;
+    a.id = traced->id;
+    for (int k = 0; k < 3; ++k) a.light[k] = L->pos[k];
+    a.h = L->h;
+    a.tol = L->tol;
+    a.max_iters = L->max_iters;
+    a.max_steps = L->max_steps;
+    a.shade = out->shade;
+    a.status = out->status;
+    a.dir = out->dir;
+    a.len = out->len;
+    const int64_t n = (int64_t)cam->width * cam->height * c->n_sets;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)c->n_cu * 8));
+    hipStream_t s = (hipStream_t)stream;
+    e = rti::launch_illum(a, c->dd, grid, s);
+    if (e != hipSuccess) return hip_fail(c, e, "rt_illuminate launch");
+    c->last_stream = s;
+    c->err.clear();
+    return RT_OK;
+}
+
 rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
                    void *stream) {
     return trace_impl(c, cam, r, max_steps, o, stream, nullptr, 0, 0);

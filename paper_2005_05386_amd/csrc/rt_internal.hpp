@@ -156,6 +156,21 @@ struct DeviceData {
 // control block after the pass blocks must hold CTR_SURR_WORDS words.
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid_blocks,
                         int refine_blocks, hipStream_t s, hipEvent_t *ev, const struct SurrArgs *S, int mlp_blocks);
+// ------------------------------------------------------ direct illumination
+struct IllumArgs {
+    int kind, n_sets, n_bumps;
+    float twist_amp, twist_theta0;
+    int n_spheres, n_planes, n_tori;
+    int width, height;
+    const float *hit;  // traced hit points [n_sets * H * W][3]
+    const int *id;     // traced object ids
+    float light[3];
+    float h, tol;
+    int max_iters, max_steps;
+    float *shade, *dir, *len;
+    int *status;
+};
+hipError_t launch_illum(const IllumArgs &a, const DeviceData &d, int grid, hipStream_t s);
 // ------------------------------------------------------------- MLP (BF16)
 enum Epi { EPI_NONE = 0, EPI_HIDDEN = 1, EPI_BIAS = 2, EPI_DSILU = 3 };
 

@@ -192,4 +192,41 @@ template <int KIND, bool COUNT, bool SREG = false> struct Acc32 {
     }
 };
 
+// g(d, d) at x for every metric kind, in single precision; Bs is the
+// parameter set's table and n its number of records.
+template <int KIND>
+__device__ __forceinline__ float metric_gdd(const float4 *__restrict__ Bs, int n, float amp, float th0, V3<float> x,
+                                            V3<float> d) {
+    if constexpr (KIND == KIND_GRAPH) {
+        GraphAccum G{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < n; ++b) graph_bump_f32(Bs[2 * b], Bs[2 * b + 1], x, d, 1.0f, G);
+        const float gd = G.gx * d.x + G.gy * d.y + G.gz * d.z;
+        return dot(d, d) + gd * gd;
+    } else if constexpr (KIND == KIND_TWIST) {
+        return twist_gdd<float>(amp, th0, x, d);
+    } else if constexpr (KIND == KIND_ZTWIST) {
+        return ztwist_gdd<float>(x, d);
+    } else if constexpr (KIND == KIND_DEFORM) {
+        return deform_gdd<float>(Bs, n, x, d);
+    } else if constexpr (KIND == KIND_GANISO) {
+        // g(d, d) = |d|^2 + (grad f . d)^2
+        float gd = 0.f;
+        for (int b = 0; b < n; ++b) {
+            const ABump<float> P = abump_at(Bs, b);
+            const V3<float> q = mk(x.x - P.c.x, x.y - P.c.y, x.z - P.c.z);
+            const V3<float> Sq = mk(P.s.x * q.x, P.s.y * q.y, P.s.z * q.z);
+            const float r2 = dot(q, Sq);
+            const float w = r2 <= P.cut2 ? P.a * exp2_(-0.5f * log2e_<float>() * r2) : 0.f;
+            gd -= w * dot(Sq, d);
+        }
+        return dot(d, d) + gd * gd;
+    } else if constexpr (KIND == KIND_GQUAD) {
+        const float4 q = Bs[0];
+        const float gd = 2.f * (q.x * x.x * d.x + q.y * x.y * d.y + q.z * x.z * d.z);
+        return dot(d, d) + gd * gd;
+    } else {
+        return dot(d, d);
+    }
+}
+
 }  // namespace rtd

@@ -64,37 +64,7 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
                          su * A.right[2] + sv * A.up[2] + A.fwd[2]);
         d = rsqrt_(dot(d, d)) * d;
         V3<float> e = mk(A.eye[0], A.eye[1], A.eye[2]);
-        float gdd;
-        if constexpr (KIND == KIND_GRAPH) {
-            GraphAccum G{0.f, 0.f, 0.f, 0.f};
-            for (int b = 0; b < A.n_bumps; ++b) graph_bump_f32(Bs[2 * b], Bs[2 * b + 1], e, d, 1.0f, G);
-            float gd = G.gx * d.x + G.gy * d.y + G.gz * d.z;
-            gdd = dot(d, d) + gd * gd;
-        } else if constexpr (KIND == KIND_TWIST) {
-            gdd = twist_gdd<float>(A.twist_amp, A.twist_theta0, e, d);
-        } else if constexpr (KIND == KIND_ZTWIST) {
-            gdd = ztwist_gdd<float>(e, d);
-        } else if constexpr (KIND == KIND_DEFORM) {
-            gdd = deform_gdd<float>(Bs, A.n_bumps, e, d);
-        } else if constexpr (KIND == KIND_GANISO) {
-            // g(d, d) = |d|^2 + (grad f . d)^2
-            float gd = 0.f;
-            for (int b = 0; b < A.n_bumps; ++b) {
-                const ABump<float> P = abump_at(Bs, b);
-                const V3<float> q = mk(e.x - P.c.x, e.y - P.c.y, e.z - P.c.z);
-                const V3<float> Sq = mk(P.s.x * q.x, P.s.y * q.y, P.s.z * q.z);
-                const float r2 = dot(q, Sq);
-                const float w = r2 <= P.cut2 ? P.a * exp2_(-0.5f * log2e_<float>() * r2) : 0.f;
-                gd -= w * dot(Sq, d);
-            }
-            gdd = dot(d, d) + gd * gd;
-        } else if constexpr (KIND == KIND_GQUAD) {
-            const float4 q = Bs[0];
-            const float gd = 2.f * (q.x * e.x * d.x + q.y * e.y * d.y + q.z * e.z * d.z);
-            gdd = dot(d, d) + gd * gd;
-        } else {
-            gdd = dot(d, d);
-        }
+        const float gdd = metric_gdd<KIND>(Bs, A.n_bumps, A.twist_amp, A.twist_theta0, e, d);
         V3<float> y = rsqrt_(gdd) * d;
         float *__restrict__ dst = A.st + ((id >> 6) * rti::Q_NFIELDS * 64 + (id & 63));
         auto P = [&](int f, float v) { dst[f * 64] = v; };

@@ -29,7 +29,7 @@ EXPORTS = ["rt_abi_version", "rt_create", "rt_destroy", "rt_last_error", "rt_set
            "rt_trace", "rt_sync", "rt_get_stats", "rt_tape_bytes", "rt_trace_fwd_ckpt", "rt_loss_l2",
            "rt_trace_bwd", "rt_mlp_work_bytes", "rt_mlp_fwd", "rt_mlp_fwd_grouped", "rt_mlp_bwd", "rt_mse_grad", "rt_adamw_step",
            "rt_surrogate_gen", "rt_surrogate_train_bytes", "rt_surrogate_train", "rt_surrogate_calibrate",
-           "rt_surrogate_load"]
+           "rt_surrogate_load", "rt_illuminate"]
 MLP_PARAMS = 134918
 
 
@@ -71,6 +71,15 @@ class rt_outputs(C.Structure):
                 ("steps", C.c_void_p)]
 
 
+class rt_light(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("h", C.c_float), ("tol", C.c_float), ("max_iters", C.c_int),
+                ("max_steps", C.c_int)]
+
+
+class rt_shading(C.Structure):
+    _fields_ = [("shade", C.c_void_p), ("status", C.c_void_p), ("dir", C.c_void_p), ("len", C.c_void_p)]
+
+
 class rt_stats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("ray_steps", C.c_uint64), ("attempts", C.c_uint64),
                 ("wave_iters", C.c_uint64), ("lane_iters", C.c_uint64), ("bump_list_sum", C.c_uint64),
@@ -95,6 +104,9 @@ _lib.rt_set_scene.argtypes = [_P, C.POINTER(rt_scene)]
 _lib.rt_set_scene.restype = C.c_int
 _lib.rt_trace.argtypes = [_P, C.POINTER(rt_camera), C.POINTER(rt_step_rule), C.c_int, C.POINTER(rt_outputs), _P]
 _lib.rt_trace.restype = C.c_int
+_lib.rt_illuminate.argtypes = [_P, C.POINTER(rt_camera), C.POINTER(rt_outputs), C.POINTER(rt_light),
+                               C.POINTER(rt_shading), _P]
+_lib.rt_illuminate.restype = C.c_int
 _lib.rt_sync.argtypes = [_P, _P]
 _lib.rt_sync.restype = C.c_int
 _lib.rt_get_stats.argtypes = [_P, C.POINTER(rt_stats)]
@@ -253,6 +265,32 @@ class Tracer:
             max_steps = rule["max_steps"]
         out = self.alloc_outputs(camera, with_steps)
         return self.trace_into(camera, rule, max_steps, out)
+
+    def illuminate(self, camera, traced, light, stream=None):
+        """Direct Riemannian illumination of a traced frame by a point light
+        (rt_illuminate).  light: dict(pos, h=0.01, tol=1e-4, max_iters=16,
+        max_steps=4000).  Returns dict of cuda tensors shade, status, dir,
+        len."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        n = self.n_sets * camera["height"] * camera["width"]
+        for k, shape, dt in (("hit", (n, 3), torch.float32), ("id", (n,), torch.int32)):
+            tns = traced[k]
+            if tuple(tns.shape) != shape or tns.dtype != dt or not tns.is_cuda or not tns.is_contiguous():
+                raise ValueError("traced %s must be a contiguous %s cuda tensor of shape %s" % (k, dt, shape))
+        dev = traced["hit"].device
+        out = dict(shade=torch.empty(n, dtype=torch.float32, device=dev),
+                   status=torch.empty(n, dtype=torch.int32, device=dev),
+                   dir=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                   len=torch.empty(n, dtype=torch.float32, device=dev))
+        o = rt_outputs(traced["hit"].data_ptr(), None, traced["id"].data_ptr(), None, None)
+        L = rt_light((C.c_float * 3)(*[float(v) for v in light["pos"]]), float(light.get("h", 0.01)),
+                     float(light.get("tol", 1e-4)), int(light.get("max_iters", 16)), int(light.get("max_steps", 4000)))
+        sh = rt_shading(out["shade"].data_ptr(), out["status"].data_ptr(), out["dir"].data_ptr(), out["len"].data_ptr())
+        self._check(_lib.rt_illuminate(self._h, C.byref(camera_struct(camera)), C.byref(o), C.byref(L), C.byref(sh),
+                                       C.c_void_p(stream.cuda_stream)))
+        return out
 
     def trace_raw(self, camera, rule, max_steps, out_ptrs, stream_handle):
         """Enqueue with raw device pointers (hit, t, id, dir, steps-or-0)."""

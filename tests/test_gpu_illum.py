@@ -1,0 +1,138 @@
+"""Direct Riemannian illumination (rt_illuminate) on the GPU.
+
+Several geodesics may join a surface point to the light, so the GPU's
+answer is checked for validity rather than against one reference solution:
+the FP64 oracle integrates the returned geodesic and must land on the light,
+recomputes the Lambert term in the metric from the returned direction, and
+recomputes the visibility along it.  In flat space everything has a closed
+form."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import exact
+
+pytestmark = pytest.mark.gpu
+
+LIGHT = dict(pos=(2.5, 3.5, -3.0), h=0.01, tol=1e-4, max_iters=16, max_steps=4000)
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_05386_amd import rt as _rt
+    return _rt
+
+
+def _run(rt, wl, light=LIGHT):
+    tr = rt.Tracer(0)
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    out = tr.trace(wl["camera"], wl["rule"])
+    sh = tr.illuminate(wl["camera"], out, light)
+    tr.sync()
+    tra = rt.to_numpy(out)
+    return tra, {k: v.cpu().numpy() for k, v in sh.items()}
+
+
+def _grad_F(scene, oid, q):
+    """Outward gradient of the implicit function of object oid at q (FP64)."""
+    sp = np.asarray(scene["spheres"], np.float64).reshape(-1, 4)
+    pl = np.asarray(scene["planes"], np.float64).reshape(-1, 4)
+    to = np.asarray(scene["tori"], np.float64).reshape(-1, 8)
+    if oid < len(sp):
+        return 2.0 * (q - sp[oid, :3])
+    oid -= len(sp)
+    if oid < len(pl):
+        return pl[oid, :3].copy()
+    c, a, R = to[oid - len(pl), :3], to[oid - len(pl), 3:6], to[oid - len(pl), 6]
+    x = q - c
+    ax = x @ a
+    rad = x - ax * a
+    rn = np.linalg.norm(rad)
+    e = rn - R
+    return (e * rad / rn + ax * a) / np.hypot(e, ax)
+
+
+def test_flat_space_closed_form(rt):
+    """g = I: the geodesic to the light is the segment, found at once; the
+    Lambert term is n . (L - q)/|L - q| and the visibility is the segment's."""
+    say("illumination, flat space 64x48")
+    wl = W.with_size(W.get("bumps16_1080p"), 64, 48)
+    wl["metric"] = W.metric(W.EUCLID)
+    tra, sh = _run(rt, wl)
+    L = np.array(LIGHT["pos"], np.float64)
+    hit = tra["id"] >= 0
+    assert (sh["status"][~hit] == -3).all()
+    assert (sh["status"][hit] >= 0).all(), np.unique(sh["status"][hit])
+    n_bad = 0
+    for p in np.nonzero(hit)[0]:
+        q = tra["hit"][p].astype(np.float64)
+        d = L - q
+        T = np.linalg.norm(d)
+        v = d / T
+        assert np.abs(sh["dir"][p] - v).max() < 2e-5, (p, sh["dir"][p], v)
+        assert abs(sh["len"][p] - T) < 1e-4 * max(1.0, T)
+        gF = _grad_F(wl["scene"], tra["id"][p], q)
+        cos = gF @ v / np.linalg.norm(gF)
+        if cos <= 0:
+            n_bad += sh["status"][p] != 2
+            continue
+        qs = q + 1e-3 * v
+        t, oid = exact.line_hits(qs, v[None, :], wl["scene"], T - 1e-3)
+        lit = oid[0] < 0
+        if lit:
+            n_bad += not (sh["status"][p] == 1 and abs(sh["shade"][p] - cos) < 1e-4)
+        else:
+            n_bad += sh["status"][p] != 0
+    assert n_bad <= max(2, 0.002 * hit.sum()), (n_bad, hit.sum())
+
+
+@pytest.mark.parametrize("name,w,h", [("bumps16_1080p", 64, 40), ("twist_4k", 64, 40), ("deform16_1080p", 48, 30)])
+def test_curved_geodesics_reach_the_light(rt, name, w, h):
+    """Curved metrics: the oracle integrates each returned geodesic in FP64
+    and lands on the light; the Lambert term and the visibility recomputed
+    in FP64 from the returned direction agree."""
+    say("illumination, %s %dx%d" % (name, w, h))
+    wl = W.with_size(W.get(name), w, h)
+    tra, sh = _run(rt, wl)
+    orc = oracle.Oracle(wl["metric"], wl["scene"])
+    L = np.array(LIGHT["pos"], np.float64)
+    hit = np.nonzero(tra["id"] >= 0)[0]
+    st = sh["status"]
+    found = hit[st[hit] >= 0]
+    say("hits %d found %d lit %d shadowed %d facing away %d" % (len(hit), len(found), (st == 1).sum(),
+                                                                (st == 0).sum(), (st == 2).sum()))
+    assert len(found) >= 0.95 * len(hit)
+    worst_end = worst_cos = 0.0
+    vis_bad = 0
+    for p in found:
+        q = tra["hit"][p].astype(np.float64)
+        v = sh["dir"][p].astype(np.float64)
+        g = orc.metric_tensor(q)
+        v = v / np.sqrt(v @ g @ v)
+        T = float(sh["len"][p])
+        z, ok = orc.shoot(q, v, T, LIGHT["h"])
+        assert ok
+        worst_end = max(worst_end, np.abs(z[:3] - L).max())
+        gF = _grad_F(wl["scene"], tra["id"][p], q)
+        cos = gF @ v / np.sqrt(gF @ np.linalg.solve(g, gF))
+        if st[p] == 2:
+            assert cos < 1e-3, (p, cos)
+            continue
+        assert cos > -1e-3
+        if st[p] == 1:
+            worst_cos = max(worst_cos, abs(sh["shade"][p] - cos))
+        clear = orc.geodesic_clear(q, v, T, LIGHT["h"], 1e-3)
+        vis_bad += clear != (st[p] == 1)
+    say("worst end %.2e, worst cos %.2e, visibility disagreements %d" % (worst_end, worst_cos, vis_bad))
+    assert worst_end < 5e-4
+    assert worst_cos < 2e-3
+    assert vis_bad <= max(2, 0.01 * len(found))

@@ -432,3 +432,40 @@ def test_euler_is_first_order():
         r["h"] = h
         errs.append(np.abs(orc.trajectory(r, z0, int(round(2.0 / h)))[-1] - ref).max())
     assert 1.7 < errs[0] / errs[1] < 2.3, errs
+
+
+# --------------------------------------------------- direct illumination
+def test_shoot_and_visibility_flat_space():
+    """g = I: the shot geodesic is the segment q + t v, and it is clear
+    exactly when the segment meets no object (closed form)."""
+    wl = W.get("bumps16_1080p")
+    orc = oracle.Oracle(W.metric(W.EUCLID), wl["scene"])
+    rng = np.random.default_rng(12)
+    n_clear = 0
+    for _ in range(200):
+        q = rng.uniform(-2.5, 2.5, 3)
+        v = rng.normal(size=3)
+        v /= np.linalg.norm(v)
+        T = rng.uniform(0.5, 4.0)
+        z, ok = orc.shoot(q, v, T, 0.01)
+        assert ok
+        assert np.allclose(z[:3], q + T * v, atol=1e-12) and np.allclose(z[3:], v, atol=1e-14)
+        t, oid = exact.line_hits(q, v[None, :], wl["scene"], T)
+        inside = any(np.linalg.norm(q - s[:3]) < s[3] for s in wl["scene"]["spheres"])
+        if inside:
+            continue
+        clear = orc.geodesic_clear(q, v, T, 0.01, 0.0)
+        n_clear += clear
+        assert clear == (oid[0] < 0), (q, v, T, t, oid)
+    assert 20 < n_clear < 190
+
+
+def test_shoot_matches_the_trajectory():
+    """Shooting over a whole number of steps is the trajectory itself."""
+    wl = W.get("bumps16_1080p")
+    orc = oracle.Oracle(wl["metric"], wl["scene"])
+    z0 = np.array([0.3, -0.2, -1.5, 0.1, 0.05, 0.9])
+    z0[3:] /= np.sqrt(z0[3:] @ orc.metric_tensor(z0[:3]) @ z0[3:])
+    traj = orc.trajectory(W.rule(W.RK4, h=0.01, max_steps=300), z0, 300)
+    z, ok = orc.shoot(z0[:3], z0[3:], float(np.float32(0.01)) * 300, float(np.float32(0.01)))
+    assert ok and np.allclose(z, traj[-1], atol=1e-12)

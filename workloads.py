@@ -320,6 +320,9 @@ WORKLOADS = {
     "euler_vs_rk4_1080p": lambda **kw: bumps16_1080p(kind=EULER, **kw),
     "twist_4k": twist_4k,
     "deform16_1080p": deform16_1080p,
+    "illum_1080p": lambda **kw: dict(bumps16_1080p(**kw), name="illum_1080p",
+                                     light=dict(pos=(2.5, 3.5, -3.0), h=0.01, tol=1e-4, max_iters=16,
+                                                max_steps=4000)),
     "abumps16_1080p": abumps16_1080p,
     "quadric_1080p": quadric_1080p,
     "adjoint_64x512": adjoint_64x512,
