@@ -302,8 +302,11 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
  *            the cosine between v and the metric normal g^-1 grad F of the
  *            surface F = 0, both measured in g at q;
  *   status = 1 lit, 0 the geodesic is blocked, 2 the surface faces away
- *            (cosine <= 0), -1 no geodesic found within max_iters (or a
- *            shot overran max_steps), -3 the pixel did not hit;
+ *            (cosine <= 0), -1 no geodesic found: not within max_iters,
+ *            Newton stalled (from the fifth iteration on, a residual above
+ *            half the previous one), the length grew past four times the
+ *            straight segment's length in g at q plus one, or a shot
+ *            overran max_steps; -3 the pixel did not hit;
  *   dir    = v (optional), len = T (optional).
  * Several geodesics may join q and L; the one found is the one reached
  * from the straight segment.  The paper describes this illumination but

@@ -83,6 +83,8 @@ struct rt_ctx {
     size_t grp_w_bytes = 0;
     void *d_xbuf = nullptr;            // crossing queues, sized for xbuf_cap rays
     int64_t xbuf_cap = 0;
+    void *d_ibuf = nullptr;            // illumination workspace, sized for ibuf_cap pixels
+    int64_t ibuf_cap = 0;
 };
 
 static rt_status fail(rt_ctx *c, rt_status s, const std::string &msg) {
@@ -171,6 +173,7 @@ void rt_destroy(rt_ctx *c) {
         hipFree(c->d_surr);
         hipFree(c->d_surr_sb);
         hipFree(c->d_xbuf);
+        hipFree(c->d_ibuf);
         hipFree(c->d_grp_ctl);
         hipFree(c->d_grp_w);
         for (hipEvent_t e : c->ev) hipEventDestroy(e);
@@ -906,6 +909,25 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     a.dir = out->dir;
     a.len = out->len;
     const int64_t n = (int64_t)cam->width * cam->height * c->n_sets;
+    // workspace: Newton state (4 floats), two pixel lists, the list counters
+    if (c->ibuf_cap < n) {
+        rt_status st = sync_last(c);
+        if (st != RT_OK) return st;
+        hipFree(c->d_ibuf);
+        c->d_ibuf = nullptr;
+        c->ibuf_cap = 0;
+        e = hipMalloc(&c->d_ibuf, (size_t)n * 24 + 65 * sizeof(int) + 256);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (illumination workspace)");
+        c->ibuf_cap = n;
+    }
+    char *ib = (char *)c->d_ibuf;
+    a.w_al = (float *)ib;
+    a.w_be = (float *)(ib + (size_t)n * 4);
+    a.w_T = (float *)(ib + (size_t)n * 8);
+    a.w_F = (float *)(ib + (size_t)n * 12);
+    a.list[0] = (int *)(ib + (size_t)n * 16);
+    a.list[1] = (int *)(ib + (size_t)n * 20);
+    a.ctr = (int *)(ib + (size_t)n * 24);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)c->n_cu * 8));
     hipStream_t s = (hipStream_t)stream;
     e = rti::launch_illum(a, c->dd, grid, s);

@@ -158,10 +158,26 @@ __device__ __forceinline__ void bump_at(const float4 *__restrict__ B, int b, flo
 // per evaluation keeps the emptiness test a scalar branch instead of a lane
 // mask carried across the stages of a step (the compiler rejects the copy,
 // at build time, for a mask it cannot keep in scalar registers).
-template <bool COUNT = false, bool SREG = false>
+// WAVE: lanes of a wave walk a common mask, and a bump that no active lane
+// has inside its cut is skipped by the whole wave (its terms are zero).
+template <bool COUNT = false, bool SREG = false, bool WAVE = false>
 __device__ __forceinline__ V3<float> graph_accel_f32(const float4 *__restrict__ B, uint64_t mask, V3<float> p,
                                                      V3<float> y, unsigned *n_in = nullptr) {
     if constexpr (SREG) __asm__("" : "+s"(mask));
+    if constexpr (WAVE) {
+        GraphAccum A{0.f, 0.f, 0.f, 0.f};
+        const float yy = dot(y, y);
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= ~(1ull << b);
+            float4 b0, b1;
+            bump_at(B, b, b0, b1);
+            const float dx = p.x - b0.x, dy = p.y - b0.y, dz = p.z - b0.z;
+            if (ballot(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= b1.z) == 0) continue;
+            graph_bump_f32(b0, b1, p, y, yy, A);
+        }
+        return graph_finish(A);
+    }
     if (!mask) return mk(0.f, 0.f, 0.f);
     GraphAccum A;
     float yy = dot(y, y);
@@ -211,7 +227,7 @@ __device__ __forceinline__ ABump<double> abump_at(const double *__restrict__ B, 
     return {mk(q[0], q[1], q[2]), mk(q[4], q[5], q[6]), q[3], q[7]};
 }
 
-template <class T, bool COUNT = false, class PB>
+template <class T, bool COUNT = false, bool WAVE = false, class PB>
 __device__ __forceinline__ V3<T> graph_aniso_accel(PB B, uint64_t mask, V3<T> p, V3<T> y, unsigned *n_in = nullptr) {
     T gx = T(0), gy = T(0), gz = T(0), q = T(0);
     unsigned n = 0;
@@ -222,6 +238,7 @@ __device__ __forceinline__ V3<T> graph_aniso_accel(PB B, uint64_t mask, V3<T> p,
         const V3<T> d = mk(p.x - P.c.x, p.y - P.c.y, p.z - P.c.z);
         const V3<T> Sd = mk(P.s.x * d.x, P.s.y * d.y, P.s.z * d.z);
         const T r2 = dot(d, Sd);
+        if (WAVE && ballot(r2 <= P.cut2) == 0) continue;
         const T w = r2 <= P.cut2 ? P.a * exp2_(T(-0.5) * log2e_<T>() * r2) : T(0);
         if (COUNT) n += r2 <= P.cut2 ? 1u : 0u;
         gx -= w * Sd.x;

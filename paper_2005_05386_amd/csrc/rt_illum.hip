@@ -126,103 +126,196 @@ __device__ __forceinline__ bool reaches(Acc &acc, V3<float> q, V3<float> v, floa
     return true;
 }
 
+// Per-pixel frame about the straight direction to the light and the
+// direction for the angles (al, be), normalised to g-unit at q.
+struct Frame {
+    V3<float> e0, e1, e2;
+};
+__device__ __forceinline__ Frame light_frame(V3<float> q, V3<float> L) {
+    const V3<float> dl = L - q;
+    Frame f;
+    f.e0 = rsqrt_(dot(dl, dl)) * dl;
+    const V3<float> t0 = fabsf(f.e0.x) < 0.9f ? mk(1.f, 0.f, 0.f) : mk(0.f, 1.f, 0.f);
+    f.e1 = axpy(-dot(t0, f.e0), f.e0, t0);
+    f.e1 = rsqrt_(dot(f.e1, f.e1)) * f.e1;
+    f.e2 = mk(f.e0.y * f.e1.z - f.e0.z * f.e1.y, f.e0.z * f.e1.x - f.e0.x * f.e1.z, f.e0.x * f.e1.y - f.e0.y * f.e1.x);
+    return f;
+}
+
+// Everything a lane needs for one pixel.
+template <int KIND> struct Pixel {
+    const float4 *Bs;
+    V3<float> q;
+    Frame F;
+    __device__ __forceinline__ float gdd(const rti::IllumArgs &A, V3<float> d) const {
+        return metric_gdd<KIND>(Bs, A.n_bumps, A.twist_amp, A.twist_theta0, q, d);
+    }
+    __device__ __forceinline__ V3<float> dir(const rti::IllumArgs &A, float al, float be) const {
+        const V3<float> u = axpy(be, F.e2, axpy(al, F.e1, F.e0));
+        return rsqrt_(gdd(A, u)) * u;
+    }
+};
 template <int KIND>
-__global__ __launch_bounds__(256) void k_illum(rti::IllumArgs A, const float4 *__restrict__ BF,
-                                               const float4 *__restrict__ SPH, const float4 *__restrict__ PLN,
-                                               const float *__restrict__ TOR) {
-    const int64_t n = (int64_t)A.n_sets * A.width * A.height;
-    const int HW = A.width * A.height;
-    const int stride = KIND == KIND_DEFORM ? 4 : 2;
-    const uint64_t all = A.n_bumps >= 64 ? ~0ull : ((1ull << A.n_bumps) - 1ull);
-    const V3<float> L = mk(A.light[0], A.light[1], A.light[2]);
-    for (int64_t pix = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pix < n;
-         pix += (int64_t)gridDim.x * blockDim.x) {
-        const int obj = A.id[pix];
-        int status = -3;
-        float shade = 0.f, T = 0.f;
-        V3<float> v = mk(0.f, 0.f, 0.f);
-        if (obj >= 0) {
-            const int set = (int)(pix / HW);
-            const float4 *__restrict__ Bs = BF + (int64_t)set * A.n_bumps * stride;
-            Acc32<KIND, false> acc{Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
-            const V3<float> q = mk(A.hit[3 * pix], A.hit[3 * pix + 1], A.hit[3 * pix + 2]);
-            auto gdd = [&](V3<float> d) { return metric_gdd<KIND>(Bs, A.n_bumps, A.twist_amp, A.twist_theta0, q, d); };
-            // orthonormal frame about the straight direction to the light
-            const V3<float> dl = L - q;
-            const V3<float> e0 = rsqrt_(dot(dl, dl)) * dl;
-            const V3<float> t0 = fabsf(e0.x) < 0.9f ? mk(1.f, 0.f, 0.f) : mk(0.f, 1.f, 0.f);
-            V3<float> e1 = axpy(-dot(t0, e0), e0, t0);
-            e1 = rsqrt_(dot(e1, e1)) * e1;
-            const V3<float> e2 = mk(e0.y * e1.z - e0.z * e1.y, e0.z * e1.x - e0.x * e1.z, e0.x * e1.y - e0.y * e1.x);
-            auto dir = [&](float al, float be) {
-                const V3<float> u = axpy(be, e2, axpy(al, e1, e0));
-                return rsqrt_(gdd(u)) * u;
-            };
-            float al = 0.f, be = 0.f;
-            T = sqrtf(gdd(dl));
-            bool conv = false;
-            const float eps = 1e-3f;
-            for (int it = 0; it < A.max_iters; ++it) {
-                v = dir(al, be);
-                V3<float> X, Y, Xa, Xb, Ya, Yb;
-                if (!shoot(acc, q, v, T, A.h, A.max_steps, X, Y)) break;
-                const V3<float> F = X - L;
-                if (fmaxf(fabsf(F.x), fmaxf(fabsf(F.y), fabsf(F.z))) < A.tol) {
-                    conv = true;
-                    break;
-                }
-                if (!shoot(acc, q, dir(al + eps, be), T, A.h, A.max_steps, Xa, Ya)) break;
-                if (!shoot(acc, q, dir(al, be + eps), T, A.h, A.max_steps, Xb, Yb)) break;
-                // Newton step on (al, be, T): columns dX/dal, dX/dbe, dX/dT = Y
-                const V3<float> ca = (1.f / eps) * (Xa - X), cb = (1.f / eps) * (Xb - X);
-                const float M[9] = {ca.x, cb.x, Y.x, ca.y, cb.y, Y.y, ca.z, cb.z, Y.z};
-                const float c0 = M[4] * M[8] - M[5] * M[7], c1 = M[2] * M[7] - M[1] * M[8], c2 = M[1] * M[5] - M[2] * M[4];
-                const float c3 = M[5] * M[6] - M[3] * M[8], c4 = M[0] * M[8] - M[2] * M[6], c5 = M[2] * M[3] - M[0] * M[5];
-                const float c6 = M[3] * M[7] - M[4] * M[6], c7 = M[1] * M[6] - M[0] * M[7], c8 = M[0] * M[4] - M[1] * M[3];
-                const float det = M[0] * c0 + M[1] * c3 + M[2] * c6;
-                if (!(fabsf(det) > 1e-20f)) break;
-                const float idet = -1.f / det;
-                float da = idet * (c0 * F.x + c1 * F.y + c2 * F.z);
-                float db = idet * (c3 * F.x + c4 * F.y + c5 * F.z);
-                float dT = idet * (c6 * F.x + c7 * F.y + c8 * F.z);
-                // damping: at most 0.3 in the angles and half the length per step
-                const float sa = fmaxf(fabsf(da), fabsf(db)) > 0.3f ? 0.3f / fmaxf(fabsf(da), fabsf(db)) : 1.f;
-                const float sT = fabsf(dT) > 0.5f * T ? 0.5f * T / fabsf(dT) : 1.f;
-                const float sc = fminf(sa, sT);
-                al += sc * da;
-                be += sc * db;
-                T += sc * dT;
+__device__ __forceinline__ Pixel<KIND> pixel(const rti::IllumArgs &A, const float4 *__restrict__ BF, int pix) {
+    const int set = pix / (A.width * A.height);
+    Pixel<KIND> P;
+    P.Bs = BF + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
+    P.q = mk(A.hit[3 * pix], A.hit[3 * pix + 1], A.hit[3 * pix + 2]);
+    P.F = light_frame(P.q, mk(A.light[0], A.light[1], A.light[2]));
+    return P;
+}
+__device__ __forceinline__ uint64_t all_bumps(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+// Wave-aggregated append of pix to list (count at *ctr).
+__device__ __forceinline__ void append(int *list, int *ctr, int pix, bool take) {
+    const uint64_t m = ballot(take);
+    if (!m) return;
+    const int lane = lane_id();
+    const int leader = __builtin_ctzll(m);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(ctr, __popcll(m));
+    base = __shfl(base, leader);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = pix;
+}
+
+// Status codes of the API; 3 marks a converged pixel awaiting the finish.
+enum { ST_LIT = 1, ST_BLOCKED = 0, ST_AWAY = 2, ST_NONE = -1, ST_NOHIT = -3, ST_CONV = 3 };
+
+// Initial state: pixels that hit start from the straight segment.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_illum_init(rti::IllumArgs A, const float4 *__restrict__ BF) {
+    const int n = A.n_sets * A.width * A.height;
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int pix = base + threadIdx.x;
+        const bool hit = pix < n && A.id[pix] >= 0;
+        if (pix < n) {
+            float T = 0.f;
+            if (hit) {
+                const Pixel<KIND> P = pixel<KIND>(A, BF, pix);
+                const V3<float> L = mk(A.light[0], A.light[1], A.light[2]);
+                T = sqrtf(P.gdd(A, L - P.q));
             }
-            if (!conv) {
-                status = -1;
-            } else {
-                // Lambert term in the metric: grad F . v / sqrt(grad F^T g^-1 grad F)
-                const V3<float> gF = obj_grad(obj, q, A.n_spheres, A.n_planes, SPH, PLN, TOR);
-                float G[9];
-                const V3<float> E[3] = {mk(1.f, 0.f, 0.f), mk(0.f, 1.f, 0.f), mk(0.f, 0.f, 1.f)};
-                for (int i = 0; i < 3; ++i) G[4 * i] = gdd(E[i]);
-                for (int i = 0; i < 3; ++i)
-                    for (int j = i + 1; j < 3; ++j)
-                        G[3 * i + j] = G[3 * j + i] = 0.5f * (gdd(E[i] + E[j]) - G[4 * i] - G[4 * j]);
-                const float a0 = G[4] * G[8] - G[5] * G[7], a1 = G[2] * G[7] - G[1] * G[8], a2 = G[1] * G[5] - G[2] * G[4];
-                const float a4 = G[0] * G[8] - G[2] * G[6], a5 = G[2] * G[3] - G[0] * G[5], a8 = G[0] * G[4] - G[1] * G[3];
-                const float gdet = G[0] * a0 + G[1] * (G[5] * G[6] - G[3] * G[8]) + G[2] * (G[3] * G[7] - G[4] * G[6]);
-                // grad F^T adj(G) grad F / det (adj(G) symmetric for symmetric G)
-                const float qf = (gF.x * (a0 * gF.x + a1 * gF.y + a2 * gF.z) + gF.y * (a1 * gF.x + a4 * gF.y + a5 * gF.z) +
-                                  gF.z * (a2 * gF.x + a5 * gF.y + a8 * gF.z)) / gdet;
-                const float c = dot(gF, v) * rsqrt_(qf);
-                if (!(c > 0.f)) {
-                    status = 2;
-                } else if (reaches(acc, q, v, T, A.h, 1e-3f, A, SPH, PLN, TOR)) {
-                    status = 1;
-                    shade = fminf(c, 1.f);
-                } else {
-                    status = 0;
+            A.w_al[pix] = 0.f;
+            A.w_be[pix] = 0.f;
+            A.w_T[pix] = T;
+            A.w_F[pix] = __builtin_huge_valf();
+            A.status[pix] = hit ? ST_NONE : ST_NOHIT;
+            A.shade[pix] = 0.f;
+        }
+        append(A.list[0], A.ctr + 0, pix, hit);
+    }
+}
+
+// One Newton iteration for every pixel of list[it & 1]: shoot; converged
+// pixels are marked, the others take a damped step and move to the next list.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const float4 *__restrict__ BF, int it) {
+    const int *in = A.list[it & 1];
+    int *out = A.list[(it + 1) & 1];
+    const int n_in = A.ctr[it];
+    const uint64_t all = all_bumps(A.n_bumps);
+    const V3<float> L = mk(A.light[0], A.light[1], A.light[2]);
+    const float eps = 1e-3f;
+    for (int base = blockIdx.x * blockDim.x; base < n_in; base += gridDim.x * blockDim.x) {
+        const int k = base + threadIdx.x;
+        bool again = false;
+        int pix = 0;
+        if (k < n_in) {
+            pix = in[k];
+            const Pixel<KIND> P = pixel<KIND>(A, BF, pix);
+            Acc32<KIND, false, false, true> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
+            float al = A.w_al[pix], be = A.w_be[pix], T = A.w_T[pix];
+            V3<float> X, Y, Xa, Xb, Ya, Yb;
+            if (shoot(acc, P.q, P.dir(A, al, be), T, A.h, A.max_steps, X, Y)) {
+                const V3<float> F = X - L;
+                const float fn = fmaxf(fabsf(F.x), fmaxf(fabsf(F.y), fabsf(F.z)));
+                // give up when Newton stalls (after the first, damped, iterations)
+                const bool stalled = it >= 4 && fn > 0.5f * A.w_F[pix];
+                A.w_F[pix] = fn;
+                if (fn < A.tol) {
+                    A.status[pix] = ST_CONV;
+                } else if (!stalled && shoot(acc, P.q, P.dir(A, al + eps, be), T, A.h, A.max_steps, Xa, Ya) &&
+                           shoot(acc, P.q, P.dir(A, al, be + eps), T, A.h, A.max_steps, Xb, Yb)) {
+                    // Newton step on (al, be, T): columns dX/dal, dX/dbe, dX/dT = Y
+                    const V3<float> ca = (1.f / eps) * (Xa - X), cb = (1.f / eps) * (Xb - X);
+                    const float M[9] = {ca.x, cb.x, Y.x, ca.y, cb.y, Y.y, ca.z, cb.z, Y.z};
+                    const float c0 = M[4] * M[8] - M[5] * M[7], c1 = M[2] * M[7] - M[1] * M[8],
+                                c2 = M[1] * M[5] - M[2] * M[4];
+                    const float c3 = M[5] * M[6] - M[3] * M[8], c4 = M[0] * M[8] - M[2] * M[6],
+                                c5 = M[2] * M[3] - M[0] * M[5];
+                    const float c6 = M[3] * M[7] - M[4] * M[6], c7 = M[1] * M[6] - M[0] * M[7],
+                                c8 = M[0] * M[4] - M[1] * M[3];
+                    const float det = M[0] * c0 + M[1] * c3 + M[2] * c6;
+                    if (fabsf(det) > 1e-20f) {
+                        const float idet = -1.f / det;
+                        const float da = idet * (c0 * F.x + c1 * F.y + c2 * F.z);
+                        const float db = idet * (c3 * F.x + c4 * F.y + c5 * F.z);
+                        const float dT = idet * (c6 * F.x + c7 * F.y + c8 * F.z);
+                        // damping: at most 0.3 in the angles and half the length per step
+                        const float m = fmaxf(fabsf(da), fabsf(db));
+                        const float sa = m > 0.3f ? 0.3f / m : 1.f;
+                        const float sT = fabsf(dT) > 0.5f * T ? 0.5f * T / fabsf(dT) : 1.f;
+                        const float sc = fminf(sa, sT);
+                        A.w_al[pix] = al + sc * da;
+                        A.w_be[pix] = be + sc * db;
+                        A.w_T[pix] = T + sc * dT;
+                        // geodesics much longer than the straight segment are not pursued
+                        again = T + sc * dT <= 4.f * sqrtf(P.gdd(A, L - P.q)) + 1.f;
+                    }
                 }
             }
         }
-        A.shade[pix] = shade;
+        append(out, A.ctr + it + 1, pix, again);
+    }
+}
+
+// Lambert term and visibility for the converged pixels; every hit pixel
+// gets its direction and length.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_illum_finish(rti::IllumArgs A, const float4 *__restrict__ BF,
+                                                      const float4 *__restrict__ SPH, const float4 *__restrict__ PLN,
+                                                      const float *__restrict__ TOR) {
+    const int n = A.n_sets * A.width * A.height;
+    const uint64_t all = all_bumps(A.n_bumps);
+    for (int pix = blockIdx.x * blockDim.x + threadIdx.x; pix < n; pix += gridDim.x * blockDim.x) {
+        int status = A.status[pix];
+        if (status == ST_NOHIT) {
+            if (A.dir) A.dir[3 * pix] = A.dir[3 * pix + 1] = A.dir[3 * pix + 2] = 0.f;
+            if (A.len) A.len[pix] = 0.f;
+            continue;
+        }
+        const Pixel<KIND> P = pixel<KIND>(A, BF, pix);
+        const float T = A.w_T[pix];
+        const V3<float> v = P.dir(A, A.w_al[pix], A.w_be[pix]);
+        float shade = 0.f;
+        if (status == ST_CONV) {
+            // Lambert term in the metric: grad F . v / sqrt(grad F^T g^-1 grad F)
+            const V3<float> gF = obj_grad(A.id[pix], P.q, A.n_spheres, A.n_planes, SPH, PLN, TOR);
+            float G[9];
+            const V3<float> E[3] = {mk(1.f, 0.f, 0.f), mk(0.f, 1.f, 0.f), mk(0.f, 0.f, 1.f)};
+            for (int i = 0; i < 3; ++i) G[4 * i] = P.gdd(A, E[i]);
+            for (int i = 0; i < 3; ++i)
+                for (int j = i + 1; j < 3; ++j)
+                    G[3 * i + j] = G[3 * j + i] = 0.5f * (P.gdd(A, E[i] + E[j]) - G[4 * i] - G[4 * j]);
+            const float a0 = G[4] * G[8] - G[5] * G[7], a1 = G[2] * G[7] - G[1] * G[8], a2 = G[1] * G[5] - G[2] * G[4];
+            const float a4 = G[0] * G[8] - G[2] * G[6], a5 = G[2] * G[3] - G[0] * G[5], a8 = G[0] * G[4] - G[1] * G[3];
+            const float gdet = G[0] * a0 + G[1] * (G[5] * G[6] - G[3] * G[8]) + G[2] * (G[3] * G[7] - G[4] * G[6]);
+            // grad F^T adj(G) grad F / det (adj(G) is symmetric for symmetric G)
+            const float qf = (gF.x * (a0 * gF.x + a1 * gF.y + a2 * gF.z) + gF.y * (a1 * gF.x + a4 * gF.y + a5 * gF.z) +
+                              gF.z * (a2 * gF.x + a5 * gF.y + a8 * gF.z)) / gdet;
+            const float c = dot(gF, v) * rsqrt_(qf);
+            Acc32<KIND, false, false, true> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
+            if (!(c > 0.f)) {
+                status = ST_AWAY;
+            } else if (reaches(acc, P.q, v, T, A.h, 1e-3f, A, SPH, PLN, TOR)) {
+                status = ST_LIT;
+                shade = fminf(c, 1.f);
+            } else {
+                status = ST_BLOCKED;
+            }
+        }
         A.status[pix] = status;
+        A.shade[pix] = shade;
         if (A.dir) {
             A.dir[3 * pix] = v.x;
             A.dir[3 * pix + 1] = v.y;
@@ -232,15 +325,28 @@ __global__ __launch_bounds__(256) void k_illum(rti::IllumArgs A, const float4 *_
     }
 }
 
+__global__ void k_illum_zero(int *ctr, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0;
+}
+
+template <int KIND>
+hipError_t illum_kind(const rti::IllumArgs &a, const rti::DeviceData &d, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_illum_zero, dim3(1), dim3(256), 0, s, a.ctr, a.max_iters + 1);
+    hipLaunchKernelGGL((k_illum_init<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f);
+    for (int it = 0; it < a.max_iters; ++it)
+        hipLaunchKernelGGL((k_illum_iter<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+    hipLaunchKernelGGL((k_illum_finish<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f, d.tor_f);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 namespace rti {
 
 hipError_t launch_illum(const IllumArgs &a, const DeviceData &d, int grid, hipStream_t s) {
     switch (a.kind) {
-#define RT_ILLUM(K)                                                                                             \
-    case K: hipLaunchKernelGGL((k_illum<K>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f, d.tor_f); \
-        break;
+#define RT_ILLUM(K) \
+    case K: return illum_kind<K>(a, d, grid, s);
         RT_ILLUM(KIND_EUCLID)
         RT_ILLUM(KIND_GRAPH)
         RT_ILLUM(KIND_TWIST)
@@ -251,7 +357,6 @@ hipError_t launch_illum(const IllumArgs &a, const DeviceData &d, int grid, hipSt
 #undef RT_ILLUM
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace rti

@@ -169,6 +169,10 @@ struct IllumArgs {
     int max_iters, max_steps;
     float *shade, *dir, *len;
     int *status;
+    // workspace: Newton state per pixel, two pixel lists, one counter per iteration
+    float *w_al, *w_be, *w_T, *w_F;  // angles, length, last residual
+    int *list[2];
+    int *ctr;  // max_iters + 1 words
 };
 hipError_t launch_illum(const IllumArgs &a, const DeviceData &d, int grid, hipStream_t s);
 // ------------------------------------------------------------- MLP (BF16)

@@ -161,7 +161,9 @@ __device__ __forceinline__ bool finite6(V3<float> a, V3<float> b) {
 }
 
 // SREG: the bump mask is wave-uniform and held in scalar registers.
-template <int KIND, bool COUNT, bool SREG = false> struct Acc32 {
+// WAVE: the lanes of a wave share the mask but not their region; a bump or
+// deformation none of them is inside is skipped by the wave.
+template <int KIND, bool COUNT, bool SREG = false, bool WAVE = false> struct Acc32 {
     const float4 *__restrict__ B;
     uint64_t mask;
     float amp, th0;
@@ -169,7 +171,7 @@ template <int KIND, bool COUNT, bool SREG = false> struct Acc32 {
     __device__ __forceinline__ bool operator()(V3<float> p, V3<float> y, V3<float> &a) const {
         if (COUNT) *n_eval += 1;
         if constexpr (KIND == KIND_GRAPH) {
-            a = graph_accel_f32<COUNT, SREG>(B, mask, p, y, n_bump);
+            a = graph_accel_f32<COUNT, SREG, WAVE>(B, mask, p, y, n_bump);
             return true;
         } else if constexpr (KIND == KIND_TWIST) {
             return twist_accel<float>(amp, th0, p, y, a);
@@ -179,7 +181,7 @@ template <int KIND, bool COUNT, bool SREG = false> struct Acc32 {
         } else if constexpr (KIND == KIND_DEFORM) {
             return deform_accel<float, COUNT>(B, mask, p, y, a, n_bump);
         } else if constexpr (KIND == KIND_GANISO) {
-            a = graph_aniso_accel<float, COUNT>(B, mask, p, y, n_bump);
+            a = graph_aniso_accel<float, COUNT, WAVE>(B, mask, p, y, n_bump);
             return true;
         } else if constexpr (KIND == KIND_GQUAD) {
             const float4 q = B[0];

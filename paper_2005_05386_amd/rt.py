@@ -292,6 +292,15 @@ class Tracer:
                                        C.c_void_p(stream.cuda_stream)))
         return out
 
+    def illuminate_raw(self, camera, hit_ptr, id_ptr, light, shade_ptr, status_ptr, stream_handle=0):
+        """rt_illuminate with raw device pointers (validation tests)."""
+        o = rt_outputs(hit_ptr or None, None, id_ptr or None, None, None)
+        L = rt_light((C.c_float * 3)(*[float(v) for v in light["pos"]]), float(light.get("h", 0.01)),
+                     float(light.get("tol", 1e-4)), int(light.get("max_iters", 16)), int(light.get("max_steps", 4000)))
+        sh = rt_shading(shade_ptr or None, status_ptr or None, None, None)
+        self._check(_lib.rt_illuminate(self._h, C.byref(camera_struct(camera)), C.byref(o), C.byref(L), C.byref(sh),
+                                       C.c_void_p(stream_handle)))
+
     def trace_raw(self, camera, rule, max_steps, out_ptrs, stream_handle):
         """Enqueue with raw device pointers (hit, t, id, dir, steps-or-0)."""
         o = rt_outputs(*[p if p else None for p in out_ptrs])

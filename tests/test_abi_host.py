@@ -240,3 +240,26 @@ def test_surrogate_train_validates():
     bad = np.array([-0.1, 0.2], np.float32)
     assert call(scale=bad.ctypes.data) == rt.RT_EINVAL
     assert call() == rt.RT_ESTATE
+
+
+def test_illuminate_validates():
+    rt = _rt()
+    tr = rt.Tracer(-1)
+    wl = W.get("single_bump_64")
+    light = dict(pos=(1.0, 2.0, -1.0))
+    with pytest.raises(rt.RtError) as e:  # no metric yet
+        tr.illuminate_raw(wl["camera"], 16, 16, light, 16, 16)
+    assert e.value.status == rt.RT_ESTATE
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    for bad, ptrs in [(dict(light, h=0.5), (16, 16, 16, 16)), (dict(light, h=0.0), (16, 16, 16, 16)),
+                      (dict(light, tol=-1.0), (16, 16, 16, 16)), (dict(light, max_iters=0), (16, 16, 16, 16)),
+                      (dict(light, pos=(np.nan, 0.0, 0.0)), (16, 16, 16, 16)), (light, (0, 16, 16, 16)),
+                      (light, (16, 16, 0, 16))]:
+        with pytest.raises(rt.RtError) as e:
+            tr.illuminate_raw(wl["camera"], ptrs[0], ptrs[1], bad, ptrs[2], ptrs[3])
+        assert e.value.status == rt.RT_EINVAL, bad
+    # every argument valid: a host-only context stops after validation
+    with pytest.raises(rt.RtError) as e:
+        tr.illuminate_raw(wl["camera"], 16, 16, light, 16, 16)
+    assert e.value.status == rt.RT_ESTATE
