@@ -330,3 +330,21 @@ def test_aniso_deterministic_across_culling(rt):
     g = gpu_trace(rt, wl, rule=dict(wl["rule"], cull_every=4, pass_steps=64))
     for k in ("hit", "t", "id", "dir", "steps"):
         assert np.array_equal(ref[k], g[k]), k
+
+
+@pytest.mark.parametrize("name,kind", [("deform16_1080p", W.RK45), ("abumps16_1080p", W.RK45),
+                                       ("quadric_1080p", W.EULER), ("twist_4k", W.EULER)])
+def test_other_integrators_on_new_metrics(rt, name, kind):
+    """DP5(4) and the paper's Euler march on the newer metric kinds, small
+    frames, against the oracle running the same discrete method."""
+    say("%s with step kind %d, 64x36" % (name, kind))
+    wl = W.with_size(W.get(name), 64, 36)
+    if kind == W.RK45:
+        rule = W.rule(W.RK45, h=0.005, max_steps=4000, t_max=20.0, rtol=1e-6, atol=1e-6, h_min=1e-6, h_max=0.02,
+                      pass_steps=4000)
+    else:
+        rule = W.rule(W.EULER, h=0.005, max_steps=4000, t_max=20.0, pass_steps=4000)
+    g = gpu_trace(rt, wl, rule=rule)
+    rep = compare(g, oracle_trace(wl, rule=rule))
+    say(rep)
+    assert_parity(rep)
