@@ -16,8 +16,9 @@
 // (bf16), arbitrary strides so that transposed operands need no copies.
 // A 256-thread workgroup computes a 64x64 tile of C: the 64x32 A slice and
 // 32x64 B slice of each K step are staged in LDS (zero-filled outside the
-// matrix), then each wave accumulates a 32x32 block with four
-// v_mfma_f32_16x16x32_bf16 per step.  Lane l of a 16x16x32 MFMA supplies
+// matrix; the next slice is read into registers during the products), then
+// each wave accumulates a 32x32 block with four v_mfma_f32_16x16x32_bf16
+// per step.  Lane l of a 16x16x32 MFMA supplies
 // A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. +7][l%16] and receives
 // D[4(l/16) + j][l%16], j = 0..3.
 #include <hip/hip_runtime.h>
@@ -38,9 +39,67 @@ __device__ __forceinline__ float dsilu(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
+// Operand staging layouts of the backward GEMM: L_GEN reads element by
+// element through both strides (any shape); L_KC has unit stride along k
+// (16-byte loads of 8 consecutive k); L_MC has unit stride along the row
+// index m (or n for B): 16-byte loads of 8 consecutive rows at one k,
+// written transposed into LDS; L_MC4 is L_MC with four 4-byte loads for
+// operands whose group stride is only even.  The vector layouts need
+// 8 | M, N, K and the other stride, 8 | the group stride and 16-byte
+// aligned bases (2 | and 4-byte aligned for L_MC4).
+enum { L_GEN = 0, L_KC = 1, L_MC = 2, L_MC4 = 3 };
+
+// Stage a 64 x 32 (row, k) slice of X(row, k) = X[row*srow + k*sk] into
+// S[row][k]; rows >= R and k >= K are zero.
+template <int L>
+__device__ __forceinline__ void stage_load(const __bf16 *__restrict__ X, int64_t srow, int64_t sk, int r0, int R,
+                                           int k0, int K, int tid, bf16x8 &v) {
+    if constexpr (L == L_KC) {
+        const int r = r0 + (tid >> 2), k = k0 + (tid & 3) * 8;
+        if (r < R && k < K) {
+            v = *(const bf16x8 *)(X + (int64_t)r * srow + k);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.0f;
+        }
+    } else if constexpr (L == L_MC || L == L_MC4) {
+        const int k = k0 + (tid >> 3), r = r0 + (tid & 7) * 8;
+        if (r < R && k < K) {
+            if constexpr (L == L_MC) {
+                v = *(const bf16x8 *)(X + (int64_t)k * sk + r);
+            } else {
+                const uint32_t *w = (const uint32_t *)(X + (int64_t)k * sk + r);
+                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                const u32x4 u = {w[0], w[1], w[2], w[3]};
+                v = __builtin_bit_cast(bf16x8, u);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.0f;
+        }
+    } else {
+        const int r = r0 + (tid >> 2), kc = k0 + (tid & 3) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            v[e] = (r < R && kc + e < K) ? X[(int64_t)r * srow + (int64_t)(kc + e) * sk] : (__bf16)0.0f;
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void stage_store(__bf16 (*S)[40], int tid, const bf16x8 &v) {
+    if constexpr (L == L_MC || L == L_MC4) {
+        const int k = tid >> 3, r = (tid & 7) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) S[r + e][k] = v[e];
+    } else {
+        *(bf16x8 *)&S[tid >> 2][(tid & 3) * 8] = v;
+    }
+}
+
+template <int LA, int LB>
 __global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G) {
-    __shared__ __bf16 As[64][32 + 8];
-    __shared__ __bf16 Bs[64][32 + 8];  // transposed: Bs[n][k]
+    __shared__ __attribute__((aligned(16))) __bf16 As[64][32 + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[64][32 + 8];  // transposed: Bs[n][k]
     const int g = blockIdx.z;
     int M = G.M;
     int64_t row0 = 0;
@@ -59,29 +118,25 @@ __global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const __bf16 zero = (__bf16)0.0f;
+    // the next slice is loaded into registers while the current one is
+    // multiplied
+    bf16x8 va, vb;
+    stage_load<LA>(A, G.sam, G.sak, m0, M, 0, G.K, tid, va);
+    stage_load<LB>(B, G.sbn, G.sbk, n0, G.N, 0, G.K, tid, vb);
+    const int kq = (lane >> 4) * 8;
     for (int k0 = 0; k0 < G.K; k0 += 32) {
-        // stage: thread t loads row t/4 (A) / column t/4 (B), 8 k values
-        {
-            const int r = tid >> 2, kc = (tid & 3) * 8;
-            const int m = m0 + r, n = n0 + r;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = k0 + kc + i;
-                As[r][kc + i] = (m < M && k < G.K) ? A[(int64_t)m * G.sam + (int64_t)k * G.sak] : zero;
-                Bs[r][kc + i] = (n < G.N && k < G.K) ? B[(int64_t)k * G.sbk + (int64_t)n * G.sbn] : zero;
-            }
-        }
+        stage_store<LA>(As, tid, va);
+        stage_store<LB>(Bs, tid, vb);
         __syncthreads();
-        const int kq = (lane >> 4) * 8;
+        if (k0 + 32 < G.K) {
+            stage_load<LA>(A, G.sam, G.sak, m0, M, k0 + 32, G.K, tid, va);
+            stage_load<LB>(B, G.sbn, G.sbk, n0, G.N, k0 + 32, G.K, tid, vb);
+        }
         bf16x8 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                a[i][e] = As[wm + 16 * i + (lane & 15)][kq + e];
-                b[i][e] = Bs[wn + 16 * i + (lane & 15)][kq + e];
-            }
+            a[i] = *(const bf16x8 *)&As[wm + 16 * i + (lane & 15)][kq];
+            b[i] = *(const bf16x8 *)&Bs[wn + 16 * i + (lane & 15)][kq];
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -365,12 +420,13 @@ __global__ __launch_bounds__(256) void k_gemm_x3(const __bf16 *__restrict__ Hh, 
             }
 }
 
-// out[g][n] = sum_m X[g][m][n], fixed order: per block of 256 rows a
-// sequential partial, then partials summed in order.
+// out[g][n] = sum_m X[g][m][n], fixed order: per block of COLSUM_ROWS rows
+// a sequential partial, then partials summed in order.
+constexpr int COLSUM_ROWS = 64;
 __global__ void k_colsum_part(const float *__restrict__ X, int64_t xg, int rows, int N, float *__restrict__ part) {
     const int g = blockIdx.z, n = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
     if (n >= N) return;
-    const int r0 = c * 256, r1 = min(rows, r0 + 256);
+    const int r0 = c * COLSUM_ROWS, r1 = min(rows, r0 + COLSUM_ROWS);
     float s = 0.f;
     for (int r = r0; r < r1; ++r) s += X[g * xg + (int64_t)r * N + n];
     part[((int64_t)g * gridDim.y + c) * N + n] = s;
@@ -431,13 +487,31 @@ namespace rti {
 
 hipError_t launch_gemm(const GemmArgs &G, int groups, int max_rows, hipStream_t s) {
     dim3 grid((G.N + 63) / 64, (max_rows + 63) / 64, groups);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, G);
+    // vector staging when every 8-element run it loads lies inside the
+    // operand and starts on a 16-byte boundary
+    auto al = [](const void *p, int64_t a, int64_t b) {
+        return ((uintptr_t)p % 16 == 0) && a % 8 == 0 && b % 8 == 0;
+    };
+    const bool dims = !G.rows && G.M % 8 == 0 && G.N % 8 == 0 && G.K % 8 == 0;
+    const bool a_mc = dims && G.sam == 1 && al(G.A, G.a_g, G.sak);
+    const bool a_kc = dims && G.sak == 1 && al(G.A, G.a_g, G.sam);
+    const bool b_nc = dims && G.sbn == 1 && al(G.B, G.b_g, G.sbk);
+    const bool b_nc4 = dims && G.sbn == 1 && (uintptr_t)G.B % 4 == 0 && G.b_g % 2 == 0 && G.sbk % 8 == 0;
+    if (a_mc && b_nc)
+        hipLaunchKernelGGL((k_gemm<L_MC, L_MC>), grid, dim3(256), 0, s, G);
+    else if (a_kc && b_nc)
+        hipLaunchKernelGGL((k_gemm<L_KC, L_MC>), grid, dim3(256), 0, s, G);
+    else if (a_kc && b_nc4)
+        hipLaunchKernelGGL((k_gemm<L_KC, L_MC4>), grid, dim3(256), 0, s, G);
+    else
+        hipLaunchKernelGGL((k_gemm<L_GEN, L_GEN>), grid, dim3(256), 0, s, G);
     return hipGetLastError();
 }
 
 hipError_t launch_colsum(const float *X, int64_t xg, int rows, int N, int groups, float *part, float *out,
                          int64_t out_g, hipStream_t s) {
-    int nchunk = (rows + 255) / 256;
+    // part holds groups x nchunk x N floats
+    int nchunk = (rows + COLSUM_ROWS - 1) / COLSUM_ROWS;
     hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, nchunk, groups), dim3(64), 0, s, X, xg, rows, N, part);
     hipLaunchKernelGGL(k_colsum_final, dim3((N + 63) / 64, groups), dim3(64), 0, s, (const float *)part, nchunk, N,
                        out, out_g);
@@ -491,6 +565,8 @@ void mlp_work_carve(void *base, int n_nets, int batch, MlpWork &w) {
     w.dyb = (__bf16 *)take(nb * MLP_OUT * 2);
     for (int i = 0; i < 2; ++i) w.dzf[i] = (float *)take(nb * MLP_H * 4);
     for (int i = 0; i < 2; ++i) w.dzb[i] = (__bf16 *)take(nb * MLP_H * 2);
+    // partials: nch x 7 x 256 per network for the FP32 layers, and
+    // ceil(batch / 64) x 256 <= 4 nch x 256 for the column sums
     w.part = (float *)take((size_t)n_nets * nch * MLP_H * 7 * 4);
 }
 
