@@ -904,6 +904,16 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     a.tol = L->tol;
     a.max_iters = L->max_iters;
     a.max_steps = L->max_steps;
+    {
+        // culling windows of the shots, as for a trace with step h: a
+        // g-unit geodesic covers at most (K+1) h vmax of Euclidean length
+        // before the next window (no bound for the z-twist)
+        const double K1 = rti::ILLUM_CULL_EVERY + 1;
+        double m = K1 * L->h * (c->kind == RT_METRIC_PULLBACK_TWIST ? 1.05 : 1.0) * 1.02 + 1e-4;
+        if (c->kind == RT_METRIC_PULLBACK_DEFORM)
+            m = std::min(K1 * L->h * c->deform_vmax * 1.02, K1 * L->h * 1.02 + 2.0 * c->deform_disp) + 1e-4;
+        a.cull_margin = c->kind == RT_METRIC_PULLBACK_ZTWIST ? -1.0f : (float)m;
+    }
     a.shade = out->shade;
     a.status = out->status;
     a.dir = out->dir;

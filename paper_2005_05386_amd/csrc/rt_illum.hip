@@ -7,8 +7,9 @@
 //     method on two direction angles and T (finite-difference columns for
 //     the angles, the end velocity for T), starting from the straight
 //     segment;
-//   - marches that geodesic (RK4, each step's chord tested against every
-//     object, hits within 1e-3 of q ignored) to decide whether it reaches L;
+//   - marches that geodesic (RK4, each step's chord tested against the
+//     objects its culling window reaches, hits within 1e-3 of q ignored) to
+//     decide whether it reaches L;
 //   - takes the Lambert term cos = g(N, v) / |N|_g with N the metric normal
 //     of the surface, g^-1 grad F, so that g(N, v) = grad F . v and
 //     |N|_g^2 = grad F^T g^-1 grad F.
@@ -48,16 +49,54 @@ __device__ __forceinline__ V3<float> obj_grad(int id, V3<float> x, int ns, int n
     return rsqrt_(e * e + ax * ax) * g;
 }
 
+// Culling windows of the shots and the visibility march: every
+// ILLUM_CULL_EVERY steps a lane's window is the box of half-width
+// A.cull_margin about its position (the distance it can cover before the
+// next window, from the metric's speed bound); the bumps and objects that
+// some active lane's window reaches are OR-ed over the wave by ballots.
+// Isotropic and anisotropic graph bumps are culled this way; the other
+// kinds walk every record of the table and skip, wave by wave, a record no
+// lane is inside.
+template <int KIND> constexpr bool bump_cull = KIND == KIND_GRAPH || KIND == KIND_GANISO;
+template <int KIND> using IAcc = Acc32<KIND, false, false, !bump_cull<KIND>>;
+
+struct Box {
+    float lo[3], hi[3];
+};
+__device__ __forceinline__ Box lane_box(V3<float> p, float m) {
+    return {{p.x - m, p.y - m, p.z - m}, {p.x + m, p.y + m, p.z + m}};
+}
+
+template <int KIND>
+__device__ __forceinline__ uint64_t bump_window(const float4 *__restrict__ Bs, int n, const Box &w) {
+    uint64_t mask = 0;
+    for (int b = 0; b < n; ++b) {
+        const float4 b0 = Bs[2 * b], b1 = Bs[2 * b + 1];
+        bool need;
+        if constexpr (KIND == KIND_GRAPH) {
+            need = box_dist2(b0.x, b0.y, b0.z, w.lo, w.hi) <= b1.z;
+        } else {
+            const float rho = aniso_box_rho(b0, b1, w.lo, w.hi);
+            need = rho * rho <= b1.w * 1.00001f;
+        }
+        if (ballot(need)) mask |= 1ull << b;
+    }
+    return mask;
+}
+
 // Integrate the geodesic from (q, v) over arc length T: n = ceil(T / h)
 // RK4 steps, the last one shortened; two-float position.  Returns false on
 // a non-finite state or a step budget overrun.
-template <class Acc>
-__device__ __forceinline__ bool shoot(Acc &acc, V3<float> q, V3<float> v, float T, float h, int max_steps,
+template <int KIND>
+__device__ __forceinline__ bool shoot(IAcc<KIND> &acc, const rti::IllumArgs &A, V3<float> q, V3<float> v, float T,
                                       V3<float> &X, V3<float> &Y) {
+    const float h = A.h;
     const int n = max(1, (int)ceilf(T / h));
-    if (n > max_steps) return false;
+    if (n > A.max_steps) return false;
     V3<float> xh = q, xl = mk(0.f, 0.f, 0.f), y = v;
     for (int i = 0; i < n; ++i) {
+        if constexpr (bump_cull<KIND>)
+            if (i % rti::ILLUM_CULL_EVERY == 0) acc.mask = bump_window<KIND>(acc.B, A.n_bumps, lane_box(xh + xl, A.cull_margin));
         const float hs = i == n - 1 ? T - (float)(n - 1) * h : h;
         V3<float> dx, dv;
         if (!step_rk4<float>(acc, xh + xl, y, hs, dx, dv) || !finite6(dx, dv)) return false;
@@ -71,36 +110,78 @@ __device__ __forceinline__ bool shoot(Acc &acc, V3<float> q, V3<float> v, float 
     return true;
 }
 
-// March the same geodesic with the chord of every step tested against every
-// object; true when nothing is crossed between t = skip and t = T.
-template <class Acc>
-__device__ __forceinline__ bool reaches(Acc &acc, V3<float> q, V3<float> v, float T, float h, float skip,
+// March the same geodesic with the chord of every step tested against the
+// objects of the window; true when nothing is crossed between t = skip and
+// t = T.
+template <int KIND>
+__device__ __forceinline__ bool reaches(IAcc<KIND> &acc, V3<float> q, V3<float> v, float T, float skip,
                                         const rti::IllumArgs &A, const float4 *__restrict__ SPH,
                                         const float4 *__restrict__ PLN, const float *__restrict__ TOR) {
+    const float h = A.h;
     const int n = max(1, (int)ceilf(T / h));
+    const int no = A.n_planes + A.n_tori;
     V3<float> xh = q, xl = mk(0.f, 0.f, 0.f), y = v;
     float t = 0.f;
+    uint64_t sm[4] = {0ull, 0ull, 0ull, 0ull};
+    uint32_t om = 0;
     for (int i = 0; i < n; ++i) {
-        const float hs = i == n - 1 ? T - (float)(n - 1) * h : h;
-        V3<float> dx, dv;
-        if (!step_rk4<float>(acc, xh + xl, y, hs, dx, dv)) return false;
         const V3<float> p = xh + xl;
-        const float DD = dot(dx, dx);
-        float first = 2.f;
-        for (int k = 0; k < A.n_spheres; ++k) {
-            const float4 s = SPH[k];
-            const V3<float> o = mk((xh.x - s.x) + xl.x, (xh.y - s.y) + xl.y, (xh.z - s.z) + xl.z);
-            // both roots: a chord that starts on a sphere (s ~ 0) may still cross it later
-            const float B = dot(dx, o), C = fmaf(-s.w, s.w, dot(o, o));
-            const float disc = fmaf(B, B, -DD * C);
-            if (disc >= 0.f) {
-                const float qd = sqrt_(disc), inv = rcp_(DD);
-                const float s1 = (-B - qd) * inv, s2 = (-B + qd) * inv;
-                if (s1 >= 0.f && s1 <= 1.f && t + s1 * hs > skip) first = fminf(first, s1);
-                else if (s2 >= 0.f && s2 <= 1.f && t + s2 * hs > skip) first = fminf(first, s2);
+        if (i % rti::ILLUM_CULL_EVERY == 0) {
+            if (A.cull_margin >= 0.f) {
+                const Box w = lane_box(p, A.cull_margin);
+                if constexpr (bump_cull<KIND>) acc.mask = bump_window<KIND>(acc.B, A.n_bumps, w);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sm[c] = 0ull;
+                for (int k = 0; k < A.n_spheres; ++k) {
+                    const float4 s = SPH[k];
+                    if (ballot(box_dist2(s.x, s.y, s.z, w.lo, w.hi) <= s.w * s.w)) sm[k >> 6] |= 1ull << (k & 63);
+                }
+                om = 0;
+                for (int k = 0; k < no; ++k) {
+                    bool on;
+                    if (k < A.n_planes) {
+                        const float4 pl = PLN[k];
+                        const float c = pl.x * p.x + pl.y * p.y + pl.z * p.z - pl.w;
+                        on = fabsf(c) <= A.cull_margin * (fabsf(pl.x) + fabsf(pl.y) + fabsf(pl.z));
+                    } else {
+                        const float *tp = TOR + 8 * (k - A.n_planes);
+                        const float rr = tp[6] + tp[7];
+                        on = box_dist2(tp[0], tp[1], tp[2], w.lo, w.hi) <= rr * rr;
+                    }
+                    if (ballot(on)) om |= 1u << k;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int rem = A.n_spheres - 64 * c;
+                    sm[c] = rem >= 64 ? ~0ull : (rem > 0 ? (1ull << rem) - 1ull : 0ull);
+                }
+                om = (1u << no) - 1u;
             }
         }
-        for (int k = 0; k < A.n_planes + A.n_tori; ++k) {
+        const float hs = i == n - 1 ? T - (float)(n - 1) * h : h;
+        V3<float> dx, dv;
+        if (!step_rk4<float>(acc, p, y, hs, dx, dv)) return false;
+        const float DD = dot(dx, dx);
+        float first = 2.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            for (uint64_t m = sm[c]; m; m &= m - 1ull) {
+                const float4 s = SPH[64 * c + __builtin_ctzll(m)];
+                const V3<float> o = mk((xh.x - s.x) + xl.x, (xh.y - s.y) + xl.y, (xh.z - s.z) + xl.z);
+                // both roots: a chord that starts on a sphere (s ~ 0) may still cross it later
+                const float B = dot(dx, o), C = fmaf(-s.w, s.w, dot(o, o));
+                const float disc = fmaf(B, B, -DD * C);
+                if (disc >= 0.f) {
+                    const float qd = sqrt_(disc), inv = rcp_(DD);
+                    const float s1 = (-B - qd) * inv, s2 = (-B + qd) * inv;
+                    if (s1 >= 0.f && s1 <= 1.f && t + s1 * hs > skip) first = fminf(first, s1);
+                    else if (s2 >= 0.f && s2 <= 1.f && t + s2 * hs > skip) first = fminf(first, s2);
+                }
+            }
+        }
+        for (uint32_t m = om; m; m &= m - 1u) {
+            const int k = __builtin_ctz(m);
             float F0, F1;
             if (k < A.n_planes) {
                 const float4 pl = PLN[k];
@@ -206,8 +287,60 @@ __global__ __launch_bounds__(256) void k_illum_init(rti::IllumArgs A, const floa
     }
 }
 
+// Residual of the base shot of pixel pix: returns 1 when a Newton step is
+// to be taken, 0 when the pixel leaves the list (converged, marked ST_CONV,
+// or stalled: from the fifth iteration on, a residual that did not halve).
+__device__ __forceinline__ int judge(const rti::IllumArgs &A, int pix, int it, V3<float> F) {
+    const float fn = fmaxf(fabsf(F.x), fmaxf(fabsf(F.y), fabsf(F.z)));
+    const bool stalled = it >= 4 && fn > 0.5f * A.w_F[pix];
+    A.w_F[pix] = fn;
+    if (fn < A.tol) {
+        A.status[pix] = ST_CONV;
+        return 0;
+    }
+    return stalled ? 0 : 1;
+}
+
+// Damped Newton step on (al, be, T) from the residual F = X - L, the end
+// velocity Y (the T column) and the shots Xa, Xb at al + eps, be + eps;
+// true when the pixel stays on the list.
+template <int KIND>
+__device__ __forceinline__ bool newton(const rti::IllumArgs &A, const Pixel<KIND> &P, int pix, V3<float> L, float eps,
+                                      float al, float be, float T, V3<float> F, V3<float> X, V3<float> Y,
+                                      V3<float> Xa, V3<float> Xb) {
+    const V3<float> ca = (1.f / eps) * (Xa - X), cb = (1.f / eps) * (Xb - X);
+    const float M[9] = {ca.x, cb.x, Y.x, ca.y, cb.y, Y.y, ca.z, cb.z, Y.z};
+    const float c0 = M[4] * M[8] - M[5] * M[7], c1 = M[2] * M[7] - M[1] * M[8], c2 = M[1] * M[5] - M[2] * M[4];
+    const float c3 = M[5] * M[6] - M[3] * M[8], c4 = M[0] * M[8] - M[2] * M[6], c5 = M[2] * M[3] - M[0] * M[5];
+    const float c6 = M[3] * M[7] - M[4] * M[6], c7 = M[1] * M[6] - M[0] * M[7], c8 = M[0] * M[4] - M[1] * M[3];
+    const float det = M[0] * c0 + M[1] * c3 + M[2] * c6;
+    if (!(fabsf(det) > 1e-20f)) return false;
+    const float idet = -1.f / det;
+    const float da = idet * (c0 * F.x + c1 * F.y + c2 * F.z);
+    const float db = idet * (c3 * F.x + c4 * F.y + c5 * F.z);
+    const float dT = idet * (c6 * F.x + c7 * F.y + c8 * F.z);
+    // damping: at most 0.3 in the angles and half the length per step
+    const float m = fmaxf(fabsf(da), fabsf(db));
+    const float sa = m > 0.3f ? 0.3f / m : 1.f;
+    const float sT = fabsf(dT) > 0.5f * T ? 0.5f * T / fabsf(dT) : 1.f;
+    const float sc = fminf(sa, sT);
+    A.w_al[pix] = al + sc * da;
+    A.w_be[pix] = be + sc * db;
+    A.w_T[pix] = T + sc * dT;
+    // geodesics much longer than the straight segment are not pursued
+    return T + sc * dT <= 4.f * sqrtf(P.gdd(A, L - P.q)) + 1.f;
+}
+
+// Pixels per wave when the three shots of an iteration run on three lanes.
+constexpr int PAR_PIX = 21;
+
 // One Newton iteration for every pixel of list[it & 1]: shoot; converged
 // pixels are marked, the others take a damped step and move to the next list.
+// While the list fills the grid, a lane takes a pixel and shoots the
+// finite-difference directions only when a step is due.  Once the list fits
+// in one pass at three lanes per pixel (the latency-bound last iterations),
+// lanes 3j, 3j+1, 3j+2 of a wave shoot the base and the two displaced
+// directions of pixel j side by side.  Both ways compute the same values.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const float4 *__restrict__ BF, int it) {
     const int *in = A.list[it & 1];
@@ -216,6 +349,40 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
     const uint64_t all = all_bumps(A.n_bumps);
     const V3<float> L = mk(A.light[0], A.light[1], A.light[2]);
     const float eps = 1e-3f;
+    const int per_block = PAR_PIX * (blockDim.x / 64);
+    if (n_in <= (int)gridDim.x * per_block) {
+        const int lane = lane_id(), role = lane % 3;
+        for (int base = blockIdx.x * per_block; base < n_in; base += gridDim.x * per_block) {
+            const int k = base + (threadIdx.x >> 6) * PAR_PIX + lane / 3;
+            const bool act = lane < 3 * PAR_PIX && k < n_in;
+            bool again = false, ok = false;
+            int pix = 0;
+            V3<float> X = mk(0.f, 0.f, 0.f), Y = X;
+            float al = 0.f, be = 0.f, T = 0.f;
+            Pixel<KIND> P{};
+            if (act) {
+                pix = in[k];
+                P = pixel<KIND>(A, BF, pix);
+                IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
+                al = A.w_al[pix];
+                be = A.w_be[pix];
+                T = A.w_T[pix];
+                const float as = role == 1 ? al + eps : al, bs = role == 2 ? be + eps : be;
+                ok = shoot<KIND>(acc, A, P.q, P.dir(A, as, bs), T, X, Y);
+            }
+            // the displaced shots of lanes 3j+1, 3j+2 to lane 3j
+            const int src = lane + 1 < 64 ? lane + 1 : lane, src2 = lane + 2 < 64 ? lane + 2 : lane;
+            const V3<float> Xa = mk(__shfl(X.x, src), __shfl(X.y, src), __shfl(X.z, src));
+            const V3<float> Xb = mk(__shfl(X.x, src2), __shfl(X.y, src2), __shfl(X.z, src2));
+            const int oka = __shfl((int)ok, src), okb = __shfl((int)ok, src2);
+            if (act && role == 0 && ok) {
+                const V3<float> F = X - L;
+                if (judge(A, pix, it, F) && oka && okb) again = newton<KIND>(A, P, pix, L, eps, al, be, T, F, X, Y, Xa, Xb);
+            }
+            append(out, A.ctr + it + 1, pix, again);
+        }
+        return;
+    }
     for (int base = blockIdx.x * blockDim.x; base < n_in; base += gridDim.x * blockDim.x) {
         const int k = base + threadIdx.x;
         bool again = false;
@@ -223,46 +390,14 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
         if (k < n_in) {
             pix = in[k];
             const Pixel<KIND> P = pixel<KIND>(A, BF, pix);
-            Acc32<KIND, false, false, true> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
-            float al = A.w_al[pix], be = A.w_be[pix], T = A.w_T[pix];
+            IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
+            const float al = A.w_al[pix], be = A.w_be[pix], T = A.w_T[pix];
             V3<float> X, Y, Xa, Xb, Ya, Yb;
-            if (shoot(acc, P.q, P.dir(A, al, be), T, A.h, A.max_steps, X, Y)) {
+            if (shoot<KIND>(acc, A, P.q, P.dir(A, al, be), T, X, Y)) {
                 const V3<float> F = X - L;
-                const float fn = fmaxf(fabsf(F.x), fmaxf(fabsf(F.y), fabsf(F.z)));
-                // give up when Newton stalls (after the first, damped, iterations)
-                const bool stalled = it >= 4 && fn > 0.5f * A.w_F[pix];
-                A.w_F[pix] = fn;
-                if (fn < A.tol) {
-                    A.status[pix] = ST_CONV;
-                } else if (!stalled && shoot(acc, P.q, P.dir(A, al + eps, be), T, A.h, A.max_steps, Xa, Ya) &&
-                           shoot(acc, P.q, P.dir(A, al, be + eps), T, A.h, A.max_steps, Xb, Yb)) {
-                    // Newton step on (al, be, T): columns dX/dal, dX/dbe, dX/dT = Y
-                    const V3<float> ca = (1.f / eps) * (Xa - X), cb = (1.f / eps) * (Xb - X);
-                    const float M[9] = {ca.x, cb.x, Y.x, ca.y, cb.y, Y.y, ca.z, cb.z, Y.z};
-                    const float c0 = M[4] * M[8] - M[5] * M[7], c1 = M[2] * M[7] - M[1] * M[8],
-                                c2 = M[1] * M[5] - M[2] * M[4];
-                    const float c3 = M[5] * M[6] - M[3] * M[8], c4 = M[0] * M[8] - M[2] * M[6],
-                                c5 = M[2] * M[3] - M[0] * M[5];
-                    const float c6 = M[3] * M[7] - M[4] * M[6], c7 = M[1] * M[6] - M[0] * M[7],
-                                c8 = M[0] * M[4] - M[1] * M[3];
-                    const float det = M[0] * c0 + M[1] * c3 + M[2] * c6;
-                    if (fabsf(det) > 1e-20f) {
-                        const float idet = -1.f / det;
-                        const float da = idet * (c0 * F.x + c1 * F.y + c2 * F.z);
-                        const float db = idet * (c3 * F.x + c4 * F.y + c5 * F.z);
-                        const float dT = idet * (c6 * F.x + c7 * F.y + c8 * F.z);
-                        // damping: at most 0.3 in the angles and half the length per step
-                        const float m = fmaxf(fabsf(da), fabsf(db));
-                        const float sa = m > 0.3f ? 0.3f / m : 1.f;
-                        const float sT = fabsf(dT) > 0.5f * T ? 0.5f * T / fabsf(dT) : 1.f;
-                        const float sc = fminf(sa, sT);
-                        A.w_al[pix] = al + sc * da;
-                        A.w_be[pix] = be + sc * db;
-                        A.w_T[pix] = T + sc * dT;
-                        // geodesics much longer than the straight segment are not pursued
-                        again = T + sc * dT <= 4.f * sqrtf(P.gdd(A, L - P.q)) + 1.f;
-                    }
-                }
+                if (judge(A, pix, it, F) && shoot<KIND>(acc, A, P.q, P.dir(A, al + eps, be), T, Xa, Ya) &&
+                    shoot<KIND>(acc, A, P.q, P.dir(A, al, be + eps), T, Xb, Yb))
+                    again = newton<KIND>(A, P, pix, L, eps, al, be, T, F, X, Y, Xa, Xb);
             }
         }
         append(out, A.ctr + it + 1, pix, again);
@@ -304,10 +439,10 @@ __global__ __launch_bounds__(256) void k_illum_finish(rti::IllumArgs A, const fl
             const float qf = (gF.x * (a0 * gF.x + a1 * gF.y + a2 * gF.z) + gF.y * (a1 * gF.x + a4 * gF.y + a5 * gF.z) +
                               gF.z * (a2 * gF.x + a5 * gF.y + a8 * gF.z)) / gdet;
             const float c = dot(gF, v) * rsqrt_(qf);
-            Acc32<KIND, false, false, true> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
+            IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
             if (!(c > 0.f)) {
                 status = ST_AWAY;
-            } else if (reaches(acc, P.q, v, T, A.h, 1e-3f, A, SPH, PLN, TOR)) {
+            } else if (reaches<KIND>(acc, P.q, v, T, 1e-3f, A, SPH, PLN, TOR)) {
                 status = ST_LIT;
                 shade = fminf(c, 1.f);
             } else {

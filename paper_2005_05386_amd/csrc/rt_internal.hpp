@@ -157,6 +157,8 @@ struct DeviceData {
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid_blocks,
                         int refine_blocks, hipStream_t s, hipEvent_t *ev, const struct SurrArgs *S, int mlp_blocks);
 // ------------------------------------------------------ direct illumination
+// Steps between the culling windows of the illumination's shots.
+constexpr int ILLUM_CULL_EVERY = 16;
 struct IllumArgs {
     int kind, n_sets, n_bumps;
     float twist_amp, twist_theta0;
@@ -167,6 +169,7 @@ struct IllumArgs {
     float light[3];
     float h, tol;
     int max_iters, max_steps;
+    float cull_margin;  // half-width of a lane's culling window; < 0: no culling
     float *shade, *dir, *len;
     int *status;
     // workspace: Newton state per pixel, two pixel lists, one counter per iteration
