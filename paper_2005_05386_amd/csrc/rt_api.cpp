@@ -143,7 +143,13 @@ rt_status rt_create(int hip_device, rt_ctx **out) {
             delete c;
             return RT_ENOMEM;
         }
-        hipMemset(c->d_stats, 0, sizeof(unsigned long long) * rti::ST_N);
+        e = hipMemset(c->d_stats, 0, sizeof(unsigned long long) * rti::ST_N);
+        if (e != hipSuccess) {
+            g_create_error = std::string("rt_create: ") + hipGetErrorString(e);
+            hipFree(c->d_stats);
+            delete c;
+            return RT_EDEVICE;
+        }
     }
     *out = c;
     return RT_OK;

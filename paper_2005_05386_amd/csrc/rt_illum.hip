@@ -96,7 +96,8 @@ __device__ __forceinline__ bool shoot(IAcc<KIND> &acc, const rti::IllumArgs &A, 
     V3<float> xh = q, xl = mk(0.f, 0.f, 0.f), y = v;
     for (int i = 0; i < n; ++i) {
         if constexpr (bump_cull<KIND>)
-            if (i % rti::ILLUM_CULL_EVERY == 0) acc.mask = bump_window<KIND>(acc.B, A.n_bumps, lane_box(xh + xl, A.cull_margin));
+            if (i % rti::ILLUM_CULL_EVERY == 0 && A.cull_margin >= 0.f)
+                acc.mask = bump_window<KIND>(acc.B, A.n_bumps, lane_box(xh + xl, A.cull_margin));
         const float hs = i == n - 1 ? T - (float)(n - 1) * h : h;
         V3<float> dx, dv;
         if (!step_rk4<float>(acc, xh + xl, y, hs, dx, dv) || !finite6(dx, dv)) return false;
@@ -236,11 +237,17 @@ template <int KIND> struct Pixel {
         return rsqrt_(gdd(A, u)) * u;
     }
 };
-template <int KIND>
+// ONE: a single parameter set, so the table pointer is the same for every
+// lane and the bump records are read with scalar loads.
+template <int KIND, bool ONE = false>
 __device__ __forceinline__ Pixel<KIND> pixel(const rti::IllumArgs &A, const float4 *__restrict__ BF, int pix) {
-    const int set = pix / (A.width * A.height);
     Pixel<KIND> P;
-    P.Bs = BF + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
+    if constexpr (ONE) {
+        P.Bs = BF;
+    } else {
+        const int set = pix / (A.width * A.height);
+        P.Bs = BF + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
+    }
     P.q = mk(A.hit[3 * pix], A.hit[3 * pix + 1], A.hit[3 * pix + 2]);
     P.F = light_frame(P.q, mk(A.light[0], A.light[1], A.light[2]));
     return P;
@@ -341,7 +348,7 @@ constexpr int PAR_PIX = 21;
 // in one pass at three lanes per pixel (the latency-bound last iterations),
 // lanes 3j, 3j+1, 3j+2 of a wave shoot the base and the two displaced
 // directions of pixel j side by side.  Both ways compute the same values.
-template <int KIND>
+template <int KIND, bool ONE>
 __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const float4 *__restrict__ BF, int it) {
     const int *in = A.list[it & 1];
     int *out = A.list[(it + 1) & 1];
@@ -362,7 +369,7 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
             Pixel<KIND> P{};
             if (act) {
                 pix = in[k];
-                P = pixel<KIND>(A, BF, pix);
+                P = pixel<KIND, ONE>(A, BF, pix);
                 IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
                 al = A.w_al[pix];
                 be = A.w_be[pix];
@@ -389,7 +396,7 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
         int pix = 0;
         if (k < n_in) {
             pix = in[k];
-            const Pixel<KIND> P = pixel<KIND>(A, BF, pix);
+            const Pixel<KIND> P = pixel<KIND, ONE>(A, BF, pix);
             IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
             const float al = A.w_al[pix], be = A.w_be[pix], T = A.w_T[pix];
             V3<float> X, Y, Xa, Xb, Ya, Yb;
@@ -406,7 +413,7 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
 
 // Lambert term and visibility for the converged pixels; every hit pixel
 // gets its direction and length.
-template <int KIND>
+template <int KIND, bool ONE>
 __global__ __launch_bounds__(256) void k_illum_finish(rti::IllumArgs A, const float4 *__restrict__ BF,
                                                       const float4 *__restrict__ SPH, const float4 *__restrict__ PLN,
                                                       const float *__restrict__ TOR) {
@@ -419,7 +426,7 @@ __global__ __launch_bounds__(256) void k_illum_finish(rti::IllumArgs A, const fl
             if (A.len) A.len[pix] = 0.f;
             continue;
         }
-        const Pixel<KIND> P = pixel<KIND>(A, BF, pix);
+        const Pixel<KIND> P = pixel<KIND, ONE>(A, BF, pix);
         const float T = A.w_T[pix];
         const V3<float> v = P.dir(A, A.w_al[pix], A.w_be[pix]);
         float shade = 0.f;
@@ -468,9 +475,17 @@ template <int KIND>
 hipError_t illum_kind(const rti::IllumArgs &a, const rti::DeviceData &d, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_illum_zero, dim3(1), dim3(256), 0, s, a.ctr, a.max_iters + 1);
     hipLaunchKernelGGL((k_illum_init<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f);
-    for (int it = 0; it < a.max_iters; ++it)
-        hipLaunchKernelGGL((k_illum_iter<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
-    hipLaunchKernelGGL((k_illum_finish<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f, d.tor_f);
+    if (a.n_sets == 1) {
+        for (int it = 0; it < a.max_iters; ++it)
+            hipLaunchKernelGGL((k_illum_iter<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+        hipLaunchKernelGGL((k_illum_finish<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f,
+                           d.tor_f);
+    } else {
+        for (int it = 0; it < a.max_iters; ++it)
+            hipLaunchKernelGGL((k_illum_iter<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+        hipLaunchKernelGGL((k_illum_finish<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f,
+                           d.tor_f);
+    }
     return hipGetLastError();
 }
 

@@ -95,8 +95,17 @@ def test_flat_space_closed_form(rt):
     assert n_bad <= max(2, 0.002 * hit.sum()), (n_bad, hit.sum())
 
 
-@pytest.mark.parametrize("name,w,h", [("bumps16_1080p", 64, 40), ("twist_4k", 64, 40), ("deform16_1080p", 48, 30)])
-def test_curved_geodesics_reach_the_light(rt, name, w, h):
+# found: the least fraction of hit pixels for which Newton's method from the
+# straight segment finds a geodesic.  The anisotropic bumps have the same
+# amplitudes as the isotropic ones but the smallest of three drawn spreads,
+# so steeper slopes that bend geodesics more and leave more pixels unsolved.
+# The quadric's slope grows linearly with the distance from the origin: on
+# the way to the light many geodesics bend far from the segment (about two
+# thirds are found).
+@pytest.mark.parametrize("name,w,h,found_min", [("bumps16_1080p", 64, 40, 0.95), ("twist_4k", 64, 40, 0.95),
+                                                ("deform16_1080p", 48, 30, 0.95), ("abumps16_1080p", 64, 40, 0.9),
+                                                ("quadric_1080p", 64, 40, 0.6)])
+def test_curved_geodesics_reach_the_light(rt, name, w, h, found_min):
     """Curved metrics: the oracle integrates each returned geodesic in FP64
     and lands on the light; the Lambert term and the visibility recomputed
     in FP64 from the returned direction agree."""
@@ -110,7 +119,6 @@ def test_curved_geodesics_reach_the_light(rt, name, w, h):
     found = hit[st[hit] >= 0]
     say("hits %d found %d lit %d shadowed %d facing away %d" % (len(hit), len(found), (st == 1).sum(),
                                                                 (st == 0).sum(), (st == 2).sum()))
-    assert len(found) >= 0.95 * len(hit)
     worst_end = worst_cos = 0.0
     vis_bad = 0
     for p in found:
@@ -136,3 +144,21 @@ def test_curved_geodesics_reach_the_light(rt, name, w, h):
     assert worst_end < 5e-4
     assert worst_cos < 2e-3
     assert vis_bad <= max(2, 0.01 * len(found))
+    assert len(found) >= found_min * len(hit)
+
+
+def test_multi_set_equals_single_sets(rt):
+    """Three parameter sets in one call give, set by set, bitwise the
+    single-set results (the single-set kernels read the bump table with
+    scalar loads, the multi-set ones per lane)."""
+    say("illumination, 3 parameter sets in one call vs one by one")
+    wl = W.with_size(W.get("adjoint_64x512", n_sets=3), 40, 32)
+    _, sh = _run(rt, wl)
+    n = 40 * 32
+    for s in range(3):
+        one = dict(wl)
+        one["metric"] = dict(wl["metric"], bumps=wl["metric"]["bumps"][s:s + 1])
+        _, shs = _run(rt, one)
+        say("set %d: %d lit" % (s, (shs["status"] == 1).sum()))
+        for k in ("status", "shade", "dir", "len"):
+            assert np.array_equal(sh[k][s * n:(s + 1) * n], shs[k]), (s, k)
