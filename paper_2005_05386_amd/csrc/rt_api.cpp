@@ -925,14 +925,15 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     a.dir = out->dir;
     a.len = out->len;
     const int64_t n = (int64_t)cam->width * cam->height * c->n_sets;
-    // workspace: Newton state (4 floats), two pixel lists, the list counters
+    // workspace: Newton state (4 floats), the base shot (6 floats), three
+    // pixel lists, the list counters
     if (c->ibuf_cap < n) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
         hipFree(c->d_ibuf);
         c->d_ibuf = nullptr;
         c->ibuf_cap = 0;
-        e = hipMalloc(&c->d_ibuf, (size_t)n * 24 + 65 * sizeof(int) + 256);
+        e = hipMalloc(&c->d_ibuf, (size_t)n * 52 + 130 * sizeof(int) + 256);
         if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (illumination workspace)");
         c->ibuf_cap = n;
     }
@@ -941,9 +942,12 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     a.w_be = (float *)(ib + (size_t)n * 4);
     a.w_T = (float *)(ib + (size_t)n * 8);
     a.w_F = (float *)(ib + (size_t)n * 12);
-    a.list[0] = (int *)(ib + (size_t)n * 16);
-    a.list[1] = (int *)(ib + (size_t)n * 20);
-    a.ctr = (int *)(ib + (size_t)n * 24);
+    a.w_X = (float *)(ib + (size_t)n * 16);
+    a.w_Y = (float *)(ib + (size_t)n * 28);
+    a.list[0] = (int *)(ib + (size_t)n * 40);
+    a.list[1] = (int *)(ib + (size_t)n * 44);
+    a.list[2] = (int *)(ib + (size_t)n * 48);
+    a.ctr = (int *)(ib + (size_t)n * 52);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)c->n_cu * 8));
     hipStream_t s = (hipStream_t)stream;
     e = rti::launch_illum(a, c->dd, grid, s);

@@ -340,14 +340,20 @@ __device__ __forceinline__ bool newton(const rti::IllumArgs &A, const Pixel<KIND
 
 // Pixels per wave when the three shots of an iteration run on three lanes.
 constexpr int PAR_PIX = 21;
+// Angle displacement of the finite-difference shots.
+constexpr float ILLUM_EPS = 1e-3f;
 
 // One Newton iteration for every pixel of list[it & 1]: shoot; converged
 // pixels are marked, the others take a damped step and move to the next list.
-// While the list fills the grid, a lane takes a pixel and shoots the
-// finite-difference directions only when a step is due.  Once the list fits
-// in one pass at three lanes per pixel (the latency-bound last iterations),
-// lanes 3j, 3j+1, 3j+2 of a wave shoot the base and the two displaced
-// directions of pixel j side by side.  Both ways compute the same values.
+// While the list fills the grid, the iteration runs in two launches: here a
+// lane shoots the base direction of one pixel, and a pixel that is due a
+// step keeps its end point and velocity and goes to the step list, whose
+// displaced shots k_illum_step takes two lanes per pixel; so lanes whose
+// pixel converged do not wait on the displaced shots of their neighbours.
+// Once the list fits in one pass at three lanes per pixel (the
+// latency-bound last iterations), lanes 3j, 3j+1, 3j+2 of a wave shoot the
+// base and the two displaced directions of pixel j side by side and the
+// step list stays empty.  Both ways compute the same values.
 template <int KIND, bool ONE>
 __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const float4 *__restrict__ BF, int it) {
     const int *in = A.list[it & 1];
@@ -355,7 +361,7 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
     const int n_in = A.ctr[it];
     const uint64_t all = all_bumps(A.n_bumps);
     const V3<float> L = mk(A.light[0], A.light[1], A.light[2]);
-    const float eps = 1e-3f;
+    const float eps = ILLUM_EPS;
     const int per_block = PAR_PIX * (blockDim.x / 64);
     if (n_in <= (int)gridDim.x * per_block) {
         const int lane = lane_id(), role = lane % 3;
@@ -390,22 +396,70 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
         }
         return;
     }
+    int *steps = A.list[2];
     for (int base = blockIdx.x * blockDim.x; base < n_in; base += gridDim.x * blockDim.x) {
         const int k = base + threadIdx.x;
-        bool again = false;
+        bool due = false;
         int pix = 0;
         if (k < n_in) {
             pix = in[k];
             const Pixel<KIND> P = pixel<KIND, ONE>(A, BF, pix);
             IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
-            const float al = A.w_al[pix], be = A.w_be[pix], T = A.w_T[pix];
-            V3<float> X, Y, Xa, Xb, Ya, Yb;
-            if (shoot<KIND>(acc, A, P.q, P.dir(A, al, be), T, X, Y)) {
-                const V3<float> F = X - L;
-                if (judge(A, pix, it, F) && shoot<KIND>(acc, A, P.q, P.dir(A, al + eps, be), T, Xa, Ya) &&
-                    shoot<KIND>(acc, A, P.q, P.dir(A, al, be + eps), T, Xb, Yb))
-                    again = newton<KIND>(A, P, pix, L, eps, al, be, T, F, X, Y, Xa, Xb);
+            V3<float> X, Y;
+            if (shoot<KIND>(acc, A, P.q, P.dir(A, A.w_al[pix], A.w_be[pix]), A.w_T[pix], X, Y) &&
+                judge(A, pix, it, X - L)) {
+                A.w_X[3 * pix] = X.x;
+                A.w_X[3 * pix + 1] = X.y;
+                A.w_X[3 * pix + 2] = X.z;
+                A.w_Y[3 * pix] = Y.x;
+                A.w_Y[3 * pix + 1] = Y.y;
+                A.w_Y[3 * pix + 2] = Y.z;
+                due = true;
             }
+        }
+        append(steps, A.ctr + A.max_iters + 1 + it, pix, due);
+    }
+}
+
+// Second launch of a full-grid iteration: for every pixel of the step list,
+// lanes 2j and 2j+1 shoot the two displaced directions of pixel j, and lane
+// 2j takes the Newton step from them and the stored base shot.
+template <int KIND, bool ONE>
+__global__ __launch_bounds__(256) void k_illum_step(rti::IllumArgs A, const float4 *__restrict__ BF, int it) {
+    const int *steps = A.list[2];
+    int *out = A.list[(it + 1) & 1];
+    const int n_st = A.ctr[A.max_iters + 1 + it];
+    const uint64_t all = all_bumps(A.n_bumps);
+    const V3<float> L = mk(A.light[0], A.light[1], A.light[2]);
+    const float eps = ILLUM_EPS;
+    const int lane = lane_id(), role = lane & 1;
+    const int per_block = blockDim.x / 2;
+    for (int base = blockIdx.x * per_block; base < n_st; base += gridDim.x * per_block) {
+        const int k = base + (threadIdx.x >> 1);
+        const bool act = k < n_st;
+        bool again = false, ok = false;
+        int pix = 0;
+        V3<float> Xs = mk(0.f, 0.f, 0.f), Ys = Xs;
+        float al = 0.f, be = 0.f, T = 0.f;
+        Pixel<KIND> P{};
+        if (act) {
+            pix = steps[k];
+            P = pixel<KIND, ONE>(A, BF, pix);
+            IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
+            al = A.w_al[pix];
+            be = A.w_be[pix];
+            T = A.w_T[pix];
+            const float as = role == 0 ? al + eps : al, bs = role == 1 ? be + eps : be;
+            ok = shoot<KIND>(acc, A, P.q, P.dir(A, as, bs), T, Xs, Ys);
+        }
+        // the beta shot of lane 2j+1 to lane 2j
+        const int src = lane | 1;
+        const V3<float> Xb = mk(__shfl(Xs.x, src), __shfl(Xs.y, src), __shfl(Xs.z, src));
+        const int okb = __shfl((int)ok, src);
+        if (act && role == 0 && ok && okb) {
+            const V3<float> X = mk(A.w_X[3 * pix], A.w_X[3 * pix + 1], A.w_X[3 * pix + 2]);
+            const V3<float> Y = mk(A.w_Y[3 * pix], A.w_Y[3 * pix + 1], A.w_Y[3 * pix + 2]);
+            again = newton<KIND>(A, P, pix, L, eps, al, be, T, X - L, X, Y, Xs, Xb);
         }
         append(out, A.ctr + it + 1, pix, again);
     }
@@ -473,16 +527,20 @@ __global__ void k_illum_zero(int *ctr, int n) {
 
 template <int KIND>
 hipError_t illum_kind(const rti::IllumArgs &a, const rti::DeviceData &d, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_illum_zero, dim3(1), dim3(256), 0, s, a.ctr, a.max_iters + 1);
+    hipLaunchKernelGGL(k_illum_zero, dim3(1), dim3(256), 0, s, a.ctr, 2 * (a.max_iters + 1));
     hipLaunchKernelGGL((k_illum_init<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f);
     if (a.n_sets == 1) {
-        for (int it = 0; it < a.max_iters; ++it)
+        for (int it = 0; it < a.max_iters; ++it) {
             hipLaunchKernelGGL((k_illum_iter<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+            hipLaunchKernelGGL((k_illum_step<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+        }
         hipLaunchKernelGGL((k_illum_finish<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f,
                            d.tor_f);
     } else {
-        for (int it = 0; it < a.max_iters; ++it)
+        for (int it = 0; it < a.max_iters; ++it) {
             hipLaunchKernelGGL((k_illum_iter<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+            hipLaunchKernelGGL((k_illum_step<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+        }
         hipLaunchKernelGGL((k_illum_finish<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f,
                            d.tor_f);
     }

@@ -172,10 +172,12 @@ struct IllumArgs {
     float cull_margin;  // half-width of a lane's culling window; < 0: no culling
     float *shade, *dir, *len;
     int *status;
-    // workspace: Newton state per pixel, two pixel lists, one counter per iteration
+    // workspace: Newton state per pixel, the two iteration lists and the
+    // step list, two counters per iteration
     float *w_al, *w_be, *w_T, *w_F;  // angles, length, last residual
-    int *list[2];
-    int *ctr;  // max_iters + 1 words
+    float *w_X, *w_Y;                // base shot's end point and velocity [3 per pixel]
+    int *list[3];
+    int *ctr;  // 2 (max_iters + 1) words: list sizes, then step-list sizes
 };
 hipError_t launch_illum(const IllumArgs &a, const DeviceData &d, int grid, hipStream_t s);
 // ------------------------------------------------------------- MLP (BF16)
