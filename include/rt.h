@@ -297,7 +297,8 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
  * hit point q to L by shooting -- the g-unit direction v at q and the arc
  * length T with gamma_{q,v}(T) = L, Newton's method from the straight
  * segment, each shot an RK4 integration with step h -- then marches it
- * against every object (crossings within 1e-3 of q ignored) and writes
+ * against the scene's objects (crossings within 1e-3 of q ignored) and
+ * writes
  *   shade  = grad F . v / sqrt(grad F^T g^-1 grad F) when lit, else 0:
  *            the cosine between v and the metric normal g^-1 grad F of the
  *            surface F = 0, both measured in g at q;
@@ -312,7 +313,9 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
  * from the straight segment.  The paper describes this illumination but
  * not how to compute it.  camera must be the traced camera; the metric and
  * scene of the context are used.  Outputs are device arrays of
- * n_sets * height * width entries (dir: 3 per entry). */
+ * n_sets * height * width entries (dir: 3 per entry).  Asynchronous on
+ * hip_stream; the context keeps a device workspace of 52 bytes per entry,
+ * sized for the largest frame seen so far. */
 typedef struct rt_light {
     float pos[3];   /* point light */
     float h;        /* RK4 step of the shots, (0, 0.1] */
