@@ -112,16 +112,34 @@ def test_curved_geodesics_reach_the_light(rt, name, w, h, found_min):
     say("illumination, %s %dx%d" % (name, w, h))
     wl = W.with_size(W.get(name), w, h)
     tra, sh = _run(rt, wl)
+    _check_found(wl, tra, sh, found_min)
+
+
+def test_illum_1080p_sampled(rt):
+    """The benchmarked 1080p frame and launch configuration: the counts
+    over every hit pixel, and the FP64 checks on a seeded sample of 400
+    pixels that found a geodesic."""
+    say("illumination, illum_1080p full frame, 400 sampled pixels")
+    wl = W.get("illum_1080p")
+    assert tuple(wl["light"]["pos"]) == LIGHT["pos"] and wl["light"]["h"] == LIGHT["h"]
+    tra, sh = _run(rt, wl, light=wl["light"])
+    _check_found(wl, tra, sh, 0.95, sample=400)
+
+
+def _check_found(wl, tra, sh, found_min, sample=None):
     orc = oracle.Oracle(wl["metric"], wl["scene"])
     L = np.array(LIGHT["pos"], np.float64)
     hit = np.nonzero(tra["id"] >= 0)[0]
     st = sh["status"]
+    assert (st[tra["id"] < 0] == -3).all()
     found = hit[st[hit] >= 0]
     say("hits %d found %d lit %d shadowed %d facing away %d" % (len(hit), len(found), (st == 1).sum(),
                                                                 (st == 0).sum(), (st == 2).sum()))
+    assert len(found) >= found_min * len(hit)
+    check = found if sample is None else np.sort(np.random.default_rng(5).choice(found, sample, replace=False))
     worst_end = worst_cos = 0.0
     vis_bad = 0
-    for p in found:
+    for p in check:
         q = tra["hit"][p].astype(np.float64)
         v = sh["dir"][p].astype(np.float64)
         g = orc.metric_tensor(q)
@@ -143,8 +161,7 @@ def test_curved_geodesics_reach_the_light(rt, name, w, h, found_min):
     say("worst end %.2e, worst cos %.2e, visibility disagreements %d" % (worst_end, worst_cos, vis_bad))
     assert worst_end < 5e-4
     assert worst_cos < 2e-3
-    assert vis_bad <= max(2, 0.01 * len(found))
-    assert len(found) >= found_min * len(hit)
+    assert vis_bad <= max(2, 0.01 * len(check))
 
 
 def test_multi_set_equals_single_sets(rt):
