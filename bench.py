@@ -41,6 +41,9 @@ FLOPS = {
     # updates of w, u, q 18, M 18
     "deform_eval": 51,
     "deform_term": 95,
+    # a deformation whose field also rotates, V = v + w x d: w x u, w x w and
+    # w x (the columns of M) 45, V 12, the extra terms of w 13, u 6 and M 18
+    "deform_term_rot": 189,
     # anisotropic bumps: per evaluation 1 + |grad f|^2 6, reciprocal 1, scale 4; per bump
     # inside its cut: d, S d, d.S d 11, exponent 2, w 1, grad f 6, S d . y 5, y.S y 8, q 4
     "ganiso_eval": 11,
@@ -108,7 +111,7 @@ def copy_probe(nbytes, reps=4):
     print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def algorithmic_flops(kind, step, st):
+def algorithmic_flops(kind, step, st, rotating=False):
     ev = st["acc_evals"]
     if kind == 1:
         f = FLOPS["graph_eval"] * ev + FLOPS["graph_bump"] * st["bump_evals"]
@@ -117,7 +120,7 @@ def algorithmic_flops(kind, step, st):
     elif kind == 3:
         f = FLOPS["ztwist_eval"] * ev
     elif kind == 4:
-        f = FLOPS["deform_eval"] * ev + FLOPS["deform_term"] * st["bump_evals"]
+        f = FLOPS["deform_eval"] * ev + FLOPS["deform_term_rot" if rotating else "deform_term"] * st["bump_evals"]
     elif kind == 5:
         f = FLOPS["ganiso_eval"] * ev + FLOPS["ganiso_bump"] * st["bump_evals"]
     elif kind == 6:
@@ -526,7 +529,11 @@ def main():
     ms = ev0.elapsed_time(ev1) / args.steps
     n_rays = tr.n_sets * cam["width"] * cam["height"]
 
-    flops = algorithmic_flops(wl["metric"]["kind"], rule["kind"], work)
+    import numpy as np
+    dfm = wl["metric"].get("deforms")
+    # the rotating model applies when every deformation rotates
+    rotating = dfm is not None and dfm.shape[-1] == 13 and bool(np.all(np.any(dfm[..., 10:13] != 0, axis=-1)))
+    flops = algorithmic_flops(wl["metric"]["kind"], rule["kind"], work, rotating)
     pass_s = pass_ms / 1e3 / args.steps
     achieved = flops / pass_s / 1e12
     line = {

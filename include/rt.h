@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 3
+#define RT_ABI_VERSION 4
 
 typedef enum rt_status {
     RT_OK = 0,
@@ -97,16 +97,22 @@ const char *rt_last_error(const rt_ctx *ctx);
  *                            Phi = Phi_1 o Phi_2 o ... o Phi_k of local
  *                            deformations (Sec. 6.2, "Composing
  *                            diffeomorphisms"; Phi_k acts first), each
- *                            Phi_i(p) = p + f_i(p) v_i (Eq. 6.2) with f_i
- *                            the anisotropic Gaussian of Eq. 6.1.  The
- *                            Jacobian is the chain-rule product and
+ *                            Phi_i(p) = p + f_i(p) V_i(p) (Eq. 6.2) with f_i
+ *                            the anisotropic Gaussian of Eq. 6.1 and the
+ *                            affine field V_i(p) = v_i + w_i x (p - c_i): a
+ *                            constant direction (w_i = 0) or, with w_i, a
+ *                            local rotation about the axis w_i through c_i.
+ *                            The Jacobian is the chain-rule product and
  *                            D^2 Phi[y, y] is propagated through the chain
  *                            with the pushed-forward velocity (the Hessian
  *                            composition formula of Sec. 6.2 contracted
  *                            with y); flow Eq. 5.8.  Each Phi_i must be a
- *                            diffeomorphism, which holds iff
+ *                            diffeomorphism.  With w_i = 0 that holds iff
  *                            |a| |(vx/sx, vy/sy, vz/sz)| exp(-1/2) < 1;
- *                            rt_set_metric requires <= 0.95.
+ *                            otherwise it holds when the Lipschitz bound
+ *                            |a| (exp(-1/2) |v| / s_min
+ *                                 + |w| (2/e s_max / s_min + 1)) < 1.
+ *                            rt_set_metric requires the bound <= 0.95.
  */
 typedef enum rt_metric_kind {
     RT_METRIC_EUCLID = 0,
@@ -128,7 +134,8 @@ typedef struct rt_deform {
     float a;          /* amplitude of f_i */
     float cx, cy, cz; /* centre */
     float sx, sy, sz; /* spreads along x, y, z, > 0 */
-    float vx, vy, vz; /* deformation direction v_i (its length scales the displacement) */
+    float vx, vy, vz; /* constant part v_i of the field (its length scales the displacement) */
+    float wx, wy, wz; /* rotation part w_i of the field, V_i(p) = v_i + w_i x (p - c_i) */
 } rt_deform;
 
 typedef struct rt_abump {

@@ -128,13 +128,17 @@ class Oracle:
                 b = b[set_index]
             b = b.astype(np.float64)
         self._bumps = np.ascontiguousarray(b.reshape(-1, 5))
+        # deformation rows: a, c, spreads, v and the rotation w of the field
+        # V(p) = v + w x (p - c) (w = 0 when a row has 10 values)
         dfm = metric.get("deforms")
         if dfm is None:
-            dfm = np.zeros((0, 10))
+            dfm = np.zeros((0, 13))
         dfm = np.asarray(dfm, np.float32)
         if dfm.ndim == 3:
             dfm = dfm[set_index]
-        self._deforms = np.ascontiguousarray(dfm.astype(np.float64).reshape(-1, 10))
+        if dfm.shape[-1] == 10:
+            dfm = np.concatenate([dfm, np.zeros(dfm.shape[:-1] + (3,), np.float32)], axis=-1)
+        self._deforms = np.ascontiguousarray(dfm.astype(np.float64).reshape(-1, 13))
         ab = metric.get("abumps")
         ab = np.zeros((0, 7)) if ab is None else np.asarray(ab, np.float32)
         if ab.ndim == 3:

@@ -175,18 +175,23 @@ static void phi_hd(const orc_metric *m, const hd x[3], hd out[3])
 {
     if (m->kind == ORC_PULLBACK_DEFORM) {
         /* Phi = Phi_1 o Phi_2 o ... o Phi_k (Sec. 6.2): Phi_k acts first.
-         * Phi_i(p) = p + f_i(p) v_i (Eq. 6.2), f_i the Gaussian of Eq. 6.1
-         * with amplitude a, centre c and spreads sx, sy, sz. */
+         * Phi_i(p) = p + f_i(p) V_i(p) (Eq. 6.2), f_i the Gaussian of
+         * Eq. 6.1 with amplitude a, centre c and spreads sx, sy, sz, and the
+         * field V_i(p) = v + w x (p - c). */
         hd q[3] = {x[0], x[1], x[2]};
         for (int i = m->n_deforms - 1; i >= 0; i--) {
-            const double *P = m->deforms + 10 * i;
-            hd e = hd_c(0.0);
+            const double *P = m->deforms + 13 * i;
+            hd e = hd_c(0.0), d[3];
             for (int k = 0; k < 3; k++) {
-                hd d = hd_sub(q[k], hd_c(P[1 + k]));
-                e = hd_add(e, hd_scale(hd_mul(d, d), -1.0 / (2.0 * P[4 + k] * P[4 + k])));
+                d[k] = hd_sub(q[k], hd_c(P[1 + k]));
+                e = hd_add(e, hd_scale(hd_mul(d[k], d[k]), -1.0 / (2.0 * P[4 + k] * P[4 + k])));
             }
             hd f = hd_scale(hd_exp(e), P[0]);
-            for (int k = 0; k < 3; k++) q[k] = hd_add(q[k], hd_scale(f, P[7 + k]));
+            const double *w = P + 10;
+            hd V[3] = {hd_add(hd_c(P[7]), hd_sub(hd_scale(d[2], w[1]), hd_scale(d[1], w[2]))),
+                       hd_add(hd_c(P[8]), hd_sub(hd_scale(d[0], w[2]), hd_scale(d[2], w[0]))),
+                       hd_add(hd_c(P[9]), hd_sub(hd_scale(d[1], w[0]), hd_scale(d[0], w[1])))};
+            for (int k = 0; k < 3; k++) q[k] = hd_add(q[k], hd_mul(f, V[k]));
         }
         for (int k = 0; k < 3; k++) out[k] = q[k];
         return;

@@ -30,7 +30,7 @@ typedef struct {
     const double *bumps; /* [n_bumps][5] a, cx, cy, cz, sigma */
     double twist_amp, twist_theta0;
     int n_deforms;
-    const double *deforms; /* [n_deforms][10] a, cx, cy, cz, sx, sy, sz, vx, vy, vz */
+    const double *deforms; /* [n_deforms][13] a, cx, cy, cz, sx, sy, sz, vx, vy, vz, wx, wy, wz */
     int n_abumps;
     const double *abumps;  /* [n_abumps][7] a, cx, cy, cz, sx, sy, sz */
     double quadric[3];     /* f = q0 x^2 + q1 y^2 + q2 z^2 */

@@ -32,6 +32,7 @@ struct rt_ctx {
     // PULLBACK_DEFORM: bound on the Euclidean speed of a g-unit velocity
     // (may be infinite) and on the displacement |Phi(x) - x|
     double deform_vmax = 1.0, deform_disp = 0.0;
+    bool deform_rot = false;  // some deformation's field rotates
     // scene (host copy)
     bool has_scene = false;
     std::vector<rt_sphere> sph;
@@ -233,6 +234,12 @@ static rt_status upload(rt_ctx *c, void **dst, size_t *cap, const void *src, siz
 // geodesic is the preimage of a unit-speed straight line (Sec. 5.2), so it
 // moves at most T + 2 max |Phi(x) - x|, the displacement being at most the
 // sum of |a_j| |v_j| over the balls meeting one ball.
+// Kernel variant of the context's metric: composed deformations with a
+// rotating field run the rotating chain's instantiation.
+static int kernel_kind(const rt_ctx *c) {
+    return c->kind == RT_METRIC_PULLBACK_DEFORM && c->deform_rot ? rti::KERNEL_KIND_DEFORM_ROT : c->kind;
+}
+
 static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
     const int nd = m->n_deforms;
     if (nd < 1 || nd > MAX_BUMPS) return fail(c, RT_EINVAL, "rt_set_metric: n_deforms must be in 1..64");
@@ -241,13 +248,32 @@ static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
         return fail(c, RT_EINVAL, "rt_set_metric: cull_sigmas must be finite and >= 4");
     const size_t n = (size_t)m->n_sets * nd;
     const double e_half = std::exp(-0.5);
+    // Lipschitz bound of f V for a field with a rotation part: with rho the
+    // spread-scaled distance, |grad f| <= |a| rho exp(-rho^2/2) / s_min,
+    // |d| <= s_max rho and rho^2 exp(-rho^2/2) <= 2/e, so
+    // |DF| <= |grad f| (|v| + |om| |d|) + |f| |om|
+    //      <= |a| (exp(-1/2) |v| / s_min + |om| (2/e s_max / s_min + 1)).
+    auto lip = [&](const rt_deform &d) {
+        const double smax = std::max(d.sx, std::max(d.sy, d.sz)), smin = std::min(d.sx, std::min(d.sy, d.sz));
+        const double vn = std::sqrt((double)d.vx * d.vx + (double)d.vy * d.vy + (double)d.vz * d.vz);
+        const double on = std::sqrt((double)d.wx * d.wx + (double)d.wy * d.wy + (double)d.wz * d.wz);
+        return std::fabs((double)d.a) * (e_half * vn / smin + on * (2.0 / std::exp(1.0) * smax / smin + 1.0));
+    };
+    auto rotates = [](const rt_deform &d) { return d.wx != 0.f || d.wy != 0.f || d.wz != 0.f; };
     for (size_t i = 0; i < n; ++i) {
         const rt_deform &d = m->deforms[i];
-        const float v[10] = {d.a, d.cx, d.cy, d.cz, d.sx, d.sy, d.sz, d.vx, d.vy, d.vz};
+        const float v[13] = {d.a, d.cx, d.cy, d.cz, d.sx, d.sy, d.sz, d.vx, d.vy, d.vz, d.wx, d.wy, d.wz};
         for (float x : v)
             if (!finite(x)) return fail(c, RT_EINVAL, "rt_set_metric: non-finite deformation parameter at " + std::to_string(i));
         if (!(d.sx > 0.f && d.sy > 0.f && d.sz > 0.f))
             return fail(c, RT_EINVAL, "rt_set_metric: spreads must be > 0 at deformation " + std::to_string(i));
+        if (rotates(d)) {
+            if (lip(d) > 0.95)
+                return fail(c, RT_EINVAL, "rt_set_metric: deformation " + std::to_string(i) +
+                                              " is not a diffeomorphism with margin (need the Lipschitz bound "
+                                              "|a| (exp(-1/2) |v| / s_min + |w| (2/e s_max / s_min + 1)) <= 0.95)");
+            continue;
+        }
         const double q = (double)d.vx * d.vx / ((double)d.sx * d.sx) + (double)d.vy * d.vy / ((double)d.sy * d.sy) +
                          (double)d.vz * d.vz / ((double)d.sz * d.sz);
         if (std::fabs((double)d.a) * std::sqrt(q) * e_half > 0.95)
@@ -255,8 +281,9 @@ static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
                                           " is not a diffeomorphism with margin (need |a| |v/s| exp(-1/2) <= 0.95)");
     }
     const double cut = m->cull_sigmas;
-    std::vector<float> bf(n * 16, 0.f);
-    std::vector<double> bd(n * 12, 0.0);
+    constexpr int NF = 4 * rti::DEFORM_F4, ND = rti::DEFORM_D;
+    std::vector<float> bf(n * NF, 0.f);
+    std::vector<double> bd(n * ND, 0.0);
     double vmax = 1.0, disp = 0.0;
     for (int set = 0; set < m->n_sets; ++set) {
         const rt_deform *D = m->deforms + (size_t)set * nd;
@@ -265,9 +292,13 @@ static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
             const rt_deform &d = D[i];
             const double smax = std::max(d.sx, std::max(d.sy, d.sz)), smin = std::min(d.sx, std::min(d.sy, d.sz));
             const double vn = std::sqrt((double)d.vx * d.vx + (double)d.vy * d.vy + (double)d.vz * d.vz);
+            const double on = std::sqrt((double)d.wx * d.wx + (double)d.wy * d.wy + (double)d.wz * d.wz);
             R[i] = cut * smax;
-            delta[i] = std::fabs((double)d.a) * vn;
-            kap[i] = delta[i] * e_half / smin;
+            // the largest displacement |f V| <= |a| (|v| + |om| s_max rho exp(-rho^2/2))
+            // <= |a| (|v| + |om| s_max exp(-1/2))
+            delta[i] = std::fabs((double)d.a) * (vn + on * smax * e_half);
+            // a bound on |J_i - I|
+            kap[i] = rotates(d) ? lip(d) : delta[i] * e_half / smin;
         }
         auto dist = [&](int i, int j) {
             const double dx = (double)D[i].cx - D[j].cx, dy = (double)D[i].cy - D[j].cy, dz = (double)D[i].cz - D[j].cz;
@@ -295,13 +326,20 @@ static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
             const double s[3] = {1.0 / ((double)d.sx * d.sx), 1.0 / ((double)d.sy * d.sy), 1.0 / ((double)d.sz * d.sz)};
             const double smin = std::min(d.sx, std::min(d.sy, d.sz));
             // slack and displacement rounded up so that the float tests stay conservative
-            const float f[16] = {d.cx, d.cy, d.cz, d.a, (float)s[0], (float)s[1], (float)s[2], 0.f,
+            const double smax = std::max(d.sx, std::max(d.sy, d.sz));
+            const double av = std::fabs((double)d.a) *
+                              std::sqrt((double)d.vx * d.vx + (double)d.vy * d.vy + (double)d.vz * d.vz);
+            const double aw = std::fabs((double)d.a) * smax *
+                              std::sqrt((double)d.wx * d.wx + (double)d.wy * d.wy + (double)d.wz * d.wz);
+            const float f[NF] = {d.cx, d.cy, d.cz, d.a, (float)s[0], (float)s[1], (float)s[2], 0.f,
                                  d.vx, d.vy, d.vz, (float)(cut * cut),
-                                 (float)((rb[i] - R[i]) / smin * (1.0 + 1e-6)), (float)(delta[i] * (1.0 + 1e-6)),
-                                 (float)(1.0 / smin * (1.0 + 1e-6)), 0.f};
-            const double g[12] = {d.cx, d.cy, d.cz, d.a, s[0], s[1], s[2], cut * cut, d.vx, d.vy, d.vz, 0.0};
-            std::copy(f, f + 16, bf.begin() + o * 16);
-            std::copy(g, g + 12, bd.begin() + o * 12);
+                                 (float)((rb[i] - R[i]) / smin * (1.0 + 1e-6)), (float)(av * (1.0 + 1e-6)),
+                                 (float)(1.0 / smin * (1.0 + 1e-6)), (float)(aw * (1.0 + 1e-6)),
+                                 d.wx, d.wy, d.wz, 0.f};
+            const double g[ND] = {d.cx, d.cy, d.cz, d.a, s[0], s[1], s[2], cut * cut,
+                                  d.vx, d.vy, d.vz, 0.0, d.wx, d.wy, d.wz, 0.0};
+            std::copy(f, f + NF, bf.begin() + o * NF);
+            std::copy(g, g + ND, bd.begin() + o * ND);
         }
     }
     if (!c->host_only) {
@@ -322,6 +360,7 @@ static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
     c->bumps.clear();
     c->deform_vmax = vmax;
     c->deform_disp = disp;
+    c->deform_rot = std::any_of(m->deforms, m->deforms + n, rotates);
     c->has_metric = true;
     c->surr_sb_dirty = true;
     c->adj_valid = false;
@@ -740,7 +779,7 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     if (st != RT_OK) return st;
 
     rti::TraceArgs a{};
-    a.kind = c->kind;
+    a.kind = kernel_kind(c);
     a.n_sets = c->n_sets;
     a.n_bumps = c->n_bumps;
     a.twist_amp = c->amp;
@@ -893,7 +932,7 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     rti::IllumArgs a{};
-    a.kind = c->kind;
+    a.kind = kernel_kind(c);
     a.n_sets = c->n_sets;
     a.n_bumps = c->n_bumps;
     a.twist_amp = c->amp;

@@ -12,7 +12,12 @@
 
 namespace rtd {
 
-enum { KIND_EUCLID = 0, KIND_GRAPH = 1, KIND_TWIST = 2, KIND_ZTWIST = 3, KIND_DEFORM = 4, KIND_GANISO = 5, KIND_GQUAD = 6 };
+enum { KIND_EUCLID = 0, KIND_GRAPH = 1, KIND_TWIST = 2, KIND_ZTWIST = 3, KIND_DEFORM = 4, KIND_GANISO = 5, KIND_GQUAD = 6,
+       // composed deformations with at least one rotating field: the same
+       // metric kind, compiled separately so that the constant-field chain
+       // keeps its registers
+       KIND_DEFORM_ROT = 7 };
+constexpr bool is_deform(int kind) { return kind == KIND_DEFORM || kind == KIND_DEFORM_ROT; }
 enum { STEP_RK4 = 0, STEP_RK45 = 1, STEP_EULER = 2 };
 
 constexpr int MAX_BUMPS = 64;
@@ -386,36 +391,42 @@ template <class T> __device__ __forceinline__ T ztwist_gdd(V3<T> x, V3<T> d) {
 
 // ---------------------------------------------- composed local deformations
 // Phi = Phi_1 o ... o Phi_k (Sec. 6.2, "Composing diffeomorphisms"),
-// Phi_i(q) = q + f_i(q) v_i (Eq. 6.2), f_i = a exp(-d^T S d / 2) with
-// d = q - c and S = diag(1/sx^2, 1/sy^2, 1/sz^2) (Eq. 6.1).  Walking the
-// chain from Phi_k (applied first) to Phi_1 with the point q, the pushed-
-// forward velocity u = J(Phi_[i+1,k]) y and w = D^2 Phi_[i+1,k][y, y]:
-//   grad f = -f S d,   u^T H(f) u = f ((S d . u)^2 - u^T S u)
-//   w <- w + v (grad f . w + u^T H(f) u)   (= J_i w + D^2 Phi_i[u, u])
-//   u <- u + v (grad f . u),   q <- q + f v,   M <- M + v (grad f^T M)
+// Phi_i(q) = q + f_i(q) V_i(q) (Eq. 6.2), f_i = a exp(-d^T S d / 2) with
+// d = q - c and S = diag(1/sx^2, 1/sy^2, 1/sz^2) (Eq. 6.1), and the affine
+// field V_i(q) = v + om x d (om = 0: a constant direction).  With
+// grad f = -f S d and u^T H(f) u = f ((S d . u)^2 - u^T S u), Phi_i has
+//   J_i = I + V grad f^T + f [om]x,
+//   D^2 Phi_i[u, u] = V (u^T H(f) u) + 2 (grad f . u) (om x u).
+// Walking the chain from Phi_k (applied first) to Phi_1 with the point q,
+// the pushed-forward velocity u = J(Phi_[i+1,k]) y and w = D^2 Phi_[i+1,k][y, y]:
+//   w <- J_i w + D^2 Phi_i[u, u],   u <- J_i u,   q <- q + f V,   M <- J_i M
 // leaves M = J(Phi) (the chain rule product) and w = D^2 Phi[y, y]: the
 // Hessian composition formula of Sec. 6.2 contracted with y on both sides.
 // Then y' = -M^-1 w (Eq. 5.8).  Where the spread-scaled squared distance
 // exceeds cut2, Phi_i is the identity (f = 0), so every lane's result is
 // the same for any superset mask.  Bit i of the mask is Phi_{i+1}.
-// Parameters: float, four float4 per deformation
+// Parameters: float, DEFORM_F4 = 5 float4 per deformation
 // (cx, cy, cz, a), (1/sx^2, 1/sy^2, 1/sz^2, 0), (vx, vy, vz, cut2),
-// (slack / min spread, |a| |v|, 1 / min spread, 0) with slack the largest
-// displacement of a point by the deformations applied before this one where
-// they can bring it into this one's region;
-// double, twelve values (cx, cy, cz, a, 1/sx^2, 1/sy^2, 1/sz^2, cut2, vx, vy, vz, 0).
+// (slack / min spread, |a| |v|, 1 / min spread, |a| |om| s_max),
+// (omx, omy, omz, 0) with slack the largest displacement of a point by the
+// deformations applied before this one where they can bring it into this
+// one's region; at spread-scaled distance >= rho,
+// |f V| <= (|a| |v| + |a| |om| s_max max(rho, 1)) exp(-rho^2 / 2);
+// double, DEFORM_D = 16 values (cx, cy, cz, a, 1/sx^2, 1/sy^2, 1/sz^2, cut2,
+// vx, vy, vz, 0, omx, omy, omz, 0).
+constexpr int DEFORM_F4 = 5, DEFORM_D = 16;
 template <class T> struct Deform {
-    V3<T> c, s, v;
+    V3<T> c, s, v, om;
     T a, cut2;
 };
 __device__ __forceinline__ Deform<float> deform_at(const float4 *__restrict__ B, int i) {
-    const float4 *q = (const float4 *)((const char *)B + (unsigned)i * 64u);
-    const float4 d0 = q[0], d1 = q[1], d2 = q[2];
-    return {mk(d0.x, d0.y, d0.z), mk(d1.x, d1.y, d1.z), mk(d2.x, d2.y, d2.z), d0.w, d2.w};
+    const float4 *q = B + (unsigned)i * (unsigned)DEFORM_F4;
+    const float4 d0 = q[0], d1 = q[1], d2 = q[2], d4 = q[4];
+    return {mk(d0.x, d0.y, d0.z), mk(d1.x, d1.y, d1.z), mk(d2.x, d2.y, d2.z), mk(d4.x, d4.y, d4.z), d0.w, d2.w};
 }
 __device__ __forceinline__ Deform<double> deform_at(const double *__restrict__ B, int i) {
-    const double *q = B + 12 * i;
-    return {mk(q[0], q[1], q[2]), mk(q[4], q[5], q[6]), mk(q[8], q[9], q[10]), q[3], q[7]};
+    const double *q = B + DEFORM_D * i;
+    return {mk(q[0], q[1], q[2]), mk(q[4], q[5], q[6]), mk(q[8], q[9], q[10]), mk(q[12], q[13], q[14]), q[3], q[7]};
 }
 
 // Spread-scaled distance from the box [lo, hi] to the centre of an
@@ -446,7 +457,11 @@ __device__ __forceinline__ float deform_box_rho(const float4 *__restrict__ P, co
 // One deformation of the chain; returns f (0 outside the cut).  WAVE: when
 // no active lane of the wave is inside the cut, the whole wave skips the
 // update, which is the identity there.
-template <class T, bool WAVE = false>
+template <class T> __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+template <class T, bool WAVE = false, bool ROT = false>
 __device__ __forceinline__ T deform_apply(const Deform<T> &D, V3<T> &q, V3<T> &u, V3<T> &w, T M[9]) {
     const V3<T> d = mk(q.x - D.c.x, q.y - D.c.y, q.z - D.c.z);
     const V3<T> Sd = mk(D.s.x * d.x, D.s.y * d.y, D.s.z * d.z);
@@ -461,16 +476,30 @@ __device__ __forceinline__ T deform_apply(const Deform<T> &D, V3<T> &q, V3<T> &u
     const T m0 = g.x * M[0] + g.y * M[3] + g.z * M[6];
     const T m1 = g.x * M[1] + g.y * M[4] + g.z * M[7];
     const T m2 = g.x * M[2] + g.y * M[5] + g.z * M[8];
-    w = axpy(cw, D.v, w);
-    u = axpy(cu, D.v, u);
-    q = axpy(f, D.v, q);
-    M[0] += D.v.x * m0; M[1] += D.v.x * m1; M[2] += D.v.x * m2;
-    M[3] += D.v.y * m0; M[4] += D.v.y * m1; M[5] += D.v.y * m2;
-    M[6] += D.v.z * m0; M[7] += D.v.z * m1; M[8] += D.v.z * m2;
+    // ROT: the rotation part, from the old u, w, M before they are updated
+    V3<T> V = D.v;
+    if constexpr (ROT) {
+        const V3<T> ou = cross(D.om, u), ow = cross(D.om, w);
+        const V3<T> oc0 = cross(D.om, mk(M[0], M[3], M[6]));
+        const V3<T> oc1 = cross(D.om, mk(M[1], M[4], M[7]));
+        const V3<T> oc2 = cross(D.om, mk(M[2], M[5], M[8]));
+        V = V + cross(D.om, d);
+        w = w + (T(2) * cu) * ou + f * ow;
+        u = u + f * ou;
+        M[0] += f * oc0.x; M[1] += f * oc1.x; M[2] += f * oc2.x;
+        M[3] += f * oc0.y; M[4] += f * oc1.y; M[5] += f * oc2.y;
+        M[6] += f * oc0.z; M[7] += f * oc1.z; M[8] += f * oc2.z;
+    }
+    w = axpy(cw, V, w);
+    u = axpy(cu, V, u);
+    q = axpy(f, V, q);
+    M[0] += V.x * m0; M[1] += V.x * m1; M[2] += V.x * m2;
+    M[3] += V.y * m0; M[4] += V.y * m1; M[5] += V.y * m2;
+    M[6] += V.z * m0; M[7] += V.z * m1; M[8] += V.z * m2;
     return f;
 }
 
-template <class T, bool COUNT = false, class PB>
+template <class T, bool COUNT = false, bool ROT = false, class PB>
 __device__ __forceinline__ bool deform_accel(PB B, uint64_t mask, V3<T> p, V3<T> y, V3<T> &acc,
                                              unsigned *n_in = nullptr) {
     V3<T> q = p, u = y, w = mk(T(0), T(0), T(0));
@@ -479,7 +508,7 @@ __device__ __forceinline__ bool deform_accel(PB B, uint64_t mask, V3<T> p, V3<T>
     while (mask) {
         const int i = 63 - __builtin_clzll(mask);
         mask &= ~(1ull << i);
-        const T f = deform_apply<T, sizeof(T) == 4>(deform_at(B, i), q, u, w, M);
+        const T f = deform_apply<T, sizeof(T) == 4, ROT>(deform_at(B, i), q, u, w, M);
         if (COUNT) n += f != T(0) ? 1u : 0u;
     }
     if (COUNT) *n_in += n;
@@ -496,10 +525,10 @@ __device__ __forceinline__ bool deform_accel(PB B, uint64_t mask, V3<T> p, V3<T>
 }
 
 // |J d|^2 for the chain of the first n deformations (initial speed normalisation).
-template <class T, class PB> __device__ __forceinline__ T deform_gdd(PB B, int n, V3<T> p, V3<T> d) {
+template <class T, bool ROT = false, class PB> __device__ __forceinline__ T deform_gdd(PB B, int n, V3<T> p, V3<T> d) {
     V3<T> q = p, u = d, w = mk(T(0), T(0), T(0));
     T M[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
-    for (int i = n - 1; i >= 0; --i) (void)deform_apply(deform_at(B, i), q, u, w, M);
+    for (int i = n - 1; i >= 0; --i) (void)deform_apply<T, false, ROT>(deform_at(B, i), q, u, w, M);
     return dot(u, u);
 }
 

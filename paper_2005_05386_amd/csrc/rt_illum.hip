@@ -246,7 +246,7 @@ __device__ __forceinline__ Pixel<KIND> pixel(const rti::IllumArgs &A, const floa
         P.Bs = BF;
     } else {
         const int set = pix / (A.width * A.height);
-        P.Bs = BF + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
+        P.Bs = BF + (int64_t)set * A.n_bumps * (is_deform(KIND) ? DEFORM_F4 : 2);
     }
     P.q = mk(A.hit[3 * pix], A.hit[3 * pix + 1], A.hit[3 * pix + 2]);
     P.F = light_frame(P.q, mk(A.light[0], A.light[1], A.light[2]));
@@ -560,6 +560,7 @@ hipError_t launch_illum(const IllumArgs &a, const DeviceData &d, int grid, hipSt
         RT_ILLUM(KIND_TWIST)
         RT_ILLUM(KIND_ZTWIST)
         RT_ILLUM(KIND_DEFORM)
+        RT_ILLUM(KIND_DEFORM_ROT)
         RT_ILLUM(KIND_GANISO)
         RT_ILLUM(KIND_GQUAD)
 #undef RT_ILLUM

@@ -157,6 +157,14 @@ struct DeviceData {
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid_blocks,
                         int refine_blocks, hipStream_t s, hipEvent_t *ev, const struct SurrArgs *S, int mlp_blocks);
 // ------------------------------------------------------ direct illumination
+// Table strides of a composed deformation: float4 records (FP32 table) and
+// doubles (FP64 table) per deformation; the device helpers read the same
+// layout.
+constexpr int DEFORM_F4 = 5, DEFORM_D = 16;
+// Kernel kind of composed deformations with a rotating field (the API kind
+// is RT_METRIC_PULLBACK_DEFORM; the kernels compile the rotation terms
+// only for this kind).
+constexpr int KERNEL_KIND_DEFORM_ROT = 7;
 // Steps between the culling windows of the illumination's shots.
 constexpr int ILLUM_CULL_EVERY = 16;
 struct IllumArgs {

@@ -178,8 +178,8 @@ template <int KIND, bool COUNT, bool SREG = false, bool WAVE = false> struct Acc
         } else if constexpr (KIND == KIND_ZTWIST) {
             a = ztwist_accel<float>(p, y);
             return true;
-        } else if constexpr (KIND == KIND_DEFORM) {
-            return deform_accel<float, COUNT>(B, mask, p, y, a, n_bump);
+        } else if constexpr (is_deform(KIND)) {
+            return deform_accel<float, COUNT, KIND == KIND_DEFORM_ROT>(B, mask, p, y, a, n_bump);
         } else if constexpr (KIND == KIND_GANISO) {
             a = graph_aniso_accel<float, COUNT, WAVE>(B, mask, p, y, n_bump);
             return true;
@@ -208,8 +208,8 @@ __device__ __forceinline__ float metric_gdd(const float4 *__restrict__ Bs, int n
         return twist_gdd<float>(amp, th0, x, d);
     } else if constexpr (KIND == KIND_ZTWIST) {
         return ztwist_gdd<float>(x, d);
-    } else if constexpr (KIND == KIND_DEFORM) {
-        return deform_gdd<float>(Bs, n, x, d);
+    } else if constexpr (is_deform(KIND)) {
+        return deform_gdd<float, KIND == KIND_DEFORM_ROT>(Bs, n, x, d);
     } else if constexpr (KIND == KIND_GANISO) {
         // g(d, d) = |d|^2 + (grad f . d)^2
         float gd = 0.f;

@@ -28,6 +28,10 @@
 using namespace rtd;
 using rti::TraceArgs;
 
+static_assert(rtd::DEFORM_F4 == rti::DEFORM_F4 && rtd::DEFORM_D == rti::DEFORM_D,
+              "device and host deformation table strides differ");
+static_assert(rtd::KIND_DEFORM_ROT == rti::KERNEL_KIND_DEFORM_ROT, "rotating deformation kind differs");
+
 namespace {
 
 __device__ __forceinline__ void write_out(const TraceArgs &A, unsigned oi, V3<float> x, float t, V3<float> y, int id,
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
         const int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
         const int pi = tx * 8 + (ln & 7), pj = ty * 8 + (ln >> 3);
         if (pi >= A.width || pj >= A.height) continue;
-        const float4 *__restrict__ Bs = BF + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
+        const float4 *__restrict__ Bs = BF + (int64_t)set * A.n_bumps * (is_deform(KIND) ? DEFORM_F4 : 2);
         float su = (2.0f * ((float)pi + 0.5f) / (float)A.width - 1.0f) * A.tan_half * A.aspect;
         float sv = (1.0f - 2.0f * ((float)pj + 0.5f) / (float)A.height) * A.tan_half;
         V3<float> d = mk(su * A.right[0] + sv * A.up[0] + A.fwd[0], su * A.right[1] + sv * A.up[1] + A.fwd[1],
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
             const int pi = tx * 8 + (tl_lane & 7), pj = ty * 8 + (tl_lane >> 3);
             if (pass == 0) valid = pi < A.width && pj < A.height;
             const int pix = pj * A.width + pi;
-            const float4 *__restrict__ Bs = BF + (int64_t)set * n_bumps * (KIND == KIND_DEFORM ? 4 : 2);
+            const float4 *__restrict__ Bs = BF + (int64_t)set * n_bumps * (is_deform(KIND) ? DEFORM_F4 : 2);
             const unsigned qbase = (unsigned)set * (unsigned)HW;
 
             V3<float> xh, xl, y;
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                                               wave_max(act ? p.z : -inf)};
                         float m = A.cull_margin;
                         float disp = A.cull_disp;  // DEFORM: bound on |Phi(x) - x| in the window
-                        if constexpr (KIND == KIND_DEFORM) {
+                        if constexpr (is_deform(KIND)) {
                             // A geodesic is the preimage of a unit-speed line, so in the
                             // window it moves at most T + 2 max |Phi(x) - x|.  Deformation i
                             // moves a point q by |f_i(q)| |v_i| <= |a_i| |v_i| exp(-rho^2 / 2),
@@ -236,9 +240,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                                 const float hi0[3] = {pmx[0] + m, pmx[1] + m, pmx[2] + m};
                                 float dl = 0.f;
                                 if (lane < n_bumps) {
-                                    const float rho = deform_box_rho(Bs + 4 * lane, lo0, hi0, disp);
-                                    if (rho * rho <= Bs[4 * lane + 2].w * 1.00001f)
-                                        dl = Bs[4 * lane + 3].y * exp2_(-0.5f * 1.44269504f * rho * rho);
+                                    const float rho = deform_box_rho(Bs + DEFORM_F4 * lane, lo0, hi0, disp);
+                                    if (rho * rho <= Bs[DEFORM_F4 * lane + 2].w * 1.00001f) {
+                                        // |f V| <= (|a||v| + |a||om| s_max max(rho, 1)) exp(-rho^2 / 2)
+                                        // beyond spread-scaled distance rho
+                                        const float4 d3 = Bs[DEFORM_F4 * lane + 3];
+                                        dl = fmaf(d3.w, fmaxf(rho, 1.0f), d3.y) *
+                                             exp2_(-0.5f * 1.44269504f * rho * rho);
+                                    }
                                 }
 #pragma unroll
                                 for (int o = 32; o >= 1; o >>= 1) dl += __shfl_xor(dl, o);
@@ -262,10 +271,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                             const float4 b0 = Bs[2 * lane], b1 = Bs[2 * lane + 1];
                             const float rho = aniso_box_rho(b0, b1, lo, hi);
                             need = rho * rho <= b1.w * 1.00001f;
-                        } else if (KIND == KIND_DEFORM && lane < n_bumps) {
+                        } else if (is_deform(KIND) && lane < n_bumps) {
                             // the ball (in ray coordinates) where the deformation can act
-                            const float rho = deform_box_rho(Bs + 4 * lane, lo, hi, disp);
-                            need = rho * rho <= Bs[4 * lane + 2].w * 1.00001f;
+                            const float rho = deform_box_rho(Bs + DEFORM_F4 * lane, lo, hi, disp);
+                            need = rho * rho <= Bs[DEFORM_F4 * lane + 2].w * 1.00001f;
                         }
                         bmask = ballot(need);
 #pragma unroll
@@ -652,7 +661,7 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
         double tk_lo = r3.w;
         uint64_t mask = (uint64_t)(uint32_t)__float_as_int(r4.x) | ((uint64_t)(uint32_t)__float_as_int(r4.y) << 32);
         int set = oi / HW;
-        const double *Bs = BD + (int64_t)set * A.n_bumps * (KIND == KIND_DEFORM ? 12 : 8);
+        const double *Bs = BD + (int64_t)set * A.n_bumps * (is_deform(KIND) ? DEFORM_D : 8);
         double amp = A.twist_amp, th0 = A.twist_theta0;
         auto acc = [&](V3<double> p, V3<double> v, V3<double> &a) -> bool {
             if constexpr (KIND == KIND_GRAPH) {
@@ -663,8 +672,8 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
             } else if constexpr (KIND == KIND_ZTWIST) {
                 a = ztwist_accel<double>(p, v);
                 return true;
-            } else if constexpr (KIND == KIND_DEFORM) {
-                return deform_accel<double>(Bs, mask, p, v, a);
+            } else if constexpr (is_deform(KIND)) {
+                return deform_accel<double, false, KIND == KIND_DEFORM_ROT>(Bs, mask, p, v, a);
             } else if constexpr (KIND == KIND_GANISO) {
                 a = graph_aniso_accel<double>(Bs, mask, p, v);
                 return true;
@@ -894,7 +903,7 @@ template <int KIND, int STEP> int occ() {
 namespace rti {
 
 bool supported(int kind, int step) {
-    return kind >= 0 && kind <= 6 && step >= 0 && step <= 2;
+    return kind >= 0 && kind <= 7 && step >= 0 && step <= 2;
 }
 
 #define RT_DISPATCH(KIND, FN, ...)                                                 \
@@ -911,6 +920,7 @@ int trace_blocks_per_cu(int kind, int step) {
     case KIND_TWIST: RT_DISPATCH(KIND_TWIST, occ)
     case KIND_ZTWIST: RT_DISPATCH(KIND_ZTWIST, occ)
     case KIND_DEFORM: RT_DISPATCH(KIND_DEFORM, occ)
+    case KIND_DEFORM_ROT: RT_DISPATCH(KIND_DEFORM_ROT, occ)
     case KIND_GANISO: RT_DISPATCH(KIND_GANISO, occ)
     default: RT_DISPATCH(KIND_GQUAD, occ)
     }
@@ -933,6 +943,7 @@ hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, i
     case KIND_TWIST: RT_DISPATCH(KIND_TWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_ZTWIST: RT_DISPATCH(KIND_ZTWIST, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_DEFORM: RT_DISPATCH(KIND_DEFORM, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
+    case KIND_DEFORM_ROT: RT_DISPATCH(KIND_DEFORM_ROT, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     case KIND_GANISO: RT_DISPATCH(KIND_GANISO, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     default: RT_DISPATCH(KIND_GQUAD, launch_kind_step, a, d, n_passes, grid, rgrid, s, ev, S, mlp_blocks)
     }

@@ -198,9 +198,16 @@ class Tracer:
         if b.ndim == 2:
             b = b[None]
         n_sets, n_bumps = b.shape[0], b.shape[1]
+        # deformation rows: a, c (3), spreads (3), v (3) and the optional
+        # rotation w (3) of the field V(p) = v + w x (p - c), zero if absent
         d = metric.get("deforms")
-        d = np.zeros((1, 0, 10), np.float32) if d is None else np.asarray(d, np.float32)
-        d = np.ascontiguousarray(d[None] if d.ndim == 2 else d)
+        d = np.zeros((1, 0, 13), np.float32) if d is None else np.asarray(d, np.float32)
+        d = d[None] if d.ndim == 2 else d
+        if d.shape[-1] == 10:
+            d = np.concatenate([d, np.zeros(d.shape[:-1] + (3,), np.float32)], axis=-1)
+        if d.shape[-1] != 13:
+            raise ValueError("deformation rows must have 10 or 13 values")
+        d = np.ascontiguousarray(d)
         ab = metric.get("abumps")
         ab = np.zeros((1, 0, 7), np.float32) if ab is None else np.asarray(ab, np.float32)
         ab = np.ascontiguousarray(ab[None] if ab.ndim == 2 else ab)

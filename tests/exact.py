@@ -147,13 +147,19 @@ def ztwist_inv(X):
 
 
 def deform_phi(x, deforms):
-    """Phi = Phi_1 o ... o Phi_k, Phi_i(p) = p + f_i(p) v_i (Sec. 6.2,
-    Eqs. 6.1-6.2); rows (a, cx, cy, cz, sx, sy, sz, vx, vy, vz), Phi_k
-    applied first (complex-safe)."""
+    """Phi = Phi_1 o ... o Phi_k, Phi_i(p) = p + f_i(p) V_i(p) (Sec. 6.2,
+    Eqs. 6.1-6.2) with V_i(p) = v + w x (p - c); rows (a, cx, cy, cz, sx,
+    sy, sz, vx, vy, vz[, wx, wy, wz]), Phi_k applied first (complex-safe)."""
+    d = np.asarray(deforms, np.float64)
+    d = d.reshape(-1, d.shape[-1])
+    if d.shape[1] == 10:
+        d = np.concatenate([d, np.zeros((d.shape[0], 3))], axis=1)
     q = [x[0], x[1], x[2]]
-    for a, cx, cy, cz, sx, sy, sz, vx, vy, vz in np.asarray(deforms, np.float64).reshape(-1, 10)[::-1]:
-        f = a * np.exp(-0.5 * (((q[0] - cx) / sx) ** 2 + ((q[1] - cy) / sy) ** 2 + ((q[2] - cz) / sz) ** 2))
-        q = [q[0] + f * vx, q[1] + f * vy, q[2] + f * vz]
+    for a, cx, cy, cz, sx, sy, sz, vx, vy, vz, wx, wy, wz in d[::-1]:
+        dx, dy, dz = q[0] - cx, q[1] - cy, q[2] - cz
+        f = a * np.exp(-0.5 * ((dx / sx) ** 2 + (dy / sy) ** 2 + (dz / sz) ** 2))
+        V = (vx + (wy * dz - wz * dy), vy + (wz * dx - wx * dz), vz + (wx * dy - wy * dx))
+        q = [q[0] + f * V[0], q[1] + f * V[1], q[2] + f * V[2]]
     return np.array(q)
 
 

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(rt.lib(), n), n
     assert sorted(rt.EXPORTS) == names
-    assert rt.abi_version() == 3
+    assert rt.abi_version() == 4
 
 
 def test_host_only_context_validates():
@@ -123,6 +123,18 @@ def test_metric_and_scene_validation():
     for n in (0, 65):
         with pytest.raises(rt.RtError) as e:
             tr.set_metric(W.metric(W.PULLBACK_DEFORM, deforms=W.random_deforms(n, 0).reshape(n, 10)))
+        assert e.value.status == rt.RT_EINVAL
+    # rotating fields: accepted as generated; rejected when the rotation
+    # pushes the Lipschitz bound past the margin or is not finite
+    rd = W.random_deforms(5, 0, rot=(0.3, 0.5))
+    assert rd.shape == (5, 13)
+    tr.set_metric(W.metric(W.PULLBACK_DEFORM, deforms=rd))
+    for mod in [lambda x: x.__setitem__((3, 10), 20.0 * x[3, 10] + 20.0),
+                lambda x: x.__setitem__((4, 12), np.inf)]:
+        dd = rd.copy()
+        mod(dd)
+        with pytest.raises(rt.RtError) as e:
+            tr.set_metric(W.metric(W.PULLBACK_DEFORM, deforms=dd))
         assert e.value.status == rt.RT_EINVAL
     # anisotropic bumps and the quadric
     ab = W.random_abumps(4, 0)

@@ -244,18 +244,21 @@ def test_ztwist_small(rt):
 
 
 # --------------------------------------- composed local deformations (Sec. 6.2)
-def test_deform_small_full_frame(rt):
-    say("deform16 (16 composed local deformations) 96x54 full frame")
-    wl = W.with_size(W.get("deform16_1080p"), 96, 54)
+# deform16: constant fields; rdeform16: fields with a rotation part
+@pytest.mark.parametrize("name", ["deform16_1080p", "rdeform16_1080p"])
+def test_deform_small_full_frame(rt, name):
+    say("%s (16 composed local deformations) 96x54 full frame" % name)
+    wl = W.with_size(W.get(name), 96, 54)
     g = gpu_trace(rt, wl)
     rep = compare(g, oracle_trace(wl))
     say(rep)
     assert_parity(rep)
 
 
-def test_deform_1080p_sampled(rt):
-    say("deform16_1080p full frame, 1000 sampled pixels")
-    wl = W.get("deform16_1080p")
+@pytest.mark.parametrize("name", ["deform16_1080p", "rdeform16_1080p"])
+def test_deform_1080p_sampled(rt, name):
+    say("%s full frame, 1000 sampled pixels" % name)
+    wl = W.get(name)
     g = gpu_trace(rt, wl)
     pix = W.pixel_sample(1920, 1080, 1000, seed=4)
     rep = compare(g, oracle_trace(wl, pix), pix)
@@ -263,36 +266,37 @@ def test_deform_1080p_sampled(rt):
     assert_parity(rep)
 
 
-def _strong_deform_wl(w=96, h=64):
+def _strong_deform_wl(w=96, h=64, rotating=False):
     """Six strong, overlapping deformations around the origin (the oracle
-    pins' set): the order of the composition matters and the culling bounds
-    are far from trivial."""
-    from tests.test_oracle_pins import DEFORMS
+    pins' sets, with constant or rotating fields): the order of the
+    composition matters and the culling bounds are far from trivial."""
+    from tests.test_oracle_pins import DEFORMS, RDEFORMS
     wl = W.with_size(W.get("single_bump_64"), w, h)
-    wl["metric"] = W.metric(W.PULLBACK_DEFORM, deforms=DEFORMS)
+    wl["metric"] = W.metric(W.PULLBACK_DEFORM, deforms=RDEFORMS if rotating else DEFORMS)
     wl["scene"] = W.scene(spheres=W.random_spheres(24, 1, box=1.5, radius=(0.1, 0.3)),
                           planes=W.PLANE_Y_MINUS_1, tori=W.TORUS_Z)
     wl["rule"] = dict(wl["rule"], h=0.005, max_steps=2000, t_max=10.0)
     return wl
 
 
-def test_deform_strong_small(rt):
-    say("strong overlapping deformations 96x64")
-    wl = _strong_deform_wl()
+@pytest.mark.parametrize("rotating", [False, True])
+def test_deform_strong_small(rt, rotating):
+    say("strong overlapping deformations 96x64, rotating fields %s" % rotating)
+    wl = _strong_deform_wl(rotating=rotating)
     g = gpu_trace(rt, wl)
     rep = compare(g, oracle_trace(wl))
     say(rep, g["_stats"])
     assert_parity(rep)
 
 
-@pytest.mark.parametrize("K,S", [(4, 64), (64, 2000)])
-def test_deform_deterministic_across_culling(rt, K, S):
+@pytest.mark.parametrize("K,S,rotating", [(4, 64, False), (64, 2000, False), (4, 64, True)])
+def test_deform_deterministic_across_culling(rt, K, S, rotating):
     """The per-lane cut makes each deformation the identity outside its
     region, so any superset list gives the same arithmetic: a culling period
     or pass length change must leave the frame bitwise unchanged (a list
     that missed a deformation a lane needs would change it)."""
-    say("deform determinism K=%d S=%d" % (K, S))
-    wl = _strong_deform_wl(64, 40)
+    say("deform determinism K=%d S=%d rotating fields %s" % (K, S, rotating))
+    wl = _strong_deform_wl(64, 40, rotating=rotating)
     ref = gpu_trace(rt, wl)
     g = gpu_trace(rt, wl, rule=dict(wl["rule"], cull_every=K, pass_steps=S))
     for k in ("hit", "t", "id", "dir", "steps"):

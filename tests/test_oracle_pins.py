@@ -186,15 +186,20 @@ def test_sign_invariance_is_bitwise():
 # Strong local deformations around the origin (six of them, overlapping, so
 # that the order of the composition matters).
 DEFORMS = W.random_deforms(6, seed=21, box=0.8, spread=(0.4, 0.9), kappa=(0.4, 0.8))
+# The same with fields that also rotate about an axis through each centre.
+RDEFORMS = W.random_deforms(6, seed=22, box=0.8, spread=(0.4, 0.9), kappa=(0.2, 0.4), rot=(0.3, 0.5))
+ROTATING = "rotating deformations"
 
 
 def _pullback(kind):
     if kind == W.PULLBACK_DEFORM:
         return W.metric(kind, deforms=DEFORMS), lambda z: exact.deform_phi(z, DEFORMS)
+    if kind == ROTATING:
+        return W.metric(W.PULLBACK_DEFORM, deforms=RDEFORMS), lambda z: exact.deform_phi(z, RDEFORMS)
     return W.metric(kind), (exact.twist_phi if kind == W.PULLBACK_TWIST else exact.ztwist_phi)
 
 
-PULLBACKS = [W.PULLBACK_TWIST, W.PULLBACK_ZTWIST, W.PULLBACK_DEFORM]
+PULLBACKS = [W.PULLBACK_TWIST, W.PULLBACK_ZTWIST, W.PULLBACK_DEFORM, ROTATING]
 
 
 @pytest.mark.parametrize("kind", PULLBACKS)
@@ -269,6 +274,34 @@ def test_deform_diffeomorphism_margin():
         assert kap < 0.95
         assert (1.0 + gv).min() > 0.0
         assert np.isclose(np.abs(gv).max(), kap, rtol=0.05)
+
+
+def test_rotating_deformation_lipschitz_margin():
+    """Each Phi_i of the rotating generator has |D(f V)| <= kappa + share
+    < 1 (spectral norm, brute force on a grid around each centre), so it is
+    a diffeomorphism; and the rotation part is not negligible."""
+    rot_part = 0.0
+    for a, cx, cy, cz, sx, sy, sz, vx, vy, vz, wx, wy, wz in RDEFORMS.astype(np.float64):
+        s = np.array([sx, sy, sz])
+        v, w = np.array([vx, vy, vz]), np.array([wx, wy, wz])
+        bound = abs(a) * (np.exp(-0.5) * np.linalg.norm(v) / s.min()
+                          + np.linalg.norm(w) * (2.0 / np.e * s.max() / s.min() + 1.0))
+        assert bound <= 0.95
+        W_ = np.array([[0.0, -wz, wy], [wz, 0.0, -wx], [-wy, wx, 0.0]])
+        worst = 0.0
+        grid = np.linspace(-3, 3, 13)
+        for i in grid:
+            for j in grid:
+                for k in grid:
+                    d = np.array([i, j, k]) * s
+                    f = a * np.exp(-0.5 * ((d / s) ** 2).sum())
+                    gf = -f * d / s ** 2
+                    DF = np.outer(v + np.cross(w, d), gf) + f * W_
+                    worst = max(worst, np.linalg.norm(DF, 2))
+                    rot_part = max(rot_part, abs(f) * np.linalg.norm(np.cross(w, d)))
+        assert worst <= bound + 1e-12, (worst, bound)
+        assert worst < 1.0
+    assert rot_part > 0.02
 
 
 def test_ztwist_closed_form_geodesic():

@@ -178,14 +178,21 @@ def random_abumps(n, seed, box=2.0, amp=0.6, spread=(0.15, 0.5)):
     return f32(np.concatenate([a[:, None], c, s], axis=1))
 
 
-def random_deforms(n, seed, box=3.0, amp=(0.4, 1.0), spread=(0.15, 0.35), kappa=(0.1, 0.4)):
-    """Local deformations Phi_i(p) = p + f_i(p) v_i with anisotropic
-    Gaussians f_i: rows (a, cx, cy, cz, sx, sy, sz, vx, vy, vz).  Draw
-    order: centres U[-box, box]^3 (n, 3); spreads U(spread)^3 (n, 3);
-    |a| U(amp) (n); sign of a (n); direction on the unit sphere (n, 3,
-    normalised normals); kappa U(kappa) (n).  |v| is set so that
-    |a| |v/s| exp(-1/2) = kappa: each Phi_i is a diffeomorphism with margin
-    1 - kappa."""
+def random_deforms(n, seed, box=3.0, amp=(0.4, 1.0), spread=(0.15, 0.35), kappa=(0.1, 0.4), rot=None):
+    """Local deformations Phi_i(p) = p + f_i(p) V_i(p) with anisotropic
+    Gaussians f_i: rows (a, cx, cy, cz, sx, sy, sz, vx, vy, vz) for a
+    constant field V_i = v_i.  Draw order: centres U[-box, box]^3 (n, 3);
+    spreads U(spread)^3 (n, 3); |a| U(amp) (n); sign of a (n); direction on
+    the unit sphere (n, 3, normalised normals); kappa U(kappa) (n).  |v| is
+    set so that |a| |v/s| exp(-1/2) = kappa: each Phi_i is a diffeomorphism
+    with margin 1 - kappa.
+
+    rot = (lo, hi) adds the rotation part of V_i(p) = v_i + w_i x (p - c_i):
+    rows gain (wx, wy, wz), drawn after the above as an axis on the unit
+    sphere (n, 3) and a share U(rot) (n).  Then |v| is set so that
+    |a| exp(-1/2) |v| / s_min = kappa and |w| so that
+    |a| |w| (2/e s_max / s_min + 1) = share: the Lipschitz bound of
+    f_i V_i is kappa + share."""
     rng = np.random.default_rng(seed)
     c = rng.uniform(-box, box, size=(n, 3))
     s = rng.uniform(spread[0], spread[1], size=(n, 3))
@@ -193,9 +200,17 @@ def random_deforms(n, seed, box=3.0, amp=(0.4, 1.0), spread=(0.15, 0.35), kappa=
     u = rng.normal(size=(n, 3))
     u /= np.linalg.norm(u, axis=1, keepdims=True)
     k = rng.uniform(kappa[0], kappa[1], size=n)
-    vn = k / (np.abs(a) * np.linalg.norm(u / s, axis=1) * np.exp(-0.5))
-    v = u * vn[:, None]
-    return f32(np.concatenate([a[:, None], c, s, v], axis=1))
+    if rot is None:
+        vn = k / (np.abs(a) * np.linalg.norm(u / s, axis=1) * np.exp(-0.5))
+        v = u * vn[:, None]
+        return f32(np.concatenate([a[:, None], c, s, v], axis=1))
+    ax = rng.normal(size=(n, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    share = rng.uniform(rot[0], rot[1], size=n)
+    smin, smax = s.min(axis=1), s.max(axis=1)
+    v = u * (k * smin / (np.abs(a) * np.exp(-0.5)))[:, None]
+    w = ax * (share / (np.abs(a) * (2.0 / np.e * smax / smin + 1.0)))[:, None]
+    return f32(np.concatenate([a[:, None], c, s, v, w], axis=1))
 
 
 def scene(spheres=None, planes=None, tori=None):
@@ -246,6 +261,17 @@ def deform16_1080p(width=1920, height=1080):
     base = bumps16_1080p(width, height)
     return dict(name="deform16_1080p", camera=base["camera"],
                 metric=metric(PULLBACK_DEFORM, deforms=random_deforms(16, seed=5)),
+                scene=base["scene"],
+                rule=rule(RK4, h=0.005, max_steps=4000, t_max=20.0, pass_steps=4000))
+
+
+def rdeform16_1080p(width=1920, height=1080):
+    """Sixteen local deformations whose fields also rotate about an axis
+    through their centres (V_i(p) = v_i + w_i x (p - c_i)), in the bumps16
+    scene, RK4 as the headline workload."""
+    base = bumps16_1080p(width, height)
+    return dict(name="rdeform16_1080p", camera=base["camera"],
+                metric=metric(PULLBACK_DEFORM, deforms=random_deforms(16, seed=6, kappa=(0.1, 0.3), rot=(0.2, 0.5))),
                 scene=base["scene"],
                 rule=rule(RK4, h=0.005, max_steps=4000, t_max=20.0, pass_steps=4000))
 
@@ -320,6 +346,7 @@ WORKLOADS = {
     "euler_vs_rk4_1080p": lambda **kw: bumps16_1080p(kind=EULER, **kw),
     "twist_4k": twist_4k,
     "deform16_1080p": deform16_1080p,
+    "rdeform16_1080p": rdeform16_1080p,
     "illum_1080p": lambda **kw: dict(bumps16_1080p(**kw), name="illum_1080p",
                                      light=dict(pos=(2.5, 3.5, -3.0), h=0.01, tol=1e-4, max_iters=16,
                                                 max_steps=4000)),
