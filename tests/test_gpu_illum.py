@@ -103,7 +103,8 @@ def test_flat_space_closed_form(rt):
 # the way to the light many geodesics bend far from the segment (about two
 # thirds are found).
 @pytest.mark.parametrize("name,w,h,found_min", [("bumps16_1080p", 64, 40, 0.95), ("twist_4k", 64, 40, 0.95),
-                                                ("deform16_1080p", 48, 30, 0.95), ("abumps16_1080p", 64, 40, 0.9),
+                                                ("deform16_1080p", 48, 30, 0.95), ("rdeform16_1080p", 48, 30, 0.95),
+                                                ("abumps16_1080p", 64, 40, 0.9),
                                                 ("quadric_1080p", 64, 40, 0.6)])
 def test_curved_geodesics_reach_the_light(rt, name, w, h, found_min):
     """Curved metrics: the oracle integrates each returned geodesic in FP64
