@@ -159,8 +159,9 @@ rt_status rt_create(int hip_device, rt_ctx **out) {
 void rt_destroy(rt_ctx *c) {
     if (!c) return;
     if (!c->host_only) {
-        hipSetDevice(c->device);
-        hipDeviceSynchronize();
+        // best effort: a destroy reports nothing, and frees what it can
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
         hipFree(c->d_bump_f);
         hipFree(c->d_bump_d);
         hipFree(c->d_scene);
@@ -345,7 +346,7 @@ static rt_status set_deform_metric(rt_ctx *c, const rt_metric *m) {
     if (!c->host_only) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
-        hipSetDevice(c->device);
+        if (hipError_t e = hipSetDevice(c->device); e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
         if ((st = upload(c, &c->d_bump_f, &c->bump_f_bytes, bf.data(), bf.size() * sizeof(float))) != RT_OK) return st;
         if ((st = upload(c, &c->d_bump_d, &c->bump_d_bytes, bd.data(), bd.size() * sizeof(double))) != RT_OK) return st;
         c->dd.bump_f = (const float4 *)c->d_bump_f;
@@ -414,7 +415,7 @@ static rt_status set_graph2_metric(rt_ctx *c, const rt_metric *m) {
     if (!c->host_only) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
-        hipSetDevice(c->device);
+        if (hipError_t e = hipSetDevice(c->device); e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
         if ((st = upload(c, &c->d_bump_f, &c->bump_f_bytes, bf.data(), bf.size() * sizeof(float))) != RT_OK) return st;
         if ((st = upload(c, &c->d_bump_d, &c->bump_d_bytes, bd.data(), bd.size() * sizeof(double))) != RT_OK) return st;
         c->dd.bump_f = (const float4 *)c->d_bump_f;
@@ -488,7 +489,7 @@ rt_status rt_set_metric(rt_ctx *c, const rt_metric *m) {
     if (!c->host_only) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
-        hipSetDevice(c->device);
+        if (hipError_t e = hipSetDevice(c->device); e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
         if ((st = upload(c, &c->d_bump_f, &c->bump_f_bytes, bf.data(), bf.size() * sizeof(float))) != RT_OK) return st;
         if ((st = upload(c, &c->d_bump_d, &c->bump_d_bytes, bd.data(), bd.size() * sizeof(double))) != RT_OK) return st;
         c->dd.bump_f = (const float4 *)c->d_bump_f;
@@ -566,7 +567,7 @@ rt_status rt_set_scene(rt_ctx *c, const rt_scene *s) {
         }
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
-        hipSetDevice(c->device);
+        if (hipError_t e = hipSetDevice(c->device); e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
         if ((st = upload(c, &c->d_scene, &c->scene_bytes, buf.data(), buf.size())) != RT_OK) return st;
         char *b = (char *)c->d_scene;
         c->dd.sph_f = (const float4 *)b;
