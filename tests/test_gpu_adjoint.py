@@ -171,5 +171,5 @@ def test_autograd_function(env):
     ones = np.ones(n_sets * size * size, np.uint8)
     g_api, l_api, _ = gpu_grad(rt, torch, wl, wl["metric"]["bumps"], t_out["hit"].cpu().numpy(),
                                t_out["id"].cpu().numpy(), ones)
-    assert abs(float(loss) - float(l_api.sum())) <= 1e-4 * max(1.0, float(loss))
+    assert abs(float(loss.detach()) - float(l_api.sum())) <= 1e-4 * max(1.0, float(loss.detach()))
     assert np.allclose(g_auto, g_api, rtol=1e-5, atol=1e-5 * np.abs(g_api).max())
