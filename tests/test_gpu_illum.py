@@ -180,3 +180,35 @@ def test_multi_set_equals_single_sets(rt):
         say("set %d: %d lit" % (s, (shs["status"] == 1).sum()))
         for k in ("status", "shade", "dir", "len"):
             assert np.array_equal(sh[k][s * n:(s + 1) * n], shs[k]), (s, k)
+
+
+def test_edge_cases(rt):
+    """Empty pixel lists and tiny frames: a frame with no hit (all -3, no
+    Newton work), a single pixel, and one Newton iteration only, where only
+    pixels whose straight segment already lands within tol may be lit."""
+    say("illumination edge cases")
+    base = W.get("bumps16_1080p")
+    # flat space, the camera looks up and away from every object (every ray
+    # rises, the objects lie below and ahead): no hit, every list empty
+    wl = W.with_size(base, 16, 8)
+    wl["metric"] = W.metric(W.EUCLID)
+    wl["camera"] = W.camera(16, 8, eye=(0.0, 0.0, -10.0), forward=(0.0, 1.0, 0.0), up=(0.0, 0.0, 1.0))
+    tra, sh = _run(rt, wl)
+    assert (tra["id"] < 0).all()
+    assert (sh["status"] == -3).all() and (sh["shade"] == 0).all() and (sh["len"] == 0).all()
+    # one pixel, aimed down at the plane y = -1 (or a sphere before it)
+    wl = W.with_size(base, 1, 1)
+    wl["camera"] = W.camera(1, 1, eye=(0.0, 0.0, -4.0), forward=(0.0, -0.5, 1.0))
+    tra, sh = _run(rt, wl)
+    assert tra["id"][0] >= 0 and sh["status"][0] in (-1, 0, 1, 2)
+    # one iteration: a pixel is found only if its straight segment lands
+    wl = W.with_size(base, 32, 20)
+    tra, sh = _run(rt, wl, light=dict(LIGHT, max_iters=1))
+    found = np.nonzero(sh["status"] >= 0)[0]
+    orc = oracle.Oracle(wl["metric"], wl["scene"])
+    L = np.array(LIGHT["pos"], np.float64)
+    for p in found[:50]:
+        q = tra["hit"][p].astype(np.float64)
+        d = L - q
+        v = d / np.sqrt(d @ orc.metric_tensor(q) @ d)
+        assert np.abs(sh["dir"][p] / np.linalg.norm(sh["dir"][p]) - v / np.linalg.norm(v)).max() < 1e-5, p
