@@ -147,7 +147,7 @@ rt_status rt_create(int hip_device, rt_ctx **out) {
         e = hipMemset(c->d_stats, 0, sizeof(unsigned long long) * rti::ST_N);
         if (e != hipSuccess) {
             g_create_error = std::string("rt_create: ") + hipGetErrorString(e);
-            hipFree(c->d_stats);
+            (void)hipFree(c->d_stats);
             delete c;
             return RT_EDEVICE;
         }
@@ -162,29 +162,29 @@ void rt_destroy(rt_ctx *c) {
         // best effort: a destroy reports nothing, and frees what it can
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();
-        hipFree(c->d_bump_f);
-        hipFree(c->d_bump_d);
-        hipFree(c->d_scene);
-        hipFree(c->d_st);
-        hipFree(c->d_ids[0]);
-        hipFree(c->d_ids[1]);
-        hipFree(c->d_cmask);
-        hipFree(c->d_cscan);
-        hipFree(c->d_bscan);
-        hipFree(c->d_rec);
-        hipFree(c->d_ctr);
-        hipFree(c->d_stats);
-        hipFree(c->d_adj_scr);
-        hipFree(c->d_adj_part);
-        hipFree(c->d_loss_blk);
-        hipFree(c->d_gen_ks);
-        hipFree(c->d_surr);
-        hipFree(c->d_surr_sb);
-        hipFree(c->d_xbuf);
-        hipFree(c->d_ibuf);
-        hipFree(c->d_grp_ctl);
-        hipFree(c->d_grp_w);
-        for (hipEvent_t e : c->ev) hipEventDestroy(e);
+        (void)hipFree(c->d_bump_f);
+        (void)hipFree(c->d_bump_d);
+        (void)hipFree(c->d_scene);
+        (void)hipFree(c->d_st);
+        (void)hipFree(c->d_ids[0]);
+        (void)hipFree(c->d_ids[1]);
+        (void)hipFree(c->d_cmask);
+        (void)hipFree(c->d_cscan);
+        (void)hipFree(c->d_bscan);
+        (void)hipFree(c->d_rec);
+        (void)hipFree(c->d_ctr);
+        (void)hipFree(c->d_stats);
+        (void)hipFree(c->d_adj_scr);
+        (void)hipFree(c->d_adj_part);
+        (void)hipFree(c->d_loss_blk);
+        (void)hipFree(c->d_gen_ks);
+        (void)hipFree(c->d_surr);
+        (void)hipFree(c->d_surr_sb);
+        (void)hipFree(c->d_xbuf);
+        (void)hipFree(c->d_ibuf);
+        (void)hipFree(c->d_grp_ctl);
+        (void)hipFree(c->d_grp_w);
+        for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     }
     delete c;
 }
@@ -204,7 +204,7 @@ static rt_status sync_last(rt_ctx *c) {
 static rt_status upload(rt_ctx *c, void **dst, size_t *cap, const void *src, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (*cap < bytes) {
-        hipFree(*dst);
+        (void)hipFree(*dst);
         *dst = nullptr;
         *cap = 0;
         hipError_t e = hipMalloc(dst, bytes);
@@ -590,13 +590,13 @@ rt_status rt_set_scene(rt_ctx *c, const rt_scene *s) {
 static int64_t max_chunks_for(int64_t cap) { return cap / 64 + MAX_SETS; }
 
 static void free_workspace(rt_ctx *c) {
-    hipFree(c->d_st);
-    hipFree(c->d_ids[0]);
-    hipFree(c->d_ids[1]);
-    hipFree(c->d_cmask);
-    hipFree(c->d_cscan);
-    hipFree(c->d_bscan);
-    hipFree(c->d_rec);
+    (void)hipFree(c->d_st);
+    (void)hipFree(c->d_ids[0]);
+    (void)hipFree(c->d_ids[1]);
+    (void)hipFree(c->d_cmask);
+    (void)hipFree(c->d_cscan);
+    (void)hipFree(c->d_bscan);
+    (void)hipFree(c->d_rec);
     c->d_st = nullptr;
     c->d_ids[0] = c->d_ids[1] = nullptr;
     c->d_cmask = nullptr;
@@ -695,7 +695,7 @@ static rt_status ensure_xbuf(rt_ctx *c, int64_t cap) {
     if (c->xbuf_cap >= cap) return RT_OK;
     rt_status st = sync_last(c);
     if (st != RT_OK) return st;
-    hipFree(c->d_xbuf);
+    (void)hipFree(c->d_xbuf);
     c->d_xbuf = nullptr;
     c->xbuf_cap = 0;
     hipError_t e = hipMalloc(&c->d_xbuf, (size_t)cap * (16 + 8 + 24 + 24) + 1024);
@@ -970,7 +970,7 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     if (c->ibuf_cap < n) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
-        hipFree(c->d_ibuf);
+        (void)hipFree(c->d_ibuf);
         c->d_ibuf = nullptr;
         c->ibuf_cap = 0;
         e = hipMalloc(&c->d_ibuf, (size_t)n * 52 + 130 * sizeof(int) + 256);
@@ -1040,7 +1040,7 @@ rt_status rt_loss_l2(rt_ctx *c, const rt_camera *cam, const float *hit, const in
     if (c->loss_cap < need) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
-        hipFree(c->d_loss_blk);
+        (void)hipFree(c->d_loss_blk);
         c->d_loss_blk = nullptr;
         c->loss_cap = 0;
         if ((e = hipMalloc((void **)&c->d_loss_blk, need * sizeof(float))) != hipSuccess)
@@ -1070,8 +1070,8 @@ rt_status rt_trace_bwd(rt_ctx *c, const void *tape, const float *grad_hit, float
     if (c->adj_scr_cap < scr || c->adj_part_cap < part) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
-        hipFree(c->d_adj_scr);
-        hipFree(c->d_adj_part);
+        (void)hipFree(c->d_adj_scr);
+        (void)hipFree(c->d_adj_part);
         c->d_adj_scr = c->d_adj_part = nullptr;
         c->adj_scr_cap = c->adj_part_cap = 0;
         if ((e = hipMalloc((void **)&c->d_adj_scr, scr * sizeof(float))) != hipSuccess ||
@@ -1149,7 +1149,7 @@ rt_status rt_mlp_fwd_grouped(rt_ctx *c, int n_nets, const int32_t *rows, const u
     const size_t P = RT_MLP_PARAMS, PP = rti::MLP_P_PAD;
     const size_t need = (size_t)n_nets * PP * 6;
     if (c->grp_w_bytes < need) {
-        hipFree(c->d_grp_w);
+        (void)hipFree(c->d_grp_w);
         c->d_grp_w = nullptr;
         c->grp_w_bytes = 0;
         if ((e = hipMalloc(&c->d_grp_w, need)) != hipSuccess) return hip_fail(c, e, "hipMalloc (grouped mlp)");
@@ -1395,7 +1395,7 @@ rt_status rt_surrogate_load(rt_ctx *c, int n_nets, const uint16_t *w_bf16, const
     const size_t o_w = 0, o_p = al(n_nets * PP * 2), o_s = o_p + al(n_nets * PP * 4), o_a = o_s + al(n_nets * 4),
                  o_e = o_a + al((size_t)n_nets * n_tab * 4), total = o_e + al((size_t)n_nets * n_bins * 8);
     if (c->surr_bytes < total) {
-        hipFree(c->d_surr);
+        (void)hipFree(c->d_surr);
         c->d_surr = nullptr;
         c->surr_bytes = 0;
         if ((e = hipMalloc(&c->d_surr, total)) != hipSuccess) return hip_fail(c, e, "hipMalloc (surrogate)");
