@@ -27,6 +27,16 @@ Pinning status (what fixes each function to something other than itself):
                                     quadrature hits           -- pinned
   multi-bump trajectories           no closed form: invariants and agreement
                                     of independent integrators only
+  FD gradient (fd_gradient)         exact zeros for a = 0 and for the centre
+                                    and spread of a zero-amplitude bump,
+                                    bitwise parity under a -> -a, and the
+                                    single-bump quadrature derivative
+                                    (tests/test_oracle_fd.py) -- pinned
+  twist at its centre               the hyper-dual square root divides by
+                                    |x|: an evaluation exactly at x = 0
+                                    gives NaN (the ray would fail, id -2);
+                                    rays aimed at the centre stay finite and
+                                    on their line preimage to a step's jump
 """
 from __future__ import annotations
 
