@@ -223,11 +223,11 @@ def bench_adjoint(args, wl, torch, rt):
 
 def _frame_error(out, ref, tol=1e-3):
     """Pixels whose object id differs from the reference frame or whose hit
-    point is off by more than tol (any coordinate); hit-error quantiles over
+    point is farther than tol (Euclidean) from it; hit-error quantiles over
     pixels with the same id."""
     import numpy as np
     same = out["id"] == ref["id"]
-    err = np.abs(out["hit"] - ref["hit"]).max(axis=1)
+    err = np.linalg.norm(out["hit"].astype(np.float64) - ref["hit"], axis=1)
     bad = (~same) | (err > tol)
     e = err[same]
     # over all pixels, an id mismatch counting as an infinite error

@@ -381,8 +381,8 @@ rt_status rt_loss_l2(rt_ctx *ctx, const rt_camera *camera, const float *hit, con
 
 /* Gradient of sum_p grad_hit_p . hit_p with respect to the bump parameters,
  * written to grad_params [n_sets][n_bumps][5] (device).  tape must be the
- * tape of the last rt_trace_fwd_ckpt on this context, with the metric
- * unchanged since (RT_ESTATE otherwise). */
+ * tape of the last rt_trace_fwd_ckpt on this context, with the metric and
+ * the scene unchanged since (RT_ESTATE otherwise, before any launch). */
 rt_status rt_trace_bwd(rt_ctx *ctx, const void *tape, const float *grad_hit, float *grad_params, void *hip_stream);
 
 /* ------------------------------------------------------------- surrogate

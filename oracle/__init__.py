@@ -37,6 +37,10 @@ Pinning status (what fixes each function to something other than itself):
                                     gives NaN (the ray would fail, id -2);
                                     rays aimed at the centre stay finite and
                                     on their line preimage to a step's jump
+  failed rays (id -2)               a failed ray reports the state of the
+                                    same run stopped by max_steps; rays away
+                                    from the failure region equal a run that
+                                    never rejects               -- pinned
 """
 from __future__ import annotations
 

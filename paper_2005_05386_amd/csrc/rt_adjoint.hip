@@ -245,7 +245,7 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
     // culling window: CULL steps (plus the stages of one more) of Euclidean
     // length <= h each, since g >= I keeps a g-unit velocity at |y| <= 1
     constexpr int CULL = 16;
-    const float margin = (float)((CULL + 1) * (double)A.h * 1.02 + 1e-4);
+    const float margin = (float)(CULL + 1) * A.h * 1.02f + 1e-4f;
 
     for (int chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
         const int set = chunk / tiles;
@@ -406,15 +406,30 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
     }
 }
 
+// Compensated FP32 sum in a fixed order: the rounding error of every
+// addition (Knuth's TwoSum, exact in binary floating point) is carried in a
+// second float, so the result is the sum to about one FP32 rounding,
+// independent of the number of terms, and bitwise reproducible.
+struct TwoSumAcc {
+    float s = 0.f, c = 0.f;
+    __device__ void add(float v) {
+        float t = s + v;
+        float bp = t - s;
+        c += (s - (t - bp)) + (v - bp);
+        s = t;
+    }
+    __device__ float value() const { return s + c; }
+};
+
 // grad[set][param] = sum over the set's chunks, in chunk order.
 __global__ void k_grad_reduce(const float *__restrict__ partial, int n_sets, int tiles, int np5,
                               float *__restrict__ grad) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_sets * np5) return;
     int set = t / np5, j = t - set * np5;
-    double acc = 0.0;
-    for (int c = 0; c < tiles; ++c) acc += partial[((int64_t)set * tiles + c) * np5 + j];
-    grad[t] = (float)acc;
+    TwoSumAcc acc;
+    for (int c = 0; c < tiles; ++c) acc.add(partial[((int64_t)set * tiles + c) * np5 + j]);
+    grad[t] = acc.value();
 }
 
 // Masked L2 loss: pixel p counts if mask[p] (when given), id[p] >= 0 and
@@ -453,9 +468,9 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ hit, con
 __global__ void k_loss_reduce(const float *__restrict__ block_sum, int nblk, int n_sets, float *__restrict__ loss) {
     int set = blockIdx.x * blockDim.x + threadIdx.x;
     if (set >= n_sets) return;
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += block_sum[(int64_t)set * nblk + b];
-    loss[set] = (float)acc;
+    TwoSumAcc acc;
+    for (int b = 0; b < nblk; ++b) acc.add(block_sum[(int64_t)set * nblk + b]);
+    loss[set] = acc.value();
 }
 
 }  // namespace

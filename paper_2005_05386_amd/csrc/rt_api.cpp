@@ -582,6 +582,9 @@ rt_status rt_set_scene(rt_ctx *c, const rt_scene *s) {
     c->tor.assign(s->tori, s->tori + s->n_tori);
     c->has_scene = true;
     c->surr_sb_dirty = true;
+    // the implicit hit of a taped forward refers to objects of the old
+    // scene (the table is re-laid out): the tape can no longer be reversed
+    c->adj_valid = false;
     c->err.clear();
     return RT_OK;
 }

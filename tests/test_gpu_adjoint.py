@@ -173,3 +173,22 @@ def test_autograd_function(env):
                                t_out["id"].cpu().numpy(), ones)
     assert abs(float(loss.detach()) - float(l_api.sum())) <= 1e-4 * max(1.0, float(loss.detach()))
     assert np.allclose(g_auto, g_api, rtol=1e-5, atol=1e-5 * np.abs(g_api).max())
+
+
+def test_new_scene_invalidates_tape(env):
+    rt, torch = env
+    say("rt_trace_bwd after rt_set_scene: RT_ESTATE, nothing launched")
+    n_sets, size = 1, 16
+    wl = W.with_size(W.get("adjoint_64x512", n_sets=n_sets), size, size)
+    tr = rt.Tracer(0)
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    cam, rule = wl["camera"], wl["rule"]
+    out, tape = tr.trace_fwd_ckpt(cam, rule, rule["max_steps"], 100)
+    gh = torch.zeros(n_sets * size * size, 3, dtype=torch.float32, device="cuda")
+    tr.trace_bwd(tape, gh, wl["metric"]["bumps"].shape[1])
+    torch.cuda.synchronize()
+    tr.set_scene(wl["scene"])
+    with pytest.raises(rt.RtError) as ei:
+        tr.trace_bwd(tape, gh, wl["metric"]["bumps"].shape[1])
+    assert ei.value.status == -5

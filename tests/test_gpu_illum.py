@@ -160,9 +160,17 @@ def _check_found(wl, tra, sh, found_min, sample=None):
         clear = orc.geodesic_clear(q, v, T, LIGHT["h"], 1e-3)
         vis_bad += clear != (st[p] == 1)
     say("worst end %.2e, worst cos %.2e, visibility disagreements %d" % (worst_end, worst_cos, vis_bad))
-    assert worst_end < 5e-4
-    assert worst_cos < 2e-3
-    assert vis_bad <= max(2, 0.01 * len(check))
+    # end: the GPU stops once its FP32 shot lands within tol = 1e-4 (max
+    # norm); the FP64 integration of the returned direction adds the FP32
+    # trajectory's rounding drift (measured worst 1.04e-4)
+    assert worst_end < 2e-4
+    # Lambert term: FP32 assembly and inversion of g at q; the quadric's
+    # steep slopes make g worst conditioned (measured worst 1.2e-5 there,
+    # 3.8e-7 on the other metrics)
+    assert worst_cos < 5e-5
+    # visibility: none measured; one grazing geodesic may be decided
+    # differently in FP32 and FP64
+    assert vis_bad <= max(1, 0.0025 * len(check))
 
 
 def test_multi_set_equals_single_sets(rt):

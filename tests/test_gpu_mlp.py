@@ -45,13 +45,26 @@ def test_mlp_forward_backward_match_oracle(env, n, batch):
     y = tr.mlp_fwd(pb, pt, torch.tensor(x, device="cuda"), work).cpu().numpy()
     g = tr.mlp_bwd(pb, pt, torch.tensor(dy, device="cuda"), work).cpu().numpy()
     p32 = p.astype(np.float32).astype(np.float64)
+    worst_f = worst_b = 0.0
     for i in range(n):
         yr, _ = mlp.forward(p32[i], x[i].astype(np.float64), bf16=True)
-        assert np.abs(y[i] - yr).max() <= 1e-4 * max(1.0, np.abs(yr).max()), (i, np.abs(y[i] - yr).max())
+        ef = np.abs(y[i] - yr).max() / max(1.0, np.abs(yr).max())
+        worst_f = max(worst_f, ef)
+        # the oracle rounds at the same bf16 points; what remains is FP32
+        # accumulation order (measured worst 3.6e-6)
+        assert ef <= 2e-5, (i, ef)
         gr = mlp.backward(p32[i], x[i].astype(np.float64), dy[i].astype(np.float64), bf16=True)
         for blk, (a, b) in enumerate(zip(mlp.split(g[i].astype(np.float64)), mlp.split(gr))):
-            err = np.abs(a - b).max()
-            assert err <= 1e-2 * max(1e-3, np.abs(b).max()), (i, blk, err, np.abs(b).max())
+            err = np.abs(a - b).max() / max(1e-3, np.abs(b).max())
+            worst_b = max(worst_b, err)
+            # backward operands are rounded to bf16 from FP32 values that
+            # differ from the oracle's FP64 ones by accumulation order; an
+            # element that lies that close to a rounding boundary goes to
+            # the neighbouring bf16 value (2^-8 relative), so a sum of 256
+            # terms can move by about one bf16 ulp of one term (measured
+            # worst 9.8e-4 of the largest component)
+            assert err <= 3e-3, (i, blk, err, np.abs(b).max())
+    say("worst relative error: forward %.2e, backward %.2e" % (worst_f, worst_b))
 
 
 def test_adamw_step(env):

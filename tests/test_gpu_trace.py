@@ -112,10 +112,10 @@ def test_bumps16_small_full_frame(rt):
 def test_bumps16_1080p_sampled(rt):
     """Full 1080p frame in the benchmark's launch configuration; a seeded
     sample of pixels recomputed one by one by the oracle."""
-    say("bumps16_1080p full frame, 3000 sampled pixels vs oracle")
+    say("bumps16_1080p full frame, 32400 sampled pixels vs oracle")
     wl = W.get("bumps16_1080p")
     g = gpu_trace(rt, wl)
-    pix = W.pixel_sample(1920, 1080, 3000, seed=7)
+    pix = W.pixel_sample(1920, 1080, 32400, seed=7)
     ref = oracle_trace(wl, pix)
     rep = compare(g, ref, pix)
     say(rep, g["_stats"])
@@ -135,13 +135,67 @@ def test_rk45_small(rt):
 
 
 def test_rk45_1080p_sampled(rt):
-    say("bumps16 RK45 1080p, 1500 sampled pixels")
+    say("bumps16 RK45 1080p, 32400 sampled pixels")
     wl = W.get("bumps16_1080p_rk45")
     g = gpu_trace(rt, wl)
-    pix = W.pixel_sample(1920, 1080, 1500, seed=8)
+    pix = W.pixel_sample(1920, 1080, 32400, seed=8)
     rep = compare(g, oracle_trace(wl, pix), pix)
     say(rep, g["_stats"])
     assert_parity(rep)
+
+
+def failing_rk45_case():
+    """A frame in which the rays through a steep bump fail (id -2): RK45
+    with h = h_min = h_max = 0.08, so the step never grows back and an
+    attempt whose error norm exceeds 1 cannot be retried above h_min.  A
+    ray fails where the error norm along its path exceeds 1, which varies
+    smoothly with the pixel: FP32 and FP64 take the same decision except
+    within rounding of the boundary of the failed region."""
+    wl = W.with_size(W.get("single_bump_64"), 64, 64)
+    wl["camera"] = W.camera(64, 64, vfov_deg=20.0)
+    wl["metric"] = dict(wl["metric"], bumps=W.f32([[[1.5, 0.0, 0.0, 0.0, 0.3]]]))
+    rule = W.rule(kind=W.RK45, h=0.08, max_steps=4000, t_max=10.0, rtol=1e-6, atol=1e-6)
+    rule.update(h_min=rule["h"], h_max=rule["h"])
+    wl["rule"] = rule
+    return wl
+
+
+def test_failed_rays_match_the_oracle(rt):
+    say("id -2: RK45 pinned at h_min = h_max = 0.08 through a steep bump, 64x64")
+    wl = failing_rk45_case()
+    g = gpu_trace(rt, wl)
+    ref = oracle_trace(wl)
+    rep = compare(g, ref)
+    n_fail = int((ref["id"] == -2).sum())
+    say(rep, "oracle failed", n_fail, "gpu failed", int((g["id"] == -2).sum()),
+        "id -2 disagreements", int(((g["id"] == -2) != (ref["id"] == -2)).sum()))
+    assert n_fail > 150
+    assert_parity(rep)
+    # the failed rays stop where the oracle's stop (their last accepted state)
+    f = (g["id"] == -2) & (ref["id"] == -2)
+    assert f.sum() >= n_fail - 2
+    assert np.linalg.norm(g["hit"][f] - ref["hit"][f], axis=1).max() < 1e-4
+    assert np.array_equal(g["steps"][f], ref["steps"][f])
+
+
+def test_twist_rays_near_its_centre(rt):
+    """The twist is only C^1 at its centre: rays aimed at it, or passing
+    within a few steps of it, against the oracle.  The central pixel of the
+    odd-sized frame looks straight down the z axis through the centre."""
+    say("twist: 33x33 frame, 1 degree field of view aimed at the centre, plane z = 3")
+    wl = W.with_size(W.get("twist_4k"), 33, 33)
+    wl["camera"] = W.camera(33, 33, vfov_deg=1.0)
+    wl["scene"] = W.scene(planes=[[0.0, 0.0, 1.0, 3.0]])
+    wl["rule"] = W.rule(W.RK4, h=0.005, max_steps=4000)
+    g = gpu_trace(rt, wl)
+    ref = oracle_trace(wl)
+    rep = compare(g, ref)
+    say(rep)
+    assert (ref["id"] == 0).all() and (g["id"] == 0).all()
+    assert_parity(rep)
+    # the central ray stays on the axis
+    c = 16 * 33 + 16
+    assert abs(g["hit"][c, 0]) < 1e-6 and abs(g["hit"][c, 1]) < 1e-6
 
 
 def test_euler_single_bump(rt):
@@ -222,10 +276,10 @@ def test_twist_small_full_frame(rt):
 
 
 def test_twist_4k_sampled(rt):
-    say("twist_4k full frame, 1200 sampled pixels")
+    say("twist_4k full frame, 32400 sampled pixels")
     wl = W.get("twist_4k")
     g = gpu_trace(rt, wl)
-    pix = W.pixel_sample(3840, 2160, 1200, seed=3)
+    pix = W.pixel_sample(3840, 2160, 32400, seed=3)
     rep = compare(g, oracle_trace(wl, pix), pix)
     say(rep, g["_stats"])
     assert_parity(rep)

@@ -539,3 +539,36 @@ def test_twist_rays_through_the_origin():
     # away from the origin by two steps: fourth order again
     e1, e2 = resid(0.01, 0.01)[0], resid(0.01, 0.005)[0]
     assert e2 < 1e-7 and e1 / e2 > 16.0, (e1, e2)
+
+
+def test_failed_rays_stop_at_their_last_accepted_state():
+    """id -2 (the error-controlled step of the RK45 march would have to fall
+    below h_min).  With h = h_min = h_max = 0.08 the step can never grow
+    back, and a ray fails at the first attempt whose error norm exceeds 1:
+    on the rays through the bump's steep core.  A failed ray reports the
+    state after its accepted steps: bitwise the output of the same run
+    stopped there by max_steps (a miss, id -1).  Rays that keep away from
+    the bump never see a large error and are bitwise the rays of a run with
+    tolerances so loose that no attempt is rejected."""
+    n = 32
+    wl = W.with_size(W.get("single_bump_64"), n, n)
+    wl["camera"] = W.camera(n, n, vfov_deg=20.0)
+    m = dict(wl["metric"], bumps=W.f32([[[1.5, 0.0, 0.0, 0.0, 0.3]]]))
+    strict = W.rule(kind=W.RK45, h=0.08, max_steps=4000, t_max=10.0, rtol=1e-6, atol=1e-6)
+    strict.update(h_min=strict["h"], h_max=strict["h"])
+    loose = dict(strict, rtol=1e9, atol=1e9)
+    orc = oracle.Oracle(m, wl["scene"])
+    a = orc.trace(wl["camera"], strict)
+    b = orc.trace(wl["camera"], loose)
+    fail = a["id"] == -2
+    assert 10 < fail.sum() < 0.5 * fail.size
+    assert (b["id"] != -2).all() and (b["rejected"] == 0).all()
+    for p in np.flatnonzero(fail):
+        c = orc.trace(wl["camera"], dict(strict, max_steps=int(a["steps"][p])), np.array([p]))
+        assert c["id"][0] == -1 and c["steps"][0] == a["steps"][p]
+        assert np.array_equal(c["hit"][0], a["hit"][p]) and c["t"][0] == a["t"][p]
+    ii, jj = np.unravel_index(np.arange(n * n), (n, n))
+    r = np.hypot(ii - (n - 1) / 2, jj - (n - 1) / 2)
+    assert r[fail].max() < 6 and fail.reshape(n, n)[n // 2 - 1:n // 2 + 1, n // 2 - 1:n // 2 + 1].all()
+    same = np.all(a["hit"] == b["hit"], axis=1) & (a["id"] == b["id"])
+    assert same[r > 10].all() and same.mean() > 0.7
