@@ -265,6 +265,26 @@ typedef struct rt_outputs {
 rt_status rt_trace(rt_ctx *ctx, const rt_camera *camera, const rt_step_rule *rule,
                    int max_steps, const rt_outputs *out, void *hip_stream);
 
+/* rt_trace without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, kernels and results as rt_trace
+ * (bitwise), but the trace's workspace (ray state, survivor lists, chunk
+ * scans, refine records, counters) lives in one static device array of
+ * RT_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from the first
+ * rt_create on that GPU until the process ends.  The workspace needs about
+ * 149 bytes per ray id (ids: 8x8 pixel tiles x 64 x n_sets) plus 1 KB per
+ * pass: up to about 450,000 ray ids, e.g. a 640x640 frame of one set.
+ * Larger frames return RT_EINVAL before any launch.  Also RT_EUNSUPPORTED
+ * for RT_FLAG_TIMING (event creation) and RT_FLAG_SURROGATE (crossing
+ * queues).  Every call on one GPU shares the array: calls whose work
+ * overlaps on that GPU (other streams, other contexts, other host threads)
+ * race and give undefined results; serialise them.  The counters the
+ * trace needs zeroed are cleared by its first kernel.  rt_get_stats reads
+ * the counters of the last trace, whichever entry point ran it. */
+#define RT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rt_status rt_trace_noalloc(rt_ctx *ctx, const rt_camera *camera, const rt_step_rule *rule,
+                           int max_steps, const rt_outputs *out, void *hip_stream);
+
 /* Wait for the context's work on hip_stream and report any asynchronous
  * device error as RT_EDEVICE. */
 rt_status rt_sync(rt_ctx *ctx, void *hip_stream);

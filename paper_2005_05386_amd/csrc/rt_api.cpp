@@ -51,6 +51,9 @@ struct rt_ctx {
     int64_t ws_cap = 0;                // ray ids the workspace holds
     int *d_ctr = nullptr;
     unsigned long long *d_stats = nullptr;
+    // static workspace of rt_trace_noalloc on this device (looked up at create)
+    void *d_noalloc = nullptr;
+    hipError_t noalloc_err = hipErrorNotInitialized;
     hipStream_t last_stream = nullptr;
     bool traced = false;
     int last_passes = 0;
@@ -151,6 +154,9 @@ rt_status rt_create(int hip_device, rt_ctx **out) {
             delete c;
             return RT_EDEVICE;
         }
+        // address of the allocation-free trace's workspace on this device;
+        // a failure is reported by rt_trace_noalloc, the only user
+        c->noalloc_err = rti::noalloc_scratch(hip_device, &c->d_noalloc);
     }
     *out = c;
     return RT_OK;
@@ -638,6 +644,47 @@ static rt_status ensure_workspace(rt_ctx *c, int64_t cap) {
     return RT_OK;
 }
 
+// Buffers of one trace.
+struct Workspace {
+    int *ctr;
+    float *st;
+    int *ids[2];
+    unsigned long long *cmask;
+    int *cscan, *bscan;
+    float4 *rec;
+};
+
+static Workspace context_workspace(rt_ctx *c) {
+    return Workspace{c->d_ctr, c->d_st, {c->d_ids[0], c->d_ids[1]}, c->d_cmask, c->d_cscan, c->d_bscan, c->d_rec};
+}
+
+// The same buffers carved from one block (the allocation-free trace's static
+// array): counter block for n_passes passes | ray state | two survivor lists
+// | chunk masks | chunk scans | block scans | refine records, each starting
+// on a 256-byte boundary.  Returns the bytes needed; fills *w if base is set.
+static size_t carve_workspace(char *base, int64_t cap, int n_passes, Workspace *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const int64_t mch = max_chunks_for(cap);
+    const size_t list = (size_t)(cap + 64 * MAX_SETS);
+    char *ctr = take(sizeof(int) * (rti::CTR_PASS0 + (size_t)n_passes * rti::CTR_PASS_WORDS + rti::CTR_SURR_WORDS));
+    char *st = take((size_t)cap * rti::Q_NFIELDS * sizeof(float));
+    char *i0 = take(list * sizeof(int));
+    char *i1 = take(list * sizeof(int));
+    char *cm = take((size_t)mch * sizeof(unsigned long long));
+    char *cs = take((size_t)mch * sizeof(int));
+    char *bs = take((size_t)(mch / rti::SCAN_BLOCK + 2) * sizeof(int));
+    char *rc = take((size_t)cap * rti::REC_F4 * sizeof(float4));
+    if (w)
+        *w = Workspace{(int *)ctr, (float *)st, {(int *)i0, (int *)i1}, (unsigned long long *)cm, (int *)cs, (int *)bs,
+                       (float4 *)rc};
+    return off;
+}
+
 // Eligibility of every bump for the learned crossing (one parameter set):
 // its support sphere S (centre c, radius R = 3 sigma) must meet no object and
 // lie outside every other bump's cut sphere, so that inside S the culled
@@ -709,7 +756,7 @@ static rt_status ensure_xbuf(rt_ctx *c, int64_t cap) {
 
 // Shared body of rt_trace and rt_trace_fwd_ckpt (tape != NULL).
 static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
-                            void *stream, void *tape, size_t tape_bytes, int ckpt_every) {
+                            void *stream, void *tape, size_t tape_bytes, int ckpt_every, bool noalloc = false) {
     if (!c) return RT_EINVAL;
     if (!cam || !r || !o) return fail(c, RT_EINVAL, "rt_trace: NULL camera, rule or outputs");
     if (!c->has_metric || !c->has_scene) return fail(c, RT_ESTATE, "rt_trace: set the metric and the scene first");
@@ -748,6 +795,8 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     if (r->bisect_iters < 0 || r->bisect_iters > 60) return fail(c, RT_EINVAL, "rt_trace: bisect_iters must be in 0..60");
     if (r->flags & ~(RT_FLAG_TIMING | RT_FLAG_COUNT_WORK | RT_FLAG_SURROGATE))
         return fail(c, RT_EINVAL, "rt_trace: unknown flag bits");
+    if (noalloc && (r->flags & (RT_FLAG_TIMING | RT_FLAG_SURROGATE)))
+        return fail(c, RT_EUNSUPPORTED, "rt_trace_noalloc: RT_FLAG_TIMING and RT_FLAG_SURROGATE need allocations");
     if (max_steps < 1 || max_steps > 1000000) return fail(c, RT_EINVAL, "rt_trace: max_steps must be in 1..1000000");
     const bool surr = (r->flags & RT_FLAG_SURROGATE) != 0;
     if (surr) {
@@ -779,8 +828,22 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     const int64_t T = (int64_t)tiles_x * tiles_y * 64;
     int64_t cap = T * c->n_sets;
     if (cap > 2147483647LL - 4096) return fail(c, RT_EINVAL, "rt_trace: frame too large");
-    rt_status st = ensure_workspace(c, cap);
-    if (st != RT_OK) return st;
+    Workspace ws{};
+    rt_status st = RT_OK;
+    if (noalloc) {
+        size_t need = carve_workspace(nullptr, cap, n_passes, nullptr);
+        if (need > RT_NOALLOC_SCRATCH_BYTES)
+            return fail(c, RT_EINVAL, "rt_trace_noalloc: the frame needs " + std::to_string(need) +
+                                          " bytes of workspace, more than RT_NOALLOC_SCRATCH_BYTES (" +
+                                          std::to_string(RT_NOALLOC_SCRATCH_BYTES) + ")");
+        if (c->noalloc_err != hipSuccess || !c->d_noalloc)
+            return hip_fail(c, c->noalloc_err != hipSuccess ? c->noalloc_err : hipErrorInvalidSymbol,
+                            "rt_trace_noalloc: static workspace address");
+        carve_workspace((char *)c->d_noalloc, cap, n_passes, &ws);
+    } else {
+        if ((st = ensure_workspace(c, cap)) != RT_OK) return st;
+        ws = context_workspace(c);
+    }
 
     rti::TraceArgs a{};
     a.kind = kernel_kind(c);
@@ -832,17 +895,17 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     a.cull_margin = c->kind == RT_METRIC_PULLBACK_ZTWIST ? -1.0f : (float)margin;
     a.cull_base = (float)((r->cull_every + 1) * (double)a.h_max * 1.02 + 1e-4);
     a.cull_disp = (float)(c->deform_disp * (1.0 + 1e-6));
-    a.st = c->d_st;
-    a.ids[0] = c->d_ids[0];
-    a.ids[1] = c->d_ids[1];
-    a.cmask = c->d_cmask;
-    a.cscan = c->d_cscan;
-    a.bscan = c->d_bscan;
+    a.st = ws.st;
+    a.ids[0] = ws.ids[0];
+    a.ids[1] = ws.ids[1];
+    a.cmask = ws.cmask;
+    a.cscan = ws.cscan;
+    a.bscan = ws.bscan;
     a.max_chunks = (int)max_chunks_for(cap);
     a.cap = cap;
-    a.ctr = c->d_ctr;
+    a.ctr = ws.ctr;
     a.stats = c->d_stats;
-    a.rec = c->d_rec;
+    a.rec = ws.rec;
     a.out_hit = o->hit;
     a.out_t = o->t;
     a.out_dir = o->dir;
@@ -865,7 +928,7 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
 
     a.surr = use_surr ? 1 : 0;
     a.n_passes = n_passes;
-    a.xctl = c->d_ctr + rti::CTR_PASS0 + n_passes * rti::CTR_PASS_WORDS;
+    a.xctl = ws.ctr + rti::CTR_PASS0 + n_passes * rti::CTR_PASS_WORDS;
     rti::SurrArgs S = c->surr;
     if (use_surr) {
         if ((st = ensure_xbuf(c, cap)) != RT_OK) return st;
@@ -1003,6 +1066,11 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
 rt_status rt_trace(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
                    void *stream) {
     return trace_impl(c, cam, r, max_steps, o, stream, nullptr, 0, 0);
+}
+
+rt_status rt_trace_noalloc(rt_ctx *c, const rt_camera *cam, const rt_step_rule *r, int max_steps, const rt_outputs *o,
+                           void *stream) {
+    return trace_impl(c, cam, r, max_steps, o, stream, nullptr, 0, 0, true);
 }
 
 size_t rt_tape_bytes(const rt_camera *cam, int n_sets, int max_steps, int ckpt_every) {

@@ -156,6 +156,10 @@ struct DeviceData {
 // control block after the pass blocks must hold CTR_SURR_WORDS words.
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid_blocks,
                         int refine_blocks, hipStream_t s, hipEvent_t *ev, const struct SurrArgs *S, int mlp_blocks);
+// Device address, on `device`, of the static workspace that rt_trace_noalloc
+// carves (RT_NOALLOC_SCRATCH_BYTES).  Looked up with the device made current,
+// once per device; later calls return the cached address.  Thread-safe.
+hipError_t noalloc_scratch(int device, void **ptr);
 // ------------------------------------------------------ direct illumination
 // Table strides of a composed deformation: float4 records (FP32 table) and
 // doubles (FP64 table) per deformation; the device helpers read the same

@@ -20,7 +20,9 @@
 // 64w+i and a ballot turns the answers into wave-uniform masks.  Bump
 // parameters for the masked bumps are then read with scalar loads.
 #include <algorithm>
+#include <mutex>
 
+#include "rt.h"
 #include "rt_device.hpp"
 #include "rt_internal.hpp"
 #include "rt_step.hpp"
@@ -924,6 +926,34 @@ int trace_blocks_per_cu(int kind, int step) {
     case KIND_GANISO: RT_DISPATCH(KIND_GANISO, occ)
     default: RT_DISPATCH(KIND_GQUAD, occ)
     }
+}
+
+// Workspace of the allocation-free trace: one array per GPU, held by the
+// code object until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host it names a stand-in, not device memory):
+// it uses the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[RT_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEV] = {};
+    if (!ptr || device < 0 || device >= MAX_DEV) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int prev = -1;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != device) (void)hipSetDevice(prev);  // restore the caller's device, best effort
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_trace(const TraceArgs &a, const DeviceData &d, int n_passes, int grid, int rgrid, hipStream_t s,

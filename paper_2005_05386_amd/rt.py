@@ -29,7 +29,8 @@ EXPORTS = ["rt_abi_version", "rt_create", "rt_destroy", "rt_last_error", "rt_set
            "rt_trace", "rt_sync", "rt_get_stats", "rt_tape_bytes", "rt_trace_fwd_ckpt", "rt_loss_l2",
            "rt_trace_bwd", "rt_mlp_work_bytes", "rt_mlp_fwd", "rt_mlp_fwd_grouped", "rt_mlp_bwd", "rt_mse_grad", "rt_adamw_step",
            "rt_surrogate_gen", "rt_surrogate_train_bytes", "rt_surrogate_train", "rt_surrogate_calibrate",
-           "rt_surrogate_load", "rt_illuminate"]
+           "rt_surrogate_load", "rt_illuminate", "rt_trace_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20   # RT_NOALLOC_SCRATCH_BYTES
 MLP_PARAMS = 134918
 
 
@@ -104,6 +105,8 @@ _lib.rt_set_scene.argtypes = [_P, C.POINTER(rt_scene)]
 _lib.rt_set_scene.restype = C.c_int
 _lib.rt_trace.argtypes = [_P, C.POINTER(rt_camera), C.POINTER(rt_step_rule), C.c_int, C.POINTER(rt_outputs), _P]
 _lib.rt_trace.restype = C.c_int
+_lib.rt_trace_noalloc.argtypes = [_P, C.POINTER(rt_camera), C.POINTER(rt_step_rule), C.c_int, C.POINTER(rt_outputs), _P]
+_lib.rt_trace_noalloc.restype = C.c_int
 _lib.rt_illuminate.argtypes = [_P, C.POINTER(rt_camera), C.POINTER(rt_outputs), C.POINTER(rt_light),
                                C.POINTER(rt_shading), _P]
 _lib.rt_illuminate.restype = C.c_int
@@ -243,10 +246,12 @@ class Tracer:
                     dir=torch.empty((n, 3), dtype=torch.float32, device=dev),
                     steps=torch.empty(n, dtype=torch.int32, device=dev) if with_steps else None)
 
-    def trace_into(self, camera, rule, max_steps, out, stream=None):
+    def trace_into(self, camera, rule, max_steps, out, stream=None, noalloc=False):
         """Enqueue a trace writing into the tensors of `out` (see
         alloc_outputs); asynchronous on `stream` (torch stream or None for
-        torch's current stream)."""
+        torch's current stream).  noalloc: call rt_trace_noalloc, whose
+        workspace is the library's static per-GPU array (no device
+        allocation inside the call)."""
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -263,8 +268,8 @@ class Tracer:
                        steps.data_ptr() if steps is not None else None)
         cam = camera_struct(camera)
         r = rule_struct(rule)
-        self._check(_lib.rt_trace(self._h, C.byref(cam), C.byref(r), int(max_steps), C.byref(o),
-                                  C.c_void_p(stream.cuda_stream)))
+        fn = _lib.rt_trace_noalloc if noalloc else _lib.rt_trace
+        self._check(fn(self._h, C.byref(cam), C.byref(r), int(max_steps), C.byref(o), C.c_void_p(stream.cuda_stream)))
         return out
 
     def trace(self, camera, rule, max_steps=None, with_steps=True):
@@ -308,11 +313,12 @@ class Tracer:
         self._check(_lib.rt_illuminate(self._h, C.byref(camera_struct(camera)), C.byref(o), C.byref(L), C.byref(sh),
                                        C.c_void_p(stream_handle)))
 
-    def trace_raw(self, camera, rule, max_steps, out_ptrs, stream_handle):
+    def trace_raw(self, camera, rule, max_steps, out_ptrs, stream_handle, noalloc=False):
         """Enqueue with raw device pointers (hit, t, id, dir, steps-or-0)."""
         o = rt_outputs(*[p if p else None for p in out_ptrs])
-        self._check(_lib.rt_trace(self._h, C.byref(camera_struct(camera)), C.byref(rule_struct(rule)),
-                                  int(max_steps), C.byref(o), C.c_void_p(stream_handle)))
+        fn = _lib.rt_trace_noalloc if noalloc else _lib.rt_trace
+        self._check(fn(self._h, C.byref(camera_struct(camera)), C.byref(rule_struct(rule)), int(max_steps), C.byref(o),
+                       C.c_void_p(stream_handle)))
 
     # ---- differentiation (graph metric, RK4)
     def tape_bytes(self, camera, max_steps, ckpt_every):

@@ -68,6 +68,26 @@ def test_host_only_context_validates():
     assert e.value.status == rt.RT_EINVAL
 
 
+def test_noalloc_trace_validates():
+    """rt_trace_noalloc shares rt_trace's validation; it also refuses the
+    flags that need allocations, before looking at the device."""
+    rt = _rt()
+    tr = rt.Tracer(-1)
+    wl = W.get("bumps16_1080p")
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    cam, rule = wl["camera"], wl["rule"]
+    for flags in (rt.FLAG_TIMING, rt.FLAG_SURROGATE, rt.FLAG_TIMING | rt.FLAG_COUNT_WORK):
+        with pytest.raises(rt.RtError) as e:
+            tr.trace_raw(cam, dict(rule, flags=flags), 10, (16, 16, 16, 16, 0), 0, noalloc=True)
+        assert e.value.status == rt.RT_EUNSUPPORTED
+    for c_, r_, ms, want in [(dict(cam, width=0), rule, 10, rt.RT_EINVAL), (cam, dict(rule, h=0.0), 10, rt.RT_EINVAL),
+                             (cam, rule, 0, rt.RT_EINVAL), (cam, rule, 10, rt.RT_ESTATE)]:
+        with pytest.raises(rt.RtError) as e:
+            tr.trace_raw(c_, r_, ms, (16, 16, 16, 16, 0), 0, noalloc=True)
+        assert e.value.status == want
+
+
 def test_metric_and_scene_validation():
     rt = _rt()
     tr = rt.Tracer(-1)
