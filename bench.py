@@ -24,8 +24,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector, published (counts packed FMA)
-FP32_PEAK_NONPACKED = 78.6    # 256 CU x 128 FP32 lanes-flops/clk x 2.4 GHz without packed math
+FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector, published
+# (measured on gfx950: a wave64 FP32 VALU instruction whose operands are all
+# VGPRs or constants issues every 2 cycles, which reaches this peak without
+# packed math; one that reads an SGPR takes 4 cycles, a transcendental 8)
 
 # Algorithmic FLOPs per unit (FMA = 2, each transcendental = 1); derived
 # from the formulas the kernels evaluate: FMA = 2, each transcendental = 1.
@@ -60,6 +62,16 @@ FLOPS = {
     # chord length, two-float position and time updates, velocity update 39
     "dp5_attempt": 521,
     "obj_test": 20,          # one segment-object test
+    # adjoint (RK4, graph metric), per full step reversed: the stage sums
+    # recomputed 4 x 16, the stage VJP overheads 4 x 32 (|y|^2 5, 1/(1 + |g|^2) 7,
+    # g.abar 5, qbar 1, gbar 14) and the VJP of the RK4 combination 216;
+    # per bump term inside its cut: 27 (its stage sum) + 87 (its VJP: d, |d|^2,
+    # exp, w, d.y, Cw, the cotangents of d and y, and of a, c, sigma)
+    "adj_rev_step": 408,
+    "adj_term": 114,
+    # per step recomputed from a checkpoint: one RK4 step with its 4 evaluations
+    # (106 + 4 x 16) plus 27 per bump term inside its cut
+    "adj_recomp_step": 170,
 }
 
 
@@ -189,14 +201,16 @@ def bench_adjoint(args, wl, torch, rt):
         tr.trace_fwd_ckpt(cam, rule, rule["max_steps"], ck, out=out, tape=tape)
         e1.record()
         loss, gh = tr.loss_l2(cam, out["hit"], out["id"], target["hit"], target["id"])
+        e3.record()
         g = tr.trace_bwd(tape, gh, nb)
         return loss, g
 
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    # HIP events on the stream every kernel of the step runs on (torch's current one)
+    e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    fwd_ms = tot_ms = 0.0
+    fwd_ms = tot_ms = bwd_ms = 0.0
     for _ in range(args.steps):
         e0.record()
         loss, g = step()
@@ -204,7 +218,16 @@ def bench_adjoint(args, wl, torch, rt):
         torch.cuda.synchronize()
         fwd_ms += e0.elapsed_time(e1)
         tot_ms += e0.elapsed_time(e2)
+        bwd_ms += e3.elapsed_time(e2)
     st = tr.stats()
+    # algorithmic FLOPs of one rt_trace_bwd from its work counters; the bump
+    # terms of the recomputed steps are taken in proportion to the reversed
+    # steps' (the two walk the same states, less each segment's last step)
+    S, T, Rc = st["adj_steps"], st["adj_bump_terms"], st["adj_recomputed"]
+    adj_flops = (FLOPS["adj_rev_step"] * S + FLOPS["adj_term"] * T +
+                 Rc * (FLOPS["adj_recomp_step"] + FLOPS["graph_bump"] * (T / max(S, 1))))
+    adj_ms = bwd_ms / args.steps
+    achieved = adj_flops / (adj_ms * 1e-3) / 1e12
     n_rays = tr.n_sets * cam["width"] * cam["height"]
     ms = tot_ms / args.steps
     line = {
@@ -217,6 +240,11 @@ def bench_adjoint(args, wl, torch, rt):
         "forward_ms": fwd_ms / args.steps, "backward_ms": (tot_ms - fwd_ms) / args.steps,
         "tape_gb": tape.numel() * 4 / 1e9, "ray_steps_forward": st["ray_steps"],
         "loss_mean": float(loss.mean()), "grad_abs_max": float(g.abs().max()),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": "k_adjoint",
+                     "flops_per_launch": adj_flops, "kernel_ms_per_launch": adj_ms},
+        "adjoint_work": {"steps_reversed": S, "steps_recomputed": Rc, "bump_terms": T,
+                         "bump_terms_per_step": T / max(S, 1)},
     }
     print(json.dumps(line), flush=True)
 
@@ -552,7 +580,7 @@ def main():
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, rule["pass_steps"]),
                      "kernel": "k_trace_pass", "flops_per_trace": flops,
                      "kernel_ms_per_launch": pass_ms / max(1, n_pass_launches),
-                     "frac_of_nonpacked_peak": achieved / FP32_PEAK_NONPACKED},
+                     },
         "kernel_ms": {"passes": pass_ms / args.steps, "refine": refine_ms / args.steps,
                       "compaction": compact_ms / args.steps},
         "work": {"ray_steps": work["ray_steps"], "acc_evals": work["acc_evals"],

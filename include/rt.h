@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 4
+#define RT_ABI_VERSION 5
 
 typedef enum rt_status {
     RT_OK = 0,
@@ -312,6 +312,9 @@ typedef struct rt_stats {
     uint64_t accepted;      /* SURROGATE: crossings replaced by the network's prediction */
     float surr_ms;          /* SURROGATE + TIMING: summed duration of the crossing stages */
     int eligible;           /* SURROGATE: bumps whose support sphere the networks may replace */
+    uint64_t adj_steps;     /* rt_trace_bwd since the last trace: full RK4 steps reversed */
+    uint64_t adj_bump_terms; /* rt_trace_bwd: bump terms inside their cut at those steps' stages */
+    uint64_t adj_recomputed; /* rt_trace_bwd: full RK4 steps recomputed from the checkpoints */
 } rt_stats;
 
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);

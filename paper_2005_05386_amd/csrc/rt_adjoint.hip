@@ -28,10 +28,12 @@ constexpr int ADJ_MAX_BUMPS = 16;
 
 // ---------------------------------------------------------- per-lane sums
 // Gradient accumulators of one lane live in LDS: tb[(b * 5 + j) * 64 + lane]
-// for bump b, parameter j in (a, cx, cy, cz, sigma).
+// for bump b, parameter j in (a, cx, cy, cz, sigma).  (A read-modify-write:
+// non-returning LDS atomic adds measured twice as slow here.)
 struct ThetaBar {
     float *tb;
     int lane;
+    unsigned terms;  // bump terms inside their cut seen by the parameter VJPs
     __device__ __forceinline__ void add(int b, int j, float v) { tb[(b * 5 + j) * 64 + lane] += v; }
 };
 
@@ -89,7 +91,7 @@ __device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, uint64_t
     const float yy = dot(y, y);
     const float q = S.q;
     const V3<float> g = mk(S.gx, S.gy, S.gz);
-    const float invD = 1.0f / (1.0f + dot(g, g));
+    const float invD = rcp_(1.0f + dot(g, g));
     const float ga = dot(g, ab);
     // a = -(q / D) g:  gbar = -(q/D) abar + (2 q / D^2)(g . abar) g,  qbar = -(g . abar)/D
     const float qbar = -ga * invD;
@@ -113,13 +115,14 @@ __device__ __forceinline__ void graph_vjp(const float4 *__restrict__ B, uint64_t
         pb = pb + Cd;
         yb = axpy(2.0f * qbar * w, axpy(-1.0f, y, s * u * d), yb);
         if (ACC) {
-            const float Cs = qbar * w * u * u + Cw * (w / s) * (1.0f - 0.5f * s * r2);
+            T.terms++;
             const float sig = b1.w;
+            const float Cs = qbar * w * u * u + Cw * (w * sig * sig) * (1.0f - 0.5f * s * r2);
             T.add(b, 0, Cw * s * e);
             T.add(b, 1, -Cd.x);
             T.add(b, 2, -Cd.y);
             T.add(b, 3, -Cd.z);
-            T.add(b, 4, -2.0f * Cs * s / sig);
+            T.add(b, 4, -2.0f * Cs * s * rcp_(sig));
         }
     }
 }
@@ -210,8 +213,8 @@ __device__ __forceinline__ V3<float> obj_grad(const TraceArgs &A, const float4 *
     float e = rn - tp[6];
     float sd = sqrt_(e * e + ax * ax);
     // grad = ((|q_perp| - R) q_perp / |q_perp| + q_par a) / sdf_inner
-    V3<float> gr = axpy(ax, a, (e / fmaxf(rn, 1e-30f)) * rad);
-    return (1.0f / fmaxf(sd, 1e-30f)) * gr;
+    V3<float> gr = axpy(ax, a, (e * rcp_(fmaxf(rn, 1e-30f))) * rad);
+    return rcp_(fmaxf(sd, 1e-30f)) * gr;
 }
 
 __device__ __forceinline__ V3<float> pixel_dir(const TraceArgs &A, int pi, int pj) {
@@ -225,10 +228,21 @@ __device__ __forceinline__ V3<float> pixel_dir(const TraceArgs &A, int pi, int p
 struct AdjArgs {
     const float *grad_hit;   // [n_sets * H * W][3]
     float *partial;          // [chunks][n_bumps * 5] per-chunk gradient sums
-    float *scratch;          // [grid blocks][ckpt_every][9][64] recomputed states
+    float *scratch;          // [grid blocks][ckpt_every][6][64] recomputed positions and velocities
+    int *next;               // chunk queue (zeroed by k_adj_reset)
+    unsigned long long *stats;  // ST_ADJ_STEPS, ST_ADJ_TERMS (zeroed by k_adj_reset)
 };
 
-// One wave (one block of 64 threads) per chunk of 64 ray ids.
+__global__ void k_adj_reset(int *next, unsigned long long *stats) {
+    if (threadIdx.x == 0) *next = 0;
+    if (threadIdx.x == 1) stats[rti::ST_ADJ_STEPS] = 0;
+    if (threadIdx.x == 2) stats[rti::ST_ADJ_TERMS] = 0;
+    if (threadIdx.x == 3) stats[rti::ST_ADJ_RECOMP] = 0;
+}
+
+// One wave (one block of 64 threads) per chunk of 64 ray ids; persistent
+// blocks take chunks from an atomic queue (ray costs vary: misses and hits
+// that carry no gradient cost nothing, early hits little).
 __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const float4 *__restrict__ BF,
                                                 const float4 *__restrict__ SPH, const float4 *__restrict__ PLN,
                                                 const float *__restrict__ TOR) {
@@ -240,14 +254,19 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
     const int HW = A.width * A.height;
     const int n_chunks = A.n_sets * tiles;
     const int ck = A.ckpt_every;
-    float *scr = J.scratch + (int64_t)blockIdx.x * ck * 9 * 64 + lane;
-    ThetaBar T{tb_mem, lane};
+    float *scr = J.scratch + (int64_t)blockIdx.x * ck * 6 * 64 + lane;
+    ThetaBar T{tb_mem, lane, 0u};
+    unsigned n_rev = 0, n_rec = 0;  // full steps this lane reversed and recomputed
     // culling window: CULL steps (plus the stages of one more) of Euclidean
     // length <= h each, since g >= I keeps a g-unit velocity at |y| <= 1
     constexpr int CULL = 16;
     const float margin = (float)(CULL + 1) * A.h * 1.02f + 1e-4f;
 
-    for (int chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    for (;;) {
+        int chunk = 0;
+        if (lane == 0) chunk = atomicAdd(J.next, 1);
+        chunk = uniform_i(__shfl(chunk, 0));
+        if (chunk >= n_chunks) break;
         const int set = chunk / tiles;
         const int tile = chunk - set * tiles;
         const int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
@@ -323,16 +342,15 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
             uint64_t wm = 0;
             for (int j = 0; j < lmax; ++j) {
                 if (j < len) {
-                    float *sp = scr + (int64_t)j * 9 * 64;
-                    sp[0] = h0.x;
-                    sp[64] = h0.y;
-                    sp[128] = h0.z;
-                    sp[192] = l0.x;
-                    sp[256] = l0.y;
-                    sp[320] = l0.z;
-                    sp[384] = y0.x;
-                    sp[448] = y0.y;
-                    sp[512] = y0.z;
+                    // the reverse step needs only the rounded position x_hi + x_lo
+                    const V3<float> x = h0 + l0;
+                    float *sp = scr + (int64_t)j * 6 * 64;
+                    sp[0] = x.x;
+                    sp[64] = x.y;
+                    sp[128] = x.z;
+                    sp[192] = y0.x;
+                    sp[256] = y0.y;
+                    sp[320] = y0.z;
                 }
                 if (j + 1 < lmax) {
                     if (j % CULL == 0) wm = cull_mask(Bs, nb, h0 + l0, j + 1 < len, margin);
@@ -340,6 +358,7 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
                         Acc32<KIND_GRAPH, false> accw{Bs, wm, 0.f, 0.f, nullptr, nullptr};
                         V3<float> dx, dv;
                         step_rk4<float>(accw, h0 + l0, y0, A.h, dx, dv);
+                        n_rec++;
                         two_sum_add(h0.x, l0.x, dx.x);
                         two_sum_add(h0.y, l0.y, dx.y);
                         two_sum_add(h0.z, l0.z, dx.z);
@@ -354,15 +373,17 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
             // window it is reversed under.
             for (int j = lmax - 1; j >= 0; --j) {
                 const bool has = j < len;
-                V3<float> ph = mk(0.f, 0.f, 0.f), pl = ph, vy = ph;
+                V3<float> px = mk(0.f, 0.f, 0.f), vy = px;
                 if (has) {
-                    const float *sp = scr + (int64_t)j * 9 * 64;
-                    ph = mk(sp[0], sp[64], sp[128]);
-                    pl = mk(sp[192], sp[256], sp[320]);
-                    vy = mk(sp[384], sp[448], sp[512]);
+                    const float *sp = scr + (int64_t)j * 6 * 64;
+                    px = mk(sp[0], sp[64], sp[128]);
+                    vy = mk(sp[192], sp[256], sp[320]);
                 }
-                if (j % CULL == CULL - 1 || ballot(j == len - 1)) wm = cull_mask(Bs, nb, ph + pl, has, margin);
-                if (has) (void)rk4_vjp<true>(Bs, wm, ph + pl, vy, A.h, xb, yb, T);
+                if (j % CULL == CULL - 1 || ballot(j == len - 1)) wm = cull_mask(Bs, nb, px, has, margin);
+                if (has) {
+                    (void)rk4_vjp<true>(Bs, wm, px, vy, A.h, xb, yb, T);
+                    n_rev++;
+                }
             }
         }
         // ---- the initial velocity y0 = d / sqrt(|d|^2 + (grad f . d)^2) at the eye
@@ -404,6 +425,19 @@ __global__ __launch_bounds__(64) void k_adjoint(TraceArgs A, AdjArgs J, const fl
         }
         __syncthreads();
     }
+    // work counters of this wave (integers: the sums are exact in any order)
+    unsigned long long steps = n_rev, terms = T.terms, rec = n_rec;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        steps += __shfl_xor(steps, o);
+        terms += __shfl_xor(terms, o);
+        rec += __shfl_xor(rec, o);
+    }
+    if (lane == 0) {
+        atomicAdd(J.stats + rti::ST_ADJ_STEPS, steps);
+        atomicAdd(J.stats + rti::ST_ADJ_TERMS, terms);
+        atomicAdd(J.stats + rti::ST_ADJ_RECOMP, rec);
+    }
 }
 
 // Compensated FP32 sum in a fixed order: the rounding error of every
@@ -421,15 +455,31 @@ struct TwoSumAcc {
     __device__ float value() const { return s + c; }
 };
 
-// grad[set][param] = sum over the set's chunks, in chunk order.
-__global__ void k_grad_reduce(const float *__restrict__ partial, int n_sets, int tiles, int np5,
-                              float *__restrict__ grad) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+// grad[set][param] = sum over the set's chunks: one wave per output; lane l
+// sums chunks l, l + 64, ... with a compensated sum, then the 64 partial
+// (sum, error) pairs are combined in a fixed butterfly order.  The result
+// does not depend on the launch.
+__global__ __launch_bounds__(64) void k_grad_reduce(const float *__restrict__ partial, int n_sets, int tiles,
+                                                    int np5, float *__restrict__ grad) {
+    const int t = blockIdx.x;
     if (t >= n_sets * np5) return;
-    int set = t / np5, j = t - set * np5;
+    const int set = t / np5, j = t - set * np5, lane = threadIdx.x;
     TwoSumAcc acc;
-    for (int c = 0; c < tiles; ++c) acc.add(partial[((int64_t)set * tiles + c) * np5 + j]);
-    grad[t] = acc.value();
+    for (int c = lane; c < tiles; c += 64) acc.add(partial[((int64_t)set * tiles + c) * np5 + j]);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float s2 = __shfl_xor(acc.s, o), c2 = __shfl_xor(acc.c, o);
+        // both lanes of a pair form the same sum: combine the lower lane's
+        // pair first so the two agree bit for bit
+        const bool low = (lane & o) == 0;
+        TwoSumAcc m;
+        m.s = low ? acc.s : s2;
+        m.c = low ? acc.c : c2;
+        m.add(low ? s2 : acc.s);
+        m.c += low ? c2 : acc.c;
+        acc = m;
+    }
+    if (lane == 0) grad[t] = acc.value();
 }
 
 // Masked L2 loss: pixel p counts if mask[p] (when given), id[p] >= 0 and
@@ -478,15 +528,19 @@ __global__ void k_loss_reduce(const float *__restrict__ block_sum, int nblk, int
 namespace rti {
 
 hipError_t launch_adjoint(const TraceArgs &a, const DeviceData &d, const float *grad_hit, float *partial,
-                          float *grad, float *scratch, int blocks, hipStream_t s) {
-    AdjArgs J{grad_hit, partial, scratch};
+                          float *grad, float *scratch, int *next, unsigned long long *stats, int blocks,
+                          hipStream_t s) {
+    AdjArgs J{grad_hit, partial, scratch, next, stats};
     size_t lds = (size_t)a.n_bumps * 5 * 64 * sizeof(float);
-    hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(64), lds, s, a, J, d.bump_f, d.sph_f, d.pln_f, d.tor_f);
+    hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(64), 0, s, next, stats);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(64), lds, s, a, J, d.bump_f, d.sph_f, d.pln_f, d.tor_f);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     int np5 = a.n_bumps * 5;
     int n = a.n_sets * np5;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, (const float *)partial, a.n_sets,
+    hipLaunchKernelGGL(k_grad_reduce, dim3(n), dim3(64), 0, s, (const float *)partial, a.n_sets,
                        a.tiles_x * a.tiles_y, np5, grad);
     return hipGetLastError();
 }
@@ -504,5 +558,12 @@ hipError_t launch_loss(const float *hit, const int *id, const float *thit, const
 }
 
 int adjoint_max_bumps() { return ADJ_MAX_BUMPS; }
+
+int adjoint_blocks_per_cu(int n_bumps) {
+    int n = 0;
+    size_t lds = (size_t)n_bumps * 5 * 64 * sizeof(float);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adjoint, 64, lds) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
+}
 
 }  // namespace rti

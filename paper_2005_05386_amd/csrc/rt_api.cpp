@@ -1135,9 +1135,12 @@ rt_status rt_trace_bwd(rt_ctx *c, const void *tape, const float *grad_hit, float
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     int64_t chunks = (int64_t)a.n_sets * a.tiles_x * a.tiles_y;
-    int blocks = (int)std::min<int64_t>(chunks, (int64_t)c->n_cu * 16);
-    int64_t scr = (int64_t)blocks * a.ckpt_every * 9 * 64;
-    int64_t part = chunks * a.n_bumps * 5;
+    // persistent one-wave blocks, as many as stay resident (more would wait
+    // for a slot and finish their chunk share late)
+    int blocks = (int)std::min<int64_t>(chunks, (int64_t)c->n_cu * rti::adjoint_blocks_per_cu(a.n_bumps));
+    if (blocks < 1) blocks = 1;
+    int64_t scr = (int64_t)blocks * a.ckpt_every * 6 * 64;
+    int64_t part = chunks * a.n_bumps * 5 + 64;  // + the chunk queue counter
     if (c->adj_scr_cap < scr || c->adj_part_cap < part) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
@@ -1152,7 +1155,8 @@ rt_status rt_trace_bwd(rt_ctx *c, const void *tape, const float *grad_hit, float
         c->adj_part_cap = part;
     }
     hipStream_t s = (hipStream_t)stream;
-    e = rti::launch_adjoint(a, c->dd, grad_hit, c->d_adj_part, grad_params, c->d_adj_scr, blocks, s);
+    e = rti::launch_adjoint(a, c->dd, grad_hit, c->d_adj_part, grad_params, c->d_adj_scr,
+                            (int *)(c->d_adj_part + chunks * a.n_bumps * 5), c->d_stats, blocks, s);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch (adjoint)");
     c->last_stream = s;
     return RT_OK;
@@ -1533,6 +1537,9 @@ rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
     out->passes = c->last_passes;
     out->crossings = v[rti::ST_XING];
     out->accepted = v[rti::ST_XACC];
+    out->adj_steps = v[rti::ST_ADJ_STEPS];
+    out->adj_bump_terms = v[rti::ST_ADJ_TERMS];
+    out->adj_recomputed = v[rti::ST_ADJ_RECOMP];
     out->eligible = c->last_surr_flag ? c->surr_eligible : 0;
     if (c->last_timed) {
         // events: 0 before reset, 1 after reset, 2+p after pass p, 2+np after

@@ -64,6 +64,9 @@ enum Stat {
     ST_OBJ_TESTS,
     ST_XING,  // surrogate crossings queued
     ST_XACC,  // surrogate crossings accepted
+    ST_ADJ_STEPS,  // adjoint: full RK4 steps reversed
+    ST_ADJ_TERMS,  // adjoint: bump terms inside their cut at the reversed steps' stages
+    ST_ADJ_RECOMP, // adjoint: full RK4 steps recomputed from the checkpoints
     ST_N
 };
 
@@ -269,8 +272,12 @@ hipError_t launch_surr_stage(const TraceArgs &a, const SurrArgs &S, const float4
 
 // Adjoint of a taped RK4 trace (graph metric): per-chunk partial gradients,
 // then per-set sums into grad [n_sets][n_bumps][5].
+// blocks: persistent one-wave blocks (adjoint_blocks_per_cu x CUs); scratch
+// holds ckpt_every x 6 x 64 floats per block; next: one int (chunk queue).
 hipError_t launch_adjoint(const TraceArgs &a, const DeviceData &d, const float *grad_hit, float *partial,
-                          float *grad, float *scratch, int blocks, hipStream_t s);
+                          float *grad, float *scratch, int *next, unsigned long long *stats, int blocks,
+                          hipStream_t s);
+int adjoint_blocks_per_cu(int n_bumps);
 hipError_t launch_loss(const float *hit, const int *id, const float *thit, const int *tid, const unsigned char *mask,
                        int n_sets, int HW, float *grad_hit, float *block_sum, float *loss, hipStream_t s);
 int adjoint_max_bumps();

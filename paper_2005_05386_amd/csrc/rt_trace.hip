@@ -103,8 +103,11 @@ __global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restri
 // TAPE: differentiation forward (graph metric, RK4): checkpoints of the
 // state every ckpt_every steps; a separate instantiation, so that the plain
 // trace carries no per-step checkpoint test.
+#ifndef RT_PASS_WAVES
+#define RT_PASS_WAVES 7  // waves per SIMD the RK4 and Euler pass kernels are compiled for
+#endif
 template <int KIND, int STEP, bool COUNT, bool SURR = false, bool TAPE = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 ? 6 : 7, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 ? 6 : RT_PASS_WAVES, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
                                                     const float *__restrict__ TOR) {

@@ -88,7 +88,8 @@ class rt_stats(C.Structure):
                 ("bump_evals", C.c_uint64), ("obj_tests", C.c_uint64), ("passes", C.c_int), ("pass_ms", C.c_float),
                 ("refine_ms", C.c_float), ("compact_ms", C.c_float), ("total_ms", C.c_float),
                 ("crossings", C.c_uint64), ("accepted", C.c_uint64), ("surr_ms", C.c_float),
-                ("eligible", C.c_int)]
+                ("eligible", C.c_int), ("adj_steps", C.c_uint64), ("adj_bump_terms", C.c_uint64),
+                ("adj_recomputed", C.c_uint64)]
 
 
 _P = C.c_void_p

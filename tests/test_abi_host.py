@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(rt.lib(), n), n
     assert sorted(rt.EXPORTS) == names
-    assert rt.abi_version() == 4
+    assert rt.abi_version() == 5
 
 
 def test_host_only_context_validates():
