@@ -47,7 +47,8 @@ constexpr int64_t MLP_P_PAD = 134920;
 constexpr int MAX_PASSES_API = 512;
 constexpr int SCAN_BLOCK = 1024;     // chunks per block of the survivor scan
 
-// Refine record: 5 float4 (80 bytes).
+// Refine record: at most 5 float4 (80 bytes; 4 for RK4 and Euler traces
+// without learned crossings).
 constexpr int REC_F4 = 5;
 
 enum Stat {

@@ -50,46 +50,26 @@ __device__ __forceinline__ void write_out(const TraceArgs &A, unsigned oi, V3<fl
     if (A.out_steps) A.out_steps[oi] = steps;
 }
 
+// Refine record of a chord hit: 4 float4 (64 B) where t is steps * h and
+// the hit step is h (RK4 and Euler without learned crossings), else 5
+// (80 B: also t as two floats and the step size).
+constexpr bool compact_record(int step, bool surr) { return step != STEP_RK45 && !surr; }
+
 // ========================================================= ray generation
-// Initial state of every ray: x = eye, y = the pixel direction d scaled to
-// unit length in the metric at the eye (y = d / sqrt(g(d, d))).
+// Initial state of a ray: x = eye, y = the pixel direction d scaled to unit
+// length in the metric at the eye (y = d / sqrt(g(d, d))).  Computed by the
+// first pass in registers, so the state makes no trip through memory.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_gen(TraceArgs A, const float4 *__restrict__ BF) {
-    const int64_t n = A.cap;
-    for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < n; id += (int64_t)gridDim.x * blockDim.x) {
-        const int set = (int)(id / A.T);
-        const int r = (int)(id - (int64_t)set * A.T);
-        const int tile = r >> 6, ln = r & 63;
-        const int ty = tile / A.tiles_x, tx = tile - ty * A.tiles_x;
-        const int pi = tx * 8 + (ln & 7), pj = ty * 8 + (ln >> 3);
-        if (pi >= A.width || pj >= A.height) continue;
-        const float4 *__restrict__ Bs = BF + (int64_t)set * A.n_bumps * (is_deform(KIND) ? DEFORM_F4 : 2);
-        float su = (2.0f * ((float)pi + 0.5f) / (float)A.width - 1.0f) * A.tan_half * A.aspect;
-        float sv = (1.0f - 2.0f * ((float)pj + 0.5f) / (float)A.height) * A.tan_half;
-        V3<float> d = mk(su * A.right[0] + sv * A.up[0] + A.fwd[0], su * A.right[1] + sv * A.up[1] + A.fwd[1],
-                         su * A.right[2] + sv * A.up[2] + A.fwd[2]);
-        d = rsqrt_(dot(d, d)) * d;
-        V3<float> e = mk(A.eye[0], A.eye[1], A.eye[2]);
-        const float gdd = metric_gdd<KIND>(Bs, A.n_bumps, A.twist_amp, A.twist_theta0, e, d);
-        V3<float> y = rsqrt_(gdd) * d;
-        float *__restrict__ dst = A.st + ((id >> 6) * rti::Q_NFIELDS * 64 + (id & 63));
-        auto P = [&](int f, float v) { dst[f * 64] = v; };
-        P(rti::Q_XH, e.x);
-        P(rti::Q_XH + 1, e.y);
-        P(rti::Q_XH + 2, e.z);
-        P(rti::Q_XL, 0.f);
-        P(rti::Q_XL + 1, 0.f);
-        P(rti::Q_XL + 2, 0.f);
-        P(rti::Q_Y, y.x);
-        P(rti::Q_Y + 1, y.y);
-        P(rti::Q_Y + 2, y.z);
-        P(rti::Q_TH, 0.f);
-        P(rti::Q_TL, 0.f);
-        P(rti::Q_H, A.h);
-        P(rti::Q_STEPS, __int_as_float(0));
-        P(rti::Q_ATT, __int_as_float(0));
-        P(rti::Q_SKIP, __int_as_float(-1));
-    }
+__device__ __forceinline__ V3<float> initial_velocity(const TraceArgs &A, const float4 *__restrict__ Bs, int pi,
+                                                      int pj) {
+    float su = (2.0f * ((float)pi + 0.5f) / (float)A.width - 1.0f) * A.tan_half * A.aspect;
+    float sv = (1.0f - 2.0f * ((float)pj + 0.5f) / (float)A.height) * A.tan_half;
+    V3<float> d = mk(su * A.right[0] + sv * A.up[0] + A.fwd[0], su * A.right[1] + sv * A.up[1] + A.fwd[1],
+                     su * A.right[2] + sv * A.up[2] + A.fwd[2]);
+    d = rsqrt_(dot(d, d)) * d;
+    const V3<float> e = mk(A.eye[0], A.eye[1], A.eye[2]);
+    const float gdd = metric_gdd<KIND>(Bs, A.n_bumps, A.twist_amp, A.twist_theta0, e, d);
+    return rsqrt_(gdd) * d;
 }
 
 // ================================================================ the pass
@@ -177,7 +157,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
             float th = 0.f, tl = 0.f, hc = A.h;
             int steps = 0, att = 0;
             int skip = -1;  // SURR only
-            if (valid) {
+            if (valid && pass == 0) {
+                xh = mk(A.eye[0], A.eye[1], A.eye[2]);
+                xl = mk(0.f, 0.f, 0.f);
+                y = initial_velocity<KIND>(A, Bs, pi, pj);
+            } else if (valid) {
                 const float *__restrict__ src = st + ((int64_t)(id >> 6) * rti::Q_NFIELDS * 64 + (id & 63));
                 auto F = [&](int f) { return src[f * 64]; };
                 xh = mk(F(rti::Q_XH), F(rti::Q_XH + 1), F(rti::Q_XH + 2));
@@ -543,14 +527,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                     base = uniform_i(__shfl(base, 0));
                     if (hit) {
                         int64_t r = base + mbcnt64(hm);
-                        float4 *rec = A.rec + rti::REC_F4 * r;
-                        rec[0] = make_float4(xh.x, xh.y, xh.z, xl.x);
-                        rec[1] = make_float4(xl.y, xl.z, y.x, y.y);
-                        rec[2] = make_float4(y.z, th, hstep, hit_s);
-                        rec[3] = make_float4(__int_as_float(hit_id), __int_as_float((int)(qbase + pix)),
-                                             __int_as_float(steps), tl);
-                        rec[4] = make_float4(__int_as_float((int)(uint32_t)bmask), __int_as_float((int)(bmask >> 32)),
-                                             0.f, 0.f);
+                        if constexpr (compact_record(STEP, SURR)) {
+                            // t = steps h and the step is h: 4 float4
+                            float4 *rec = A.rec + 4 * r;
+                            rec[0] = make_float4(xh.x, xh.y, xh.z, xl.x);
+                            rec[1] = make_float4(xl.y, xl.z, y.x, y.y);
+                            rec[2] = make_float4(y.z, hit_s, __int_as_float(hit_id), __int_as_float((int)(qbase + pix)));
+                            rec[3] = make_float4(__int_as_float(steps), __int_as_float((int)(uint32_t)bmask),
+                                                 __int_as_float((int)(bmask >> 32)), 0.f);
+                        } else {
+                            float4 *rec = A.rec + rti::REC_F4 * r;
+                            rec[0] = make_float4(xh.x, xh.y, xh.z, xl.x);
+                            rec[1] = make_float4(xl.y, xl.z, y.x, y.y);
+                            rec[2] = make_float4(y.z, th, hstep, hit_s);
+                            rec[3] = make_float4(__int_as_float(hit_id), __int_as_float((int)(qbase + pix)),
+                                                 __int_as_float(steps), tl);
+                            rec[4] = make_float4(__int_as_float((int)(uint32_t)bmask),
+                                                 __int_as_float((int)(bmask >> 32)), 0.f, 0.f);
+                        }
                     }
                 }
                 if constexpr (SURR) {
@@ -656,15 +650,29 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
     const int n = A.ctr[rti::CTR_REFINE];
     const int HW = A.width * A.height;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-        const float4 *rec = A.rec + rti::REC_F4 * (int64_t)r;
-        float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3], r4 = rec[4];
+        float4 r0, r1, r2, r3, r4;
+        double tk_hi, tk_lo, h, sc;
+        int obj, oi, k;
+        uint64_t mask;
+        if (!A.surr && compact_record(STEP, false)) {
+            const float4 *rec = A.rec + 4 * (int64_t)r;
+            r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
+            tk_hi = tk_lo = 0.0;
+            h = A.h;
+            sc = r2.y;
+            obj = __float_as_int(r2.z), oi = __float_as_int(r2.w), k = __float_as_int(r3.x);
+            mask = (uint64_t)(uint32_t)__float_as_int(r3.y) | ((uint64_t)(uint32_t)__float_as_int(r3.z) << 32);
+        } else {
+            const float4 *rec = A.rec + rti::REC_F4 * (int64_t)r;
+            r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3], r4 = rec[4];
+            tk_hi = r2.y, h = r2.z;
+            sc = r2.w;
+            obj = __float_as_int(r3.x), oi = __float_as_int(r3.y), k = __float_as_int(r3.z);
+            tk_lo = r3.w;
+            mask = (uint64_t)(uint32_t)__float_as_int(r4.x) | ((uint64_t)(uint32_t)__float_as_int(r4.y) << 32);
+        }
         V3<double> x = mk((double)r0.x + (double)r0.w, (double)r0.y + (double)r1.x, (double)r0.z + (double)r1.y);
         V3<double> y = mk((double)r1.z, (double)r1.w, (double)r2.x);
-        double tk_hi = r2.y, h = r2.z;
-        double sc = r2.w;
-        int obj = __float_as_int(r3.x), oi = __float_as_int(r3.y), k = __float_as_int(r3.z);
-        double tk_lo = r3.w;
-        uint64_t mask = (uint64_t)(uint32_t)__float_as_int(r4.x) | ((uint64_t)(uint32_t)__float_as_int(r4.y) << 32);
         int set = oi / HW;
         const double *Bs = BD + (int64_t)set * A.n_bumps * (is_deform(KIND) ? DEFORM_D : 8);
         double amp = A.twist_amp, th0 = A.twist_theta0;
@@ -855,10 +863,6 @@ hipError_t launch_kind_step(const TraceArgs &a, const rti::DeviceData &d, int n_
                             hipStream_t s, hipEvent_t *ev, const rti::SurrArgs *S, int mlp_blocks) {
     const int scan_blocks = std::min((a.max_chunks + rti::SCAN_BLOCK - 1) / rti::SCAN_BLOCK, 1024);
     const int scatter_blocks = std::max(1, std::min((a.max_chunks + 3) / 4, 4096));
-    {
-        int gblocks = (int)std::min<int64_t>((a.cap + 255) / 256, 8192);
-        hipLaunchKernelGGL((k_gen<KIND>), dim3(gblocks), dim3(256), 0, s, a, d.bump_f);
-    }
     for (int p = 0; p < n_passes; ++p) {
         if (p > 0) {
             // ordered compaction of the survivors of pass p-1 (not timed as a pass)
