@@ -192,3 +192,86 @@ def test_new_scene_invalidates_tape(env):
     with pytest.raises(rt.RtError) as ei:
         tr.trace_bwd(tape, gh, wl["metric"]["bumps"].shape[1])
     assert ei.value.status == -5
+
+
+def test_adjoint_directional_derivative(env):
+    """Dot-product check of the adjoint: for seeded random directions u in
+    parameter space, <grad L, u> from the GPU adjoint equals the FP64
+    oracle's central difference of L along u, (L(theta + eps u) -
+    L(theta - eps u)) / (2 eps), over pixels whose object is the same at
+    theta and at both perturbed points.  Every parameter moves at once, so
+    this also catches cross terms that coordinate differences see only one
+    at a time."""
+    rt, torch = env
+    say("adjoint: <grad, u> against the FP64 directional difference, 3 random directions, 2 sets x 64x64")
+    n_sets, size, eps = 2, 64, 1e-4
+    wl = W.with_size(W.get("adjoint_64x512", n_sets=n_sets), size, size)
+    HW = size * size
+    theta = wl["metric"]["bumps"]
+    pix = W.pixel_sample(size, size, 400, seed=90)
+    rng = np.random.default_rng(91)
+    for s in range(n_sets):
+        tm = dict(wl["metric"], bumps=wl["target_bumps"])
+        tgt = oracle.Oracle(tm, wl["scene"], s).trace(wl["camera"], wl["rule"], pix)
+        base = theta[s].astype(np.float64)
+        for trial in range(3):
+            u = rng.normal(size=base.shape)
+            u /= np.linalg.norm(u)
+            r0 = oracle.Oracle(wl["metric"], wl["scene"], bumps64=base).trace(wl["camera"], wl["rule"], pix)
+            rp = oracle.Oracle(wl["metric"], wl["scene"], bumps64=base + eps * u).trace(wl["camera"], wl["rule"], pix)
+            rm = oracle.Oracle(wl["metric"], wl["scene"], bumps64=base - eps * u).trace(wl["camera"], wl["rule"], pix)
+            m = (r0["id"] == tgt["id"]) & (r0["id"] >= 0) & (rp["id"] == r0["id"]) & (rm["id"] == r0["id"])
+            fd = (oracle.l2_loss(rp["hit"], tgt["hit"], m) - oracle.l2_loss(rm["hit"], tgt["hit"], m)) / (2 * eps)
+            target_hit = np.zeros((n_sets * HW, 3), np.float32)
+            target_id = np.full(n_sets * HW, -7, np.int32)
+            mask = np.zeros(n_sets * HW, np.uint8)
+            target_hit[s * HW + pix] = tgt["hit"]
+            target_id[s * HW + pix] = tgt["id"]
+            mask[s * HW + pix[m]] = 1
+            g, _, _ = gpu_grad(rt, torch, wl, theta, target_hit, target_id, mask)
+            dot = float((g[s] * u).sum())
+            scale = np.linalg.norm(g[s])
+            say("set %d dir %d: <g,u> %.6g  FD %.6g  |g| %.4g  pixels %d" % (s, trial, dot, fd, scale, int(m.sum())))
+            assert m.sum() > 100
+            assert abs(dot - fd) <= 1e-4 + 1e-3 * scale, (dot, fd, scale)
+
+
+def test_metric_speed_conserved_along_gpu_rays(env):
+    """g(y, y) is a first integral of the geodesic flow: the GPU trace starts
+    every ray at g-unit speed and RK4 at h = 0.01 keeps it to within its
+    truncation and FP32 rounding.  The velocities come from the adjoint
+    tape's checkpoints (x_hi, x_lo, y every 100 steps, blocked by 64 ray
+    ids); g at x is the oracle's FP64 metric tensor."""
+    rt, torch = env
+    say("g(y,y) along GPU rays from the tape checkpoints, 2 sets x 64x64, RK4 h = 0.01")
+    n_sets, size, ck = 2, 64, 100
+    wl = W.with_size(W.get("adjoint_64x512", n_sets=n_sets), size, size)
+    tr = rt.Tracer(0)
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    cam, rule = wl["camera"], wl["rule"]
+    out, tape = tr.trace_fwd_ckpt(cam, rule, rule["max_steps"], ck)
+    torch.cuda.synchronize()
+    steps = out["steps"].cpu().numpy()
+    n_ck = (rule["max_steps"] + ck - 1) // ck
+    T = (size // 8) * (size // 8) * 64
+    ckpt = tape.cpu().numpy()[:n_sets * T * n_ck * 9].reshape(n_sets * T // 64, n_ck, 9, 64)
+    rng = np.random.default_rng(92)
+    worst = 0.0
+    n_pts = 0
+    for s in range(n_sets):
+        orc = oracle.Oracle(wl["metric"], wl["scene"], s)
+        for p in rng.choice(size * size, 150, replace=False):
+            pi, pj = p % size, p // size
+            rid = s * T + ((pj // 8) * (size // 8) + pi // 8) * 64 + (pj % 8) * 8 + (pi % 8)
+            for c in range(n_ck):
+                if c * ck >= steps[s * size * size + p]:
+                    break
+                v = ckpt[rid // 64, c, :, rid % 64].astype(np.float64)
+                x = v[0:3] + v[3:6]
+                y = v[6:9]
+                worst = max(worst, abs(y @ orc.metric_tensor(x) @ y - 1.0))
+                n_pts += 1
+    say("worst |g(y,y) - 1| over %d checkpoints: %.3g" % (n_pts, worst))
+    assert n_pts > 1000
+    assert worst < 1e-5
