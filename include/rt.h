@@ -339,8 +339,16 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
  *            straight segment's length in g at q plus one, or a shot
  *            overran max_steps; -3 the pixel did not hit;
  *   dir    = v (optional), len = T (optional).
+ * A pixel left without a geodesic then retries from the converged
+ * direction and length of a neighbouring pixel (the one of its 8 neighbours
+ * with the nearest hit point), in up to 3 rounds of max(max_iters / 2, 1)
+ * iterations, each round seeded from everything converged so far; the
+ * pixels still without one then follow a continuation in the light
+ * position, aiming at q + lambda (L - q) for lambda = 1/8, 2/8, ..., 1,
+ * each stage from the previous one's solution (max(max_iters / 2, 1)
+ * iterations per stage).
  * Several geodesics may join q and L; the one found is the one reached
- * from the straight segment.  The paper describes this illumination but
+ * from the straight segment or from a neighbour's.  The paper describes this illumination but
  * not how to compute it.  camera must be the traced camera; the metric and
  * scene of the context are used.  Outputs are device arrays of
  * n_sets * height * width entries (dir: 3 per entry).  Asynchronous on

@@ -1032,14 +1032,15 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     a.len = out->len;
     const int64_t n = (int64_t)cam->width * cam->height * c->n_sets;
     // workspace: Newton state (4 floats), the base shot (6 floats), three
-    // pixel lists, the list counters
+    // pixel lists, the list counters of the first round and the retries
     if (c->ibuf_cap < n) {
         rt_status st = sync_last(c);
         if (st != RT_OK) return st;
         (void)hipFree(c->d_ibuf);
         c->d_ibuf = nullptr;
         c->ibuf_cap = 0;
-        e = hipMalloc(&c->d_ibuf, (size_t)n * 52 + 130 * sizeof(int) + 256);
+        e = hipMalloc(&c->d_ibuf, (size_t)n * 52 +
+                                      (1 + rti::ILLUM_RETRY_ROUNDS + rti::ILLUM_CONT_STAGES) * 130 * sizeof(int) + 256);
         if (e != hipSuccess) return hip_fail(c, e, "hipMalloc (illumination workspace)");
         c->ibuf_cap = n;
     }
@@ -1054,6 +1055,8 @@ rt_status rt_illuminate(rt_ctx *c, const rt_camera *cam, const rt_outputs *trace
     a.list[1] = (int *)(ib + (size_t)n * 44);
     a.list[2] = (int *)(ib + (size_t)n * 48);
     a.ctr = (int *)(ib + (size_t)n * 52);
+    a.cont = 1.0f;
+    a.conv_code = 3;  // converged, awaiting the finish
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)c->n_cu * 8));
     hipStream_t s = (hipStream_t)stream;
     e = rti::launch_illum(a, c->dd, grid, s);

@@ -266,8 +266,15 @@ __device__ __forceinline__ void append(int *list, int *ctr, int pix, bool take) 
     if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = pix;
 }
 
-// Status codes of the API; 3 marks a converged pixel awaiting the finish.
-enum { ST_LIT = 1, ST_BLOCKED = 0, ST_AWAY = 2, ST_NONE = -1, ST_NOHIT = -3, ST_CONV = 3 };
+// Status codes of the API; 3 marks a converged pixel awaiting the finish,
+// 4 one converged at an intermediate target of the continuation.
+enum { ST_LIT = 1, ST_BLOCKED = 0, ST_AWAY = 2, ST_NONE = -1, ST_NOHIT = -3, ST_CONV = 3, ST_CONT = 4 };
+
+// The target of the shots of pixel P: the light, or during the
+// continuation the point q + cont (L - q) of the straight segment.
+template <class P> __device__ __forceinline__ V3<float> target(const rti::IllumArgs &A, const P &Px, V3<float> L) {
+    return A.cont < 1.f ? axpy(A.cont, L - Px.q, Px.q) : L;
+}
 
 // Initial state: pixels that hit start from the straight segment.
 template <int KIND>
@@ -302,7 +309,7 @@ __device__ __forceinline__ int judge(const rti::IllumArgs &A, int pix, int it, V
     const bool stalled = it >= 4 && fn > 0.5f * A.w_F[pix];
     A.w_F[pix] = fn;
     if (fn < A.tol) {
-        A.status[pix] = ST_CONV;
+        A.status[pix] = A.conv_code;
         return 0;
     }
     return stalled ? 0 : 1;
@@ -389,8 +396,9 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
             const V3<float> Xb = mk(__shfl(X.x, src2), __shfl(X.y, src2), __shfl(X.z, src2));
             const int oka = __shfl((int)ok, src), okb = __shfl((int)ok, src2);
             if (act && role == 0 && ok) {
-                const V3<float> F = X - L;
-                if (judge(A, pix, it, F) && oka && okb) again = newton<KIND>(A, P, pix, L, eps, al, be, T, F, X, Y, Xa, Xb);
+                const V3<float> Lp = target(A, P, L);
+                const V3<float> F = X - Lp;
+                if (judge(A, pix, it, F) && oka && okb) again = newton<KIND>(A, P, pix, Lp, eps, al, be, T, F, X, Y, Xa, Xb);
             }
             append(out, A.ctr + it + 1, pix, again);
         }
@@ -407,7 +415,7 @@ __global__ __launch_bounds__(256) void k_illum_iter(rti::IllumArgs A, const floa
             IAcc<KIND> acc{P.Bs, all, A.twist_amp, A.twist_theta0, nullptr, nullptr};
             V3<float> X, Y;
             if (shoot<KIND>(acc, A, P.q, P.dir(A, A.w_al[pix], A.w_be[pix]), A.w_T[pix], X, Y) &&
-                judge(A, pix, it, X - L)) {
+                judge(A, pix, it, X - target(A, P, L))) {
                 A.w_X[3 * pix] = X.x;
                 A.w_X[3 * pix + 1] = X.y;
                 A.w_X[3 * pix + 2] = X.z;
@@ -459,7 +467,8 @@ __global__ __launch_bounds__(256) void k_illum_step(rti::IllumArgs A, const floa
         if (act && role == 0 && ok && okb) {
             const V3<float> X = mk(A.w_X[3 * pix], A.w_X[3 * pix + 1], A.w_X[3 * pix + 2]);
             const V3<float> Y = mk(A.w_Y[3 * pix], A.w_Y[3 * pix + 1], A.w_Y[3 * pix + 2]);
-            again = newton<KIND>(A, P, pix, L, eps, al, be, T, X - L, X, Y, Xs, Xb);
+            const V3<float> Lp = target(A, P, L);
+            again = newton<KIND>(A, P, pix, Lp, eps, al, be, T, X - Lp, X, Y, Xs, Xb);
         }
         append(out, A.ctr + it + 1, pix, again);
     }
@@ -525,25 +534,131 @@ __global__ void k_illum_zero(int *ctr, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0;
 }
 
+// Retry seeds.  A hit pixel left without a geodesic (its Newton iteration
+// from the straight segment stalled, failed or ran out of iterations)
+// starts again from the converged direction of a neighbour: of the 8
+// neighbouring pixels of the same parameter set that have converged, the
+// one whose hit point is nearest, its direction written in this pixel's
+// frame (angles about the straight direction to the light) and its length.
+// Reads only converged pixels and writes only unconverged ones.
+template <int KIND, bool ONE>
+__global__ __launch_bounds__(256) void k_illum_seed(rti::IllumArgs A, const float4 *__restrict__ BF, int *ctr) {
+    const int HW = A.width * A.height;
+    const int n = A.n_sets * HW;
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int pix = base + threadIdx.x;
+        bool take = false;
+        if (pix < n && A.status[pix] == ST_NONE) {
+            const int set = pix / HW, r = pix - set * HW, j = r / A.width, i = r - j * A.width;
+            const V3<float> q = mk(A.hit[3 * pix], A.hit[3 * pix + 1], A.hit[3 * pix + 2]);
+            int best = -1;
+            float bestd = __builtin_huge_valf();
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = i + di, jj = j + dj;
+                    if ((di == 0 && dj == 0) || ii < 0 || jj < 0 || ii >= A.width || jj >= A.height) continue;
+                    const int nb = set * HW + jj * A.width + ii;
+                    if (A.status[nb] != ST_CONV) continue;
+                    const V3<float> d = mk(A.hit[3 * nb], A.hit[3 * nb + 1], A.hit[3 * nb + 2]) - q;
+                    const float d2 = dot(d, d);
+                    if (d2 < bestd) {
+                        bestd = d2;
+                        best = nb;
+                    }
+                }
+            if (best >= 0) {
+                const Pixel<KIND> P = pixel<KIND, ONE>(A, BF, pix), Q = pixel<KIND, ONE>(A, BF, best);
+                const V3<float> v = Q.dir(A, A.w_al[best], A.w_be[best]);
+                const float c = dot(v, P.F.e0);
+                if (c > 1e-2f * sqrt_(dot(v, v))) {
+                    const float ic = 1.f / c;
+                    A.w_al[pix] = dot(v, P.F.e1) * ic;
+                    A.w_be[pix] = dot(v, P.F.e2) * ic;
+                    A.w_T[pix] = A.w_T[best];
+                    A.w_F[pix] = __builtin_huge_valf();
+                    take = true;
+                }
+            }
+        }
+        append(A.list[0], ctr, pix, take);
+    }
+}
+
+// Continuation stage: targets move from q + lam0 (L - q) to q + lam1 (L - q).
+// lam0 = 0: every hit pixel still without a geodesic starts from the
+// straight segment to the first target; otherwise the pixels that converged
+// at lam0 (ST_CONT) start from that solution, the length scaled.
+template <int KIND, bool ONE>
+__global__ __launch_bounds__(256) void k_illum_cont(rti::IllumArgs A, const float4 *__restrict__ BF, int *ctr,
+                                                    float lam0, float lam1) {
+    const int n = A.n_sets * A.width * A.height;
+    const V3<float> L = mk(A.light[0], A.light[1], A.light[2]);
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int pix = base + threadIdx.x;
+        bool take = false;
+        if (pix < n) {
+            const int st = A.status[pix];
+            if (lam0 == 0.f && st == ST_NONE) {
+                const Pixel<KIND> P = pixel<KIND, ONE>(A, BF, pix);
+                A.w_al[pix] = 0.f;
+                A.w_be[pix] = 0.f;
+                A.w_T[pix] = lam1 * sqrtf(P.gdd(A, L - P.q));
+                take = true;
+            } else if (lam0 > 0.f && st == ST_CONT) {
+                A.w_T[pix] *= lam1 / lam0;
+                take = true;
+            }
+            if (take) {
+                A.status[pix] = ST_NONE;
+                A.w_F[pix] = __builtin_huge_valf();
+            }
+        }
+        append(A.list[0], ctr, pix, take);
+    }
+}
+
+template <int KIND, bool ONE>
+void illum_rounds(const rti::IllumArgs &a, const rti::DeviceData &d, int grid, hipStream_t s) {
+    for (int it = 0; it < a.max_iters; ++it) {
+        hipLaunchKernelGGL((k_illum_iter<KIND, ONE>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+        hipLaunchKernelGGL((k_illum_step<KIND, ONE>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
+    }
+    // retries from converged neighbours; each round has its own counters
+    rti::IllumArgs r = a;
+    r.max_iters = std::max(a.max_iters / 2, 1);
+    for (int round = 1; round <= rti::ILLUM_RETRY_ROUNDS; ++round) {
+        r.ctr = a.ctr + round * 2 * (a.max_iters + 1);
+        hipLaunchKernelGGL((k_illum_seed<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, r.ctr);
+        for (int it = 0; it < r.max_iters; ++it) {
+            hipLaunchKernelGGL((k_illum_iter<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, it);
+            hipLaunchKernelGGL((k_illum_step<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, it);
+        }
+    }
+    // continuation in the light position for the pixels still unsolved
+    for (int st = 0; st < rti::ILLUM_CONT_STAGES; ++st) {
+        const float lam0 = (float)st / rti::ILLUM_CONT_STAGES, lam1 = (float)(st + 1) / rti::ILLUM_CONT_STAGES;
+        r.ctr = a.ctr + (1 + rti::ILLUM_RETRY_ROUNDS + st) * 2 * (a.max_iters + 1);
+        r.cont = lam1;
+        r.conv_code = st + 1 < rti::ILLUM_CONT_STAGES ? ST_CONT : ST_CONV;
+        hipLaunchKernelGGL((k_illum_cont<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, r.ctr, lam0, lam1);
+        for (int it = 0; it < r.max_iters; ++it) {
+            hipLaunchKernelGGL((k_illum_iter<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, it);
+            hipLaunchKernelGGL((k_illum_step<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, it);
+        }
+    }
+    hipLaunchKernelGGL((k_illum_finish<KIND, ONE>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f,
+                       d.tor_f);
+}
+
 template <int KIND>
 hipError_t illum_kind(const rti::IllumArgs &a, const rti::DeviceData &d, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_illum_zero, dim3(1), dim3(256), 0, s, a.ctr, 2 * (a.max_iters + 1));
+    hipLaunchKernelGGL(k_illum_zero, dim3(1), dim3(256), 0, s, a.ctr,
+                       (1 + rti::ILLUM_RETRY_ROUNDS + rti::ILLUM_CONT_STAGES) * 2 * (a.max_iters + 1));
     hipLaunchKernelGGL((k_illum_init<KIND>), dim3(grid), dim3(256), 0, s, a, d.bump_f);
-    if (a.n_sets == 1) {
-        for (int it = 0; it < a.max_iters; ++it) {
-            hipLaunchKernelGGL((k_illum_iter<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
-            hipLaunchKernelGGL((k_illum_step<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
-        }
-        hipLaunchKernelGGL((k_illum_finish<KIND, true>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f,
-                           d.tor_f);
-    } else {
-        for (int it = 0; it < a.max_iters; ++it) {
-            hipLaunchKernelGGL((k_illum_iter<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
-            hipLaunchKernelGGL((k_illum_step<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
-        }
-        hipLaunchKernelGGL((k_illum_finish<KIND, false>), dim3(grid), dim3(256), 0, s, a, d.bump_f, d.sph_f, d.pln_f,
-                           d.tor_f);
-    }
+    if (a.n_sets == 1)
+        illum_rounds<KIND, true>(a, d, grid, s);
+    else
+        illum_rounds<KIND, false>(a, d, grid, s);
     return hipGetLastError();
 }
 

@@ -193,8 +193,20 @@ struct IllumArgs {
     float *w_al, *w_be, *w_T, *w_F;  // angles, length, last residual
     float *w_X, *w_Y;                // base shot's end point and velocity [3 per pixel]
     int *list[3];
-    int *ctr;  // 2 (max_iters + 1) words: list sizes, then step-list sizes
+    int *ctr;  // per round 2 (max_iters + 1) words: list sizes, then step-list sizes
+    // continuation rounds: the shots aim at q + cont (L - q) instead of L,
+    // and a pixel that converges there is marked conv_code
+    float cont;
+    int conv_code;
 };
+// Pixels left without a geodesic retry from a converged neighbour's
+// direction: ILLUM_RETRY_ROUNDS rounds (each seeded from everything converged
+// so far) of max(max_iters / 2, 1) Newton iterations.
+constexpr int ILLUM_RETRY_ROUNDS = 3;
+// Then the pixels still without one follow a continuation in the light
+// position: targets q + lambda (L - q) for the ILLUM_CONT_STAGES values
+// lambda = 1/S, 2/S, ..., 1, each stage started from the previous solution.
+constexpr int ILLUM_CONT_STAGES = 8;
 hipError_t launch_illum(const IllumArgs &a, const DeviceData &d, int grid, hipStream_t s);
 // ------------------------------------------------------------- MLP (BF16)
 enum Epi { EPI_NONE = 0, EPI_HIDDEN = 1, EPI_BIAS = 2, EPI_DSILU = 3 };

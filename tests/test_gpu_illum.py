@@ -95,17 +95,16 @@ def test_flat_space_closed_form(rt):
     assert n_bad <= max(2, 0.002 * hit.sum()), (n_bad, hit.sum())
 
 
-# found: the least fraction of hit pixels for which Newton's method from the
-# straight segment finds a geodesic.  The anisotropic bumps have the same
-# amplitudes as the isotropic ones but the smallest of three drawn spreads,
-# so steeper slopes that bend geodesics more and leave more pixels unsolved.
-# The quadric's slope grows linearly with the distance from the origin: on
-# the way to the light many geodesics bend far from the segment (about two
-# thirds are found).
-@pytest.mark.parametrize("name,w,h,found_min", [("bumps16_1080p", 64, 40, 0.95), ("twist_4k", 64, 40, 0.95),
-                                                ("deform16_1080p", 48, 30, 0.95), ("rdeform16_1080p", 48, 30, 0.95),
-                                                ("abumps16_1080p", 64, 40, 0.9),
-                                                ("quadric_1080p", 64, 40, 0.6)])
+# found: the least fraction of hit pixels for which a geodesic is found
+# (Newton from the straight segment, then retries from converged
+# neighbours, then the continuation in the light position).  The quadric's
+# slope grows linearly with the distance from the origin: on the way to the
+# light many geodesics bend far from the segment, and it keeps the most
+# pixels unsolved.
+@pytest.mark.parametrize("name,w,h,found_min", [("bumps16_1080p", 64, 40, 0.99), ("twist_4k", 64, 40, 0.99),
+                                                ("deform16_1080p", 48, 30, 0.99), ("rdeform16_1080p", 48, 30, 0.99),
+                                                ("abumps16_1080p", 64, 40, 0.99),
+                                                ("quadric_1080p", 64, 40, 0.9)])
 def test_curved_geodesics_reach_the_light(rt, name, w, h, found_min):
     """Curved metrics: the oracle integrates each returned geodesic in FP64
     and lands on the light; the Lambert term and the visibility recomputed
@@ -124,7 +123,7 @@ def test_illum_1080p_sampled(rt):
     wl = W.get("illum_1080p")
     assert tuple(wl["light"]["pos"]) == LIGHT["pos"] and wl["light"]["h"] == LIGHT["h"]
     tra, sh = _run(rt, wl, light=wl["light"])
-    _check_found(wl, tra, sh, 0.95, sample=400)
+    _check_found(wl, tra, sh, 0.99, sample=400)
 
 
 def _check_found(wl, tra, sh, found_min, sample=None):
