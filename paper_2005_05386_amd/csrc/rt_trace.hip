@@ -111,6 +111,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
         total_chunks = uniform_i(__shfl(pre, 63));
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) pass_ctr[rti::CTR_NCH] = total_chunks;
+    // no survivors (the late passes of a surrogate trace): nothing to pull,
+    // count or write
+    if (total_chunks == 0) return;
     const int *__restrict__ ids_in = A.ids[pass & 1];
     float *__restrict__ st = A.st;
     const int64_t cap = A.cap;
