@@ -31,6 +31,27 @@
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// XCD-aware tile order.  Workgroups go to the 8 XCDs round-robin by their
+// linear id, and each XCD has its own L2.  Tiles are numbered with the
+// column tile fastest, then the row tile, then the group (network), and
+// XCD k takes the k-th contiguous eighth of that order: the column tiles of
+// one row tile run one after another on the same XCD (the row slice of A
+// is fetched from memory once), and a network's weights are read by one
+// XCD only.  The grid is 1-D, 8 * ceil(tiles / 8) workgroups; returns false
+// for the padding.
+__device__ __forceinline__ bool xcd_tile(int nx, int ny, int nz, int &x, int &y, int &z) {
+    const int T = nx * ny * nz;
+    const int per = (T + 7) / 8;
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per + (b >> 3);
+    if ((b >> 3) >= per || t >= T) return false;
+    x = t % nx;
+    y = (t / nx) % ny;
+    z = t / (nx * ny);
+    return true;
+}
+inline unsigned xcd_grid(int nx, int ny, int nz) { return 8u * (unsigned)(((int64_t)nx * ny * nz + 7) / 8); }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
@@ -97,17 +118,18 @@ __device__ __forceinline__ void stage_store(__bf16 (*S)[40], int tid, const bf16
 }
 
 template <int LA, int LB>
-__global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G) {
+__global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G, int ntx, int nty, int ntz) {
     __shared__ __attribute__((aligned(16))) __bf16 As[64][32 + 8];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[64][32 + 8];  // transposed: Bs[n][k]
-    const int g = blockIdx.z;
+    int tx, ty, g;
+    if (!xcd_tile(ntx, nty, ntz, tx, ty, g)) return;
     int M = G.M;
     int64_t row0 = 0;
     if (G.rows) {
         M = G.rows[g];
         row0 = G.row_off[g];
     }
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int m0 = ty * 64, n0 = tx * 64;
     if (m0 >= M) return;
     const __bf16 *__restrict__ A = G.A + g * G.a_g + row0 * G.sam;
     const __bf16 *__restrict__ B = G.B + g * G.b_g;
@@ -335,11 +357,16 @@ typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 __global__ __launch_bounds__(256) void k_gemm_x3(const __bf16 *__restrict__ Hh, const __bf16 *__restrict__ Hl,
                                                  const float *__restrict__ params, int64_t offW, int64_t offB, int B,
                                                  float *__restrict__ Zout, __bf16 *__restrict__ Oh,
-                                                 __bf16 *__restrict__ Ol) {
-    __shared__ __attribute__((aligned(16))) __bf16 Ah[64][40], Al[64][40];
-    __shared__ __attribute__((aligned(16))) __bf16 Bh[64][40], Bl[64][40];  // [n][k]
-    const int g = blockIdx.z;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+                                                 __bf16 *__restrict__ Ol, int n_nets) {
+    // one LDS block: the four staging arrays, reused for the output tile
+    __shared__ __attribute__((aligned(16))) __bf16 stage[4][64][40];
+    __bf16(&Ah)[64][40] = stage[0];
+    __bf16(&Al)[64][40] = stage[1];
+    __bf16(&Bh)[64][40] = stage[2];  // [n][k]
+    __bf16(&Bl)[64][40] = stage[3];
+    int tx, ty, g;
+    if (!xcd_tile(rti::MLP_H / 64, (B + 63) / 64, n_nets, tx, ty, g)) return;
+    const int m0 = ty * 64, n0 = tx * 64;
     if (m0 >= B) return;
     const int64_t K = rti::MLP_H;
     const __bf16 *__restrict__ Xh = Hh + (int64_t)g * B * K;
@@ -400,24 +427,53 @@ __global__ __launch_bounds__(256) void k_gemm_x3(const __bf16 *__restrict__ Hh, 
             }
         __syncthreads();
     }
+    // epilogue through LDS (the staging buffers, free after the last
+    // barrier): the tile of z = acc + bias, then every thread writes 16
+    // consecutive values of one row as whole 16-byte stores of z and of the
+    // two bf16 parts of silu(z)
     const float *__restrict__ bias = params + (int64_t)g * rti::MLP_P + offB;
+    static_assert(sizeof(stage) >= 64 * 68 * sizeof(float), "output tile exceeds the staging block");
+    float(*Zs)[68] = reinterpret_cast<float(*)[68]>(&stage[0][0][0]);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int mm = m0 + wm + 16 * i + (lane >> 4) * 4 + e;
-                const int nn = n0 + wn + 16 * j + (lane & 15);
-                if (mm >= B) continue;
-                const int64_t o = ((int64_t)g * B + mm) * K + nn;
-                const float z = acc[i][j][e] + bias[nn];
-                Zout[o] = z;
-                const float h = silu(z);
-                const __bf16 hh = (__bf16)h;
-                Oh[o] = hh;
-                Ol[o] = (__bf16)(h - (float)hh);
+                const int rr = wm + 16 * i + (lane >> 4) * 4 + e, cc = wn + 16 * j + (lane & 15);
+                Zs[rr][cc] = acc[i][j][e] + bias[n0 + cc];
             }
+    __syncthreads();
+    {
+        const int rr = tid >> 2, c0 = (tid & 3) * 16;
+        const int mm = m0 + rr;
+        if (mm < B) {
+            const int64_t o = ((int64_t)g * B + mm) * K + n0 + c0;
+            float v[16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 t = *reinterpret_cast<const float4 *>(&Zs[rr][c0 + 4 * q]);
+                v[4 * q] = t.x;
+                v[4 * q + 1] = t.y;
+                v[4 * q + 2] = t.z;
+                v[4 * q + 3] = t.w;
+                *reinterpret_cast<float4 *>(Zout + o + 4 * q) = t;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                bf16x8v hi, lo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float h = silu(v[8 * q + e]);
+                    const __bf16 hh = (__bf16)h;
+                    hi[e] = hh;
+                    lo[e] = (__bf16)(h - (float)hh);
+                }
+                *reinterpret_cast<bf16x8v *>(Oh + o + 8 * q) = hi;
+                *reinterpret_cast<bf16x8v *>(Ol + o + 8 * q) = lo;
+            }
+        }
+    }
 }
 
 // out[g][n] = sum_m X[g][m][n], fixed order: per block of COLSUM_ROWS rows
@@ -486,7 +542,8 @@ __global__ void k_to_bf16(const float *__restrict__ x, __bf16 *__restrict__ y, i
 namespace rti {
 
 hipError_t launch_gemm(const GemmArgs &G, int groups, int max_rows, hipStream_t s) {
-    dim3 grid((G.N + 63) / 64, (max_rows + 63) / 64, groups);
+    const int ntx = (G.N + 63) / 64, nty = (max_rows + 63) / 64;
+    dim3 grid(xcd_grid(ntx, nty, groups));
     // vector staging when every 8-element run it loads lies inside the
     // operand and starts on a 16-byte boundary
     auto al = [](const void *p, int64_t a, int64_t b) {
@@ -498,13 +555,13 @@ hipError_t launch_gemm(const GemmArgs &G, int groups, int max_rows, hipStream_t 
     const bool b_nc = dims && G.sbn == 1 && al(G.B, G.b_g, G.sbk);
     const bool b_nc4 = dims && G.sbn == 1 && (uintptr_t)G.B % 4 == 0 && G.b_g % 2 == 0 && G.sbk % 8 == 0;
     if (a_mc && b_nc)
-        hipLaunchKernelGGL((k_gemm<L_MC, L_MC>), grid, dim3(256), 0, s, G);
+        hipLaunchKernelGGL((k_gemm<L_MC, L_MC>), grid, dim3(256), 0, s, G, ntx, nty, groups);
     else if (a_kc && b_nc)
-        hipLaunchKernelGGL((k_gemm<L_KC, L_MC>), grid, dim3(256), 0, s, G);
+        hipLaunchKernelGGL((k_gemm<L_KC, L_MC>), grid, dim3(256), 0, s, G, ntx, nty, groups);
     else if (a_kc && b_nc4)
-        hipLaunchKernelGGL((k_gemm<L_KC, L_MC4>), grid, dim3(256), 0, s, G);
+        hipLaunchKernelGGL((k_gemm<L_KC, L_MC4>), grid, dim3(256), 0, s, G, ntx, nty, groups);
     else
-        hipLaunchKernelGGL((k_gemm<L_GEN, L_GEN>), grid, dim3(256), 0, s, G);
+        hipLaunchKernelGGL((k_gemm<L_GEN, L_GEN>), grid, dim3(256), 0, s, G, ntx, nty, groups);
     return hipGetLastError();
 }
 
@@ -585,11 +642,11 @@ hipError_t mlp_forward(int n, int B, const __bf16 *wb, const float *params, cons
     (void)keep;
     hipLaunchKernelGGL(k_l1_fwd, dim3((B + 63) / 64, n), dim3(256), 0, s, params, x, B, w.z[0], w.h[0], w.hl[0],
                        w.xf);
-    const dim3 grid((unsigned)(MLP_H / 64), (unsigned)((B + 63) / 64), (unsigned)n);
+    const dim3 grid(xcd_grid(MLP_H / 64, (B + 63) / 64, n));
     hipLaunchKernelGGL(k_gemm_x3, grid, dim3(256), 0, s, w.h[0], w.hl[0], params, OFF_W2, OFF_B2, B, w.z[1], w.h[1],
-                       w.hl[1]);
+                       w.hl[1], n);
     hipLaunchKernelGGL(k_gemm_x3, grid, dim3(256), 0, s, w.h[1], w.hl[1], params, OFF_W3, OFF_B3, B, w.z[2], w.h[2],
-                       w.hl[2]);
+                       w.hl[2], n);
     hipLaunchKernelGGL(k_l4_fwd, dim3((B * 6 + 255) / 256, n), dim3(256), 0, s, params, w.z[2], B, y);
     return hipGetLastError();
 }
