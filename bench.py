@@ -445,6 +445,54 @@ def bench_euler(args, wl, torch, rt):
     print(json.dumps(line), flush=True)
 
 
+def bench_batch(args, wl, torch, rt):
+    """Batched multi-segment intersection (RT_FLAG_BATCH_SEGMENTS, the
+    batching of polygon segments Sec. 4.1 proposes) against the per-step
+    chord test, on the 1080p 16-bump frame and on the 4K twist scene (256
+    spheres).  Both traces must give the same outputs bit for bit; `value`
+    is the rays/s of the batched 1080p frame."""
+    import numpy as np
+
+    import workloads as W_
+    res = {}
+    for name, steps in (("bumps16_1080p", max(1, args.steps)), ("twist_4k", max(1, min(args.steps, 3)))):
+        w = W_.get(name)
+        cam, rule = w["camera"], dict(w["rule"])
+        tr = rt.Tracer(0)
+        tr.set_metric(w["metric"])
+        tr.set_scene(w["scene"])
+        n_rays = cam["width"] * cam["height"]
+        r = {}
+        outs = {}
+        for mode, flags in (("per_step", 0), ("batched", rt.FLAG_BATCH_SEGMENTS)):
+            rr = dict(rule, flags=flags)
+            out = tr.alloc_outputs(cam)
+            for _ in range(max(1, args.warmup)):
+                tr.trace_into(cam, rr, rr["max_steps"], out)
+            ms, st, agg = _timed_frames(tr, cam, rr, out, steps, torch)
+            outs[mode] = rt.to_numpy(out)
+            r[mode] = {"ms_per_frame": ms, "rays_per_s": n_rays / (ms / 1e3), "pass_ms": agg["pass_ms"],
+                       "refine_ms": agg["refine_ms"], "windows": st["batch_windows"],
+                       "windows_replayed": st["batch_replays"]}
+            print("[bench] %s %s: %.2f ms/frame %s" % (name, mode, ms, json.dumps(r[mode])), flush=True)
+        r["bitwise_equal"] = all(np.array_equal(outs["per_step"][k], outs["batched"][k])
+                                 for k in ("hit", "t", "id", "dir", "steps"))
+        r["batched_over_per_step"] = r["batched"]["ms_per_frame"] / r["per_step"]["ms_per_frame"]
+        res[name] = r
+    head = res["bumps16_1080p"]["batched"]
+    cam = wl["camera"]
+    line = {
+        "metric": "batched multi-segment intersection (Sec. 4.1) vs per-step test, rays/s of the batched frame",
+        "value": head["rays_per_s"], "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_frame"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "width": cam["width"], "height": cam["height"],
+                   "window_steps": wl["rule"]["cull_every"], "scenes": list(res)},
+        "scenes": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_illum(args, wl, torch, rt):
     """Direct Riemannian illumination of the traced 1080p frame by a point
     light: shooting for the geodesic from every hit to the light, visibility
@@ -517,6 +565,8 @@ def main():
         return bench_surrogate(args, wl, torch, rt)
     if args.workload == "euler_vs_rk4_1080p":
         return bench_euler(args, wl, torch, rt)
+    if args.workload == "batch_segments_1080p":
+        return bench_batch(args, wl, torch, rt)
     if "light" in wl:
         return bench_illum(args, wl, torch, rt)
     cam, rule = wl["camera"], dict(wl["rule"])

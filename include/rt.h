@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 5
+#define RT_ABI_VERSION 6
 
 typedef enum rt_status {
     RT_OK = 0,
@@ -240,6 +240,15 @@ typedef struct rt_step_rule {
  *   support spheres of eligible bumps (graph metric, RT_STEP_RK4, one
  *   parameter set; RT_EUNSUPPORTED otherwise, RT_ESTATE if none loaded). */
 #define RT_FLAG_SURROGATE 4
+/* RT_FLAG_BATCH_SEGMENTS: batched multi-segment intersection (the batching
+ *   of polygon segments Sec. 4.1 proposes).  Each wave marches a culling
+ *   window of cull_every steps with no scene test, each lane keeping the
+ *   bounding box of its polygon; the boxes are then tested against the
+ *   window's objects, and only the lanes whose box meets one march the window
+ *   again with the per-step chord tests.  Outputs equal the plain trace's bit
+ *   for bit.  RT_STEP_RK4 and RT_STEP_EULER; not with RT_FLAG_COUNT_WORK,
+ *   RT_FLAG_SURROGATE or a tape (RT_EUNSUPPORTED). */
+#define RT_FLAG_BATCH_SEGMENTS 8
 
 /* ----------------------------------------------------------------- outputs
  * Caller-owned device arrays, indexed [set][row][column] (pixel index
@@ -315,6 +324,8 @@ typedef struct rt_stats {
     uint64_t adj_steps;     /* rt_trace_bwd since the last trace: full RK4 steps reversed */
     uint64_t adj_bump_terms; /* rt_trace_bwd: bump terms inside their cut at those steps' stages */
     uint64_t adj_recomputed; /* rt_trace_bwd: full RK4 steps recomputed from the checkpoints */
+    uint64_t batch_windows; /* BATCH_SEGMENTS: culling windows marched (one per wave and window) */
+    uint64_t batch_replays; /* BATCH_SEGMENTS: windows marched again because a lane's box met an object */
 } rt_stats;
 
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);

@@ -793,8 +793,11 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     if (r->cull_every < 1 || r->cull_every > 256) return fail(c, RT_EINVAL, "rt_trace: cull_every must be in 1..256");
     if (r->pass_steps < 16) return fail(c, RT_EINVAL, "rt_trace: pass_steps must be >= 16");
     if (r->bisect_iters < 0 || r->bisect_iters > 60) return fail(c, RT_EINVAL, "rt_trace: bisect_iters must be in 0..60");
-    if (r->flags & ~(RT_FLAG_TIMING | RT_FLAG_COUNT_WORK | RT_FLAG_SURROGATE))
+    if (r->flags & ~(RT_FLAG_TIMING | RT_FLAG_COUNT_WORK | RT_FLAG_SURROGATE | RT_FLAG_BATCH_SEGMENTS))
         return fail(c, RT_EINVAL, "rt_trace: unknown flag bits");
+    const bool batch = (r->flags & RT_FLAG_BATCH_SEGMENTS) != 0;
+    if (batch && (r->kind == RT_STEP_RK45 || (r->flags & (RT_FLAG_COUNT_WORK | RT_FLAG_SURROGATE)) || tape))
+        return fail(c, RT_EUNSUPPORTED, "rt_trace: batched segments need RK4 or Euler, a plain trace and no tape");
     if (noalloc && (r->flags & (RT_FLAG_TIMING | RT_FLAG_SURROGATE)))
         return fail(c, RT_EUNSUPPORTED, "rt_trace_noalloc: RT_FLAG_TIMING and RT_FLAG_SURROGATE need allocations");
     if (max_steps < 1 || max_steps > 1000000) return fail(c, RT_EINVAL, "rt_trace: max_steps must be in 1..1000000");
@@ -879,6 +882,7 @@ static rt_status trace_impl(rt_ctx *c, const rt_camera *cam, const rt_step_rule 
     a.S = r->pass_steps;
     a.bisect_iters = r->bisect_iters;
     a.count = (r->flags & RT_FLAG_COUNT_WORK) ? 1 : 0;
+    a.batch = batch ? 1 : 0;
     // Culling window: before the next re-cull a lane moves at most K+1 steps
     // of Euclidean length <= h_max * vmax.  A g-unit velocity has Euclidean
     // speed <= 1 wherever g >= I: always for the graph metric
@@ -1543,6 +1547,8 @@ rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
     out->adj_steps = v[rti::ST_ADJ_STEPS];
     out->adj_bump_terms = v[rti::ST_ADJ_TERMS];
     out->adj_recomputed = v[rti::ST_ADJ_RECOMP];
+    out->batch_windows = v[rti::ST_BATCH_WIN];
+    out->batch_replays = v[rti::ST_BATCH_REPLAY];
     out->eligible = c->last_surr_flag ? c->surr_eligible : 0;
     if (c->last_timed) {
         // events: 0 before reset, 1 after reset, 2+p after pass p, 2+np after

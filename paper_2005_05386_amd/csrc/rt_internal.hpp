@@ -68,6 +68,8 @@ enum Stat {
     ST_ADJ_STEPS,  // adjoint: full RK4 steps reversed
     ST_ADJ_TERMS,  // adjoint: bump terms inside their cut at the reversed steps' stages
     ST_ADJ_RECOMP, // adjoint: full RK4 steps recomputed from the checkpoints
+    ST_BATCH_WIN,     // batched segments: windows marched
+    ST_BATCH_REPLAY,  // batched segments: windows marched again with per-step tests
     ST_N
 };
 
@@ -89,6 +91,7 @@ struct TraceArgs {
     float cull_base;    // composed deformations: window motion without displacement, (K+1) h_max 1.02 + 1e-4
     float cull_disp;    // composed deformations: bound on |Phi(x) - x| over all x
     int count;          // instrumented variant
+    int batch;          // batched multi-segment intersection
     // buffers
     float *st;             // ray state, Q_NFIELDS x cap
     int *ids[2];           // sorted survivor-id lists (pass p reads ids[p & 1])

@@ -72,6 +72,13 @@ __device__ __forceinline__ V3<float> initial_velocity(const TraceArgs &A, const 
     return rsqrt_(gdd) * d;
 }
 
+// Batched segments: each lane's state at the start of a culling window, in
+// LDS (read back only when the lane marches the window again).
+__device__ __forceinline__ float4 *batch_save() {
+    __shared__ float4 save[3 * 256];
+    return save;
+}
+
 // ================================================================ the pass
 // Occupancy: 7 waves per SIMD (at most 72 VGPRs) measured fastest for the
 // RK4 graph and twist kernels, 6 for DP5(4), although long-lived values
@@ -86,11 +93,26 @@ __device__ __forceinline__ V3<float> initial_velocity(const TraceArgs &A, const 
 #ifndef RT_PASS_WAVES
 #define RT_PASS_WAVES 7  // waves per SIMD the RK4 and Euler pass kernels are compiled for
 #endif
-template <int KIND, int STEP, bool COUNT, bool SURR = false, bool TAPE = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 ? 6 : RT_PASS_WAVES, 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
+#ifndef RT_BATCH_WAVES
+#define RT_BATCH_WAVES 6  // the same for the batched-segment variant
+#endif
+// BATCH: batched multi-segment intersection (Sec. 4.1 proposes testing many
+// segments of the polygon at once).  A culling window's K steps are first
+// marched with no scene test while each lane keeps the bounding box of its
+// polygon; the boxes, grown by a rounding margin, are then tested against
+// the window's object lists.  If no lane's box meets an object the K steps
+// stand; otherwise the lanes whose box does return to the window's start and
+// march it again with the per-step chord tests, while the other lanes wait.
+// A lane that ends by a miss or a failure while marching writes its output
+// only once its box is cleared.  Windows and object lists only bound the
+// work, so the outputs equal the plain kernel's bit for bit.
+template <int KIND, int STEP, bool COUNT, bool SURR = false, bool TAPE = false, bool BATCH = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 ? 6 : (BATCH ? RT_BATCH_WAVES : RT_PASS_WAVES), 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
                                                     const float *__restrict__ TOR) {
+    static_assert(!BATCH || (STEP != STEP_RK45 && !COUNT && !SURR && !TAPE),
+                  "batched segments: fixed-step integrators, plain trace");
     const int lane = lane_id();
     const int xcd0 = blockIdx.x % N_XCD;
     int *pass_ctr = A.ctr + rti::CTR_PASS0 + pass * rti::CTR_PASS_WORDS;
@@ -120,6 +142,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
 
     unsigned long long st_wave = 0, st_lane = 0, st_bl = 0, st_ol = 0, st_steps = 0, st_rays = 0;
     unsigned long long st_ev = 0, st_be = 0, st_ot = 0;  // COUNT only
+    unsigned long long st_bw = 0, st_br = 0;             // BATCH only: windows, replayed windows
 
     for (int xi = 0; xi < N_XCD; ++xi) {
         const int xp = (xcd0 + xi) & (N_XCD - 1);
@@ -190,14 +213,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
             V3<float> A0 = mk(0.f, 0.f, 0.f);
             bool need_a0 = true;
             unsigned c_eval = 0, c_bump = 0, c_obj = 0, lane_objs = 0;  // COUNT only
+            // BATCH only: the window's marching or replaying state (wave-uniform
+            // replay, wi, wlen), the lane's state at the window start, its
+            // polygon box, and whether it waits or has an output pending
+            bool replay = false, hold = false, inb = false;
+            int wi = 0, wlen = 0, fin = 0, it_m = 0;
+            V3<float> bmin = mk(0.f, 0.f, 0.f), bmax = bmin;
 
             for (;;) {
-                bool act = alive && (STEP == STEP_RK45 ? acc_pass < A.S : it < A.S) && !(SURR && parked);
+                bool act = alive && (STEP == STEP_RK45 ? acc_pass < A.S : (BATCH ? it_m : it) < A.S) && !(SURR && parked);
+                if constexpr (BATCH) act = alive && (replay ? (!hold && wi < wlen) : it_m < A.S);
                 uint64_t am = ballot(act);
-                if (am == 0) break;
+                if (am == 0) {
+                    if constexpr (BATCH) {
+                        // every replaying lane ended before the window did
+                        if (replay) {
+                            replay = false;
+                            hold = false;
+                            wi = 0;
+                            continue;
+                        }
+                    }
+                    break;
+                }
 
                 // ---- per-wave culling window
-                if (it % A.K == 0) {
+                if (BATCH ? (!replay && wi == 0) : it % A.K == 0) {
                     V3<float> p = xh + xl;
                     if (A.cull_margin < 0.f) {
                         bmask = n_bumps >= 64 ? ~0ull : ((1ull << n_bumps) - 1ull);
@@ -324,6 +365,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                             lane_objs += box_dist2(tp[0], tp[1], tp[2], llo, lhi) <= rr * rr ? 1u : 0u;
                         }
                     }
+                    if constexpr (BATCH) {
+                        inb = act;
+                        if (act) {
+                            float4 *sv = batch_save();
+                            sv[threadIdx.x] = make_float4(xh.x, xh.y, xh.z, xl.x);
+                            sv[256 + threadIdx.x] = make_float4(xl.y, xl.z, y.x, y.y);
+                            sv[512 + threadIdx.x] = make_float4(y.z, __int_as_float(steps), __int_as_float(acc_pass), 0.f);
+                            bmin = bmax = p;
+                        }
+                        st_bw++;
+                    }
                 }
                 // wave statistics (work counting only; the lane count is also DP5's attempt count)
                 if (COUNT || STEP == STEP_RK45) st_lane += __popcll(am);
@@ -407,7 +459,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                         if (COUNT) c_obj += lane_objs;
                         // ---- segment versus scene, chord [x, x + dx] (a scalar branch:
                         // most wave iterations list no object)
-                        if ((sm[0] | sm[1] | sm[2] | sm[3] | omask) != 0) {
+                        if ((!BATCH || replay) && (sm[0] | sm[1] | sm[2] | sm[3] | omask) != 0) {
                             const float DD = dot(dx, dx);
 #pragma unroll
                             for (int w = 0; w < 4; ++w) {
@@ -511,9 +563,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                             float t = (STEP == STEP_RK45) ? th + tl : (float)steps * A.h + (SURR ? th + tl : 0.f);
                             float t_end = (STEP == STEP_RK45) ? A.t_max * (1.0f - 1e-6f) : A.t_max;
                             done_miss = steps >= A.max_steps || t >= t_end || clipped;
+                            if constexpr (BATCH) {
+                                if (!replay) {
+                                    const V3<float> q = xh + xl;
+                                    bmin = mk(fminf(bmin.x, q.x), fminf(bmin.y, q.y), fminf(bmin.z, q.z));
+                                    bmax = mk(fmaxf(bmax.x, q.x), fmaxf(bmax.y, q.y), fmaxf(bmax.z, q.z));
+                                }
+                            }
                         }
                     }
-                    if (done_fail || done_miss) {
+                    if (BATCH && !replay && (done_fail || done_miss)) {
+                        // the output waits until the window's box test clears this lane
+                        fin = done_fail ? 2 : 1;
+                    } else if (done_fail || done_miss) {
                         write_out(A, qbase + pix, xh + xl,
                                   STEP == STEP_RK45 ? th + tl : (float)steps * A.h + (SURR ? th + tl : 0.f), y,
                                   done_fail ? -2 : -1, steps);
@@ -563,6 +625,81 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                             const int rank = atomicAdd(A.xctl + net, 1);
                             A.xq[base + mbcnt64(pm)] = make_int4(id, park_b, rank, 0);
                         }
+                    }
+                }
+                if constexpr (BATCH) {
+                    wi++;
+                    if (!replay) it_m++;
+                    if (replay) {
+                        if (wi >= wlen) {
+                            replay = false;
+                            hold = false;
+                            wi = 0;
+                        }
+                    } else if (wi == A.K || ballot(alive && it_m < A.S) == 0) {
+                        // ---- end of the march: the lanes' polygon boxes against
+                        // the window's objects
+                        bool cand = false;
+                        if (inb) {
+                            // margin: FP32 rounding of the positions and of the
+                            // chord tests, far below it
+                            const float eps = 1e-3f + 1e-5f * fmaxf(fmaxf(fabsf(bmin.x), fabsf(bmax.x)),
+                                                                   fmaxf(fmaxf(fabsf(bmin.y), fabsf(bmax.y)),
+                                                                         fmaxf(fabsf(bmin.z), fabsf(bmax.z))));
+                            const float lo[3] = {bmin.x - eps, bmin.y - eps, bmin.z - eps};
+                            const float hi[3] = {bmax.x + eps, bmax.y + eps, bmax.z + eps};
+#pragma unroll
+                            for (int w = 0; w < 4; ++w) {
+                                uint64_t m = sm[w];
+                                while (m) {
+                                    const int b = __builtin_ctzll(m);
+                                    m &= m - 1;
+                                    const float4 sp = SPH[64 * w + b];
+                                    cand |= box_dist2(sp.x, sp.y, sp.z, lo, hi) <= sp.w * sp.w;
+                                }
+                            }
+                            uint64_t m = omask;
+                            while (m) {
+                                const int b = __builtin_ctzll(m);
+                                m &= m - 1;
+                                if (b < 8) {
+                                    const float4 pl = PLN[b];
+                                    const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]),
+                                                cz = 0.5f * (lo[2] + hi[2]);
+                                    const float ex = 0.5f * (hi[0] - lo[0]), ey = 0.5f * (hi[1] - lo[1]),
+                                                ez = 0.5f * (hi[2] - lo[2]);
+                                    const float c = pl.x * cx + pl.y * cy + pl.z * cz - pl.w;
+                                    cand |= fabsf(c) <= fabsf(pl.x) * ex + fabsf(pl.y) * ey + fabsf(pl.z) * ez;
+                                } else {
+                                    const float *tp = TOR + 8 * (b - 8);
+                                    const float rr = tp[6] + tp[7];
+                                    cand |= box_dist2(tp[0], tp[1], tp[2], lo, hi) <= rr * rr;
+                                }
+                            }
+                        }
+                        if (fin && !cand) {
+                            write_out(A, qbase + pix, xh + xl, (float)steps * A.h, y, fin == 2 ? -2 : -1, steps);
+                            fin = 0;
+                        }
+                        if (ballot(cand)) {
+                            if (cand) {
+                                const float4 *sv = batch_save();
+                                const float4 a = sv[threadIdx.x], b = sv[256 + threadIdx.x], c = sv[512 + threadIdx.x];
+                                xh = mk(a.x, a.y, a.z);
+                                xl = mk(a.w, b.x, b.y);
+                                y = mk(b.z, b.w, c.x);
+                                steps = __float_as_int(c.y);
+                                acc_pass = __float_as_int(c.z);
+                                alive = true;
+                                fin = 0;
+                            }
+                            hold = !cand;
+                            replay = true;
+                            wlen = wi;
+                            st_br++;
+                        }
+                        wi = 0;
+                        inb = false;
                     }
                 }
                 it++;
@@ -615,6 +752,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
         }
     }
     if (lane == 0) {
+        if (BATCH) {
+            atomicAdd(A.stats + rti::ST_BATCH_WIN, st_bw);
+            atomicAdd(A.stats + rti::ST_BATCH_REPLAY, st_br);
+        }
         if (st_rays) atomicAdd(A.stats + rti::ST_RAYS, st_rays);
         atomicAdd(A.stats + rti::ST_STEPS, st_steps);
         atomicAdd(A.stats + rti::ST_ATTEMPTS, STEP == STEP_RK45 ? st_lane : st_steps);
@@ -852,6 +993,13 @@ __global__ void k_reset(int *ctr, int n_words, unsigned long long *stats) {
 
 template <int KIND, int STEP, bool SURR, bool TAPE = false>
 hipError_t launch_pass(const TraceArgs &a, const rti::DeviceData &d, int p, int grid, hipStream_t s) {
+    if constexpr (STEP != STEP_RK45 && !SURR && !TAPE) {
+        if (a.batch) {
+            hipLaunchKernelGGL((k_trace_pass<KIND, STEP, false, false, false, true>), dim3(grid), dim3(256), 0, s, a,
+                               p, d.bump_f, d.sph_f, d.pln_f, d.tor_f);
+            return hipGetLastError();
+        }
+    }
     if (a.count)
         hipLaunchKernelGGL((k_trace_pass<KIND, STEP, true, SURR, TAPE>), dim3(grid), dim3(256), 0, s, a, p,
                            d.bump_f, d.sph_f, d.pln_f, d.tor_f);

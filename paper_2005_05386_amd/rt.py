@@ -23,7 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EUNSUPPORTED, RT_ESTATE = 0, -1, -2, -3, -4, -5
 EUCLID, GRAPH_GAUSS, PULLBACK_TWIST, PULLBACK_ZTWIST, PULLBACK_DEFORM, GRAPH_ANISO, GRAPH_QUADRIC = 0, 1, 2, 3, 4, 5, 6
 RK4, RK45, EULER = 0, 1, 2
-FLAG_TIMING, FLAG_COUNT_WORK, FLAG_SURROGATE = 1, 2, 4
+FLAG_TIMING, FLAG_COUNT_WORK, FLAG_SURROGATE, FLAG_BATCH_SEGMENTS = 1, 2, 4, 8
 
 EXPORTS = ["rt_abi_version", "rt_create", "rt_destroy", "rt_last_error", "rt_set_metric", "rt_set_scene",
            "rt_trace", "rt_sync", "rt_get_stats", "rt_tape_bytes", "rt_trace_fwd_ckpt", "rt_loss_l2",
@@ -89,7 +89,8 @@ class rt_stats(C.Structure):
                 ("refine_ms", C.c_float), ("compact_ms", C.c_float), ("total_ms", C.c_float),
                 ("crossings", C.c_uint64), ("accepted", C.c_uint64), ("surr_ms", C.c_float),
                 ("eligible", C.c_int), ("adj_steps", C.c_uint64), ("adj_bump_terms", C.c_uint64),
-                ("adj_recomputed", C.c_uint64)]
+                ("adj_recomputed", C.c_uint64),
+                ("batch_windows", C.c_uint64), ("batch_replays", C.c_uint64)]
 
 
 _P = C.c_void_p

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(rt.lib(), n), n
     assert sorted(rt.EXPORTS) == names
-    assert rt.abi_version() == 5
+    assert rt.abi_version() == 6
 
 
 def test_host_only_context_validates():
@@ -86,6 +86,31 @@ def test_noalloc_trace_validates():
         with pytest.raises(rt.RtError) as e:
             tr.trace_raw(c_, r_, ms, (16, 16, 16, 16, 0), 0, noalloc=True)
         assert e.value.status == want
+
+
+def test_batched_segments_validate():
+    """RT_FLAG_BATCH_SEGMENTS serves fixed-step plain traces: DP5(4), work
+    counting and the surrogate are refused before the device is touched; a
+    valid request gets as far as the host-only context check."""
+    rt = _rt()
+    tr = rt.Tracer(-1)
+    wl = W.get("bumps16_1080p")
+    tr.set_metric(wl["metric"])
+    tr.set_scene(wl["scene"])
+    cam, rule = wl["camera"], wl["rule"]
+    B = rt.FLAG_BATCH_SEGMENTS
+    rk45 = W.get("bumps16_1080p_rk45")["rule"]
+    for r_ in (dict(rk45, flags=B), dict(rule, flags=B | rt.FLAG_COUNT_WORK), dict(rule, flags=B | rt.FLAG_SURROGATE)):
+        with pytest.raises(rt.RtError) as e:
+            tr.trace_raw(cam, r_, 10, (16, 16, 16, 16, 0), 0)
+        assert e.value.status == rt.RT_EUNSUPPORTED
+    for r_ in (dict(rule, flags=B), dict(rule, kind=rt.EULER, flags=B | rt.FLAG_TIMING)):
+        with pytest.raises(rt.RtError) as e:
+            tr.trace_raw(cam, r_, 10, (16, 16, 16, 16, 0), 0)
+        assert e.value.status == rt.RT_ESTATE
+    with pytest.raises(rt.RtError) as e:
+        tr.trace_raw(cam, dict(rule, flags=16), 10, (16, 16, 16, 16, 0), 0)
+    assert e.value.status == rt.RT_EINVAL
 
 
 def test_metric_and_scene_validation():
@@ -206,7 +231,7 @@ def test_surrogate_and_mlp_entry_points_validate():
         tr.trace_raw(cam, dict(rule, kind=W.RK45, flags=rt.FLAG_SURROGATE), 10, (16, 16, 16, 16, 0), 0)
     assert e.value.status == rt.RT_EUNSUPPORTED
     with pytest.raises(rt.RtError) as e:
-        tr.trace_raw(cam, dict(rule, flags=8), 10, (16, 16, 16, 16, 0), 0)
+        tr.trace_raw(cam, dict(rule, flags=16), 10, (16, 16, 16, 16, 0), 0)
     assert e.value.status == rt.RT_EINVAL
     P = C.c_void_p(16)
     one = np.ones(4, np.float32)

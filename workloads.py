@@ -344,6 +344,9 @@ WORKLOADS = {
     "bumps16_1080p_rk45": lambda **kw: bumps16_1080p(kind=RK45, **kw),
     "bumps16_1080p_euler": lambda **kw: bumps16_1080p(kind=EULER, **kw),
     "euler_vs_rk4_1080p": lambda **kw: bumps16_1080p(kind=EULER, **kw),
+    # batched multi-segment intersection against the per-step test, on the
+    # 1080p frame (and on the 4K twist scene of 256 spheres)
+    "batch_segments_1080p": lambda **kw: bumps16_1080p(**kw),
     "twist_4k": twist_4k,
     "deform16_1080p": deform16_1080p,
     "rdeform16_1080p": rdeform16_1080p,
