@@ -72,7 +72,19 @@ FLOPS = {
     # per step recomputed from a checkpoint: one RK4 step with its 4 evaluations
     # (106 + 4 x 16) plus 27 per bump term inside its cut
     "adj_recomp_step": 170,
+    # crossing generator (training data): one RK4 step in the canonical frame
+    # with its single bump always inside the cut, 4 x (16 + 27) + 106
+    "cross_step": 278,
+    # FP64 hit refinement (graph metric): per evaluation and per bump inside
+    # its cut as in FP32 (the exponential counted once, although FP64 exp is
+    # a software routine); per RK4 step 80 (stage states 36, stage sums 30,
+    # scaling 8, x + dx and y + dv 6); per implicit-function value 9
+    "ref_eval": 16,
+    "ref_bump": 27,
+    "ref_rk4_step": 80,
+    "ref_obj": 9,
 }
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector, published
 
 
 KERNEL_SOURCES = ["paper_2005_05386_amd/csrc/rt_trace.hip", "paper_2005_05386_amd/csrc/rt_device.hpp",
@@ -285,6 +297,40 @@ def _timed_frames(tr, cam, rule, out, steps, torch):
     return ev0.elapsed_time(ev1) / steps, st, agg
 
 
+def cross_gen_roofline(tr, kappa, torch, h=0.01, n_per=16384, reps=3):
+    """The training-data kernel alone (k_cross_gen): `reps` launches of
+    n_per crossings per shape (16 training steps' worth) with the training
+    loop's stratified draws, timed with stream events; its RK4 steps follow
+    from the arc lengths it returns (steps of h to the exit, then 30
+    bisection steps and the final partial step)."""
+    import numpy as np
+    ones = np.ones(len(kappa), np.float32)
+    tr.surrogate_gen(kappa, ones, n_per, h, mode=4, seed=11)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for r in range(reps):
+        _, _, aux = tr.surrogate_gen(kappa, ones, n_per, h, mode=4, seed=12 + r)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    arc = aux[:, :, 1].double().cpu().numpy()
+    kmax = float(np.abs(np.asarray(kappa, np.float64)).max())
+    max_steps = int((20.0 + 10.0 * kmax) / h) + 16
+    exited = arc >= 0
+    lane = np.where(exited, np.floor(arc / h + 1e-6) + 31, max_steps)
+    total = float(lane.sum())
+    waves = lane.reshape(len(kappa), -1, 64)
+    flops = FLOPS["cross_step"] * total
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "kernel": "k_cross_gen", "ms_per_launch": ms,
+            "crossings_per_launch": int(lane.size), "rk4_steps_per_launch": total,
+            "flops_per_launch": flops, "lane_efficiency": total / float(64 * waves.max(axis=2).sum())}
+
+
 def bench_surrogate(args, wl, torch, rt):
     """Learned crossings against plain RK4 on the same frame: train one
     network per bump shape, time the RK4-only frame (the reference) and the
@@ -311,6 +357,8 @@ def bench_surrogate(args, wl, torch, rt):
     fwd_flops = 2 * (6 * 256 + 2 * 256 * 256 + 256 * 6)
     train_tflops = 3 * fwd_flops * model.samples * len(kappa) / model.train_s / 1e12
     S.load(tr, model, net, tol=args.surr_tol)
+    gen = cross_gen_roofline(tr, kappa, torch)
+    print("[bench] crossing generator: %s" % json.dumps(gen), flush=True)
 
     for _ in range(args.warmup):
         tr.trace_into(cam, rule, rule["max_steps"], out)
@@ -368,6 +416,7 @@ def bench_surrogate(args, wl, torch, rt):
                 "bf16_peak_tflops": 2500.0, "training_s": model.train_s, "training_steps": model.steps,
                 "training_samples_per_shape": model.samples, "training_mlp_tflops": train_tflops,
                 "final_loss": model.losses[-1][1] if model.losses else None},
+        "cross_gen_roofline": gen,
     }
     print(json.dumps(line), flush=True)
 
@@ -614,6 +663,19 @@ def main():
     flops = algorithmic_flops(wl["metric"]["kind"], rule["kind"], work, rotating)
     pass_s = pass_ms / 1e3 / args.steps
     achieved = flops / pass_s / 1e12
+    # FP64 refinement (graph metric, RK4): counted evaluations, bump terms and
+    # steps of the instrumented trace, priced by the FP64 model, over the
+    # refine kernel's HIP-event time
+    refine_roof = None
+    if wl["metric"]["kind"] == 1 and rule["kind"] == 0 and work["refine_evals"] > 0:
+        rf = (FLOPS["ref_eval"] * work["refine_evals"] + FLOPS["ref_bump"] * work["refine_bump_terms"] +
+              (FLOPS["ref_rk4_step"] + FLOPS["ref_obj"]) * work["refine_steps"] + FLOPS["ref_obj"] * work["refined"])
+        r_ms = refine_ms / args.steps
+        r_ach = rf / (r_ms * 1e-3) / 1e12
+        refine_roof = {"bound": "alu", "achieved": r_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s (FP64)",
+                       "frac": r_ach / FP64_PEAK_TFLOPS, "kernel": "k_refine", "flops_per_launch": rf,
+                       "kernel_ms_per_launch": r_ms, "records": work["refined"], "evals": work["refine_evals"],
+                       "bump_terms": work["refine_bump_terms"], "steps": work["refine_steps"]}
     line = {
         "metric": "rays/s & RK4 ray-steps/s (1080p, 16 bumps); surrogate vs RK4 at equal error",
         "value": n_rays / (ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
@@ -633,6 +695,7 @@ def main():
                      },
         "kernel_ms": {"passes": pass_ms / args.steps, "refine": refine_ms / args.steps,
                       "compaction": compact_ms / args.steps},
+        "refine_roofline": refine_roof,
         "work": {"ray_steps": work["ray_steps"], "acc_evals": work["acc_evals"],
                  "bump_evals": work["bump_evals"], "obj_tests": work["obj_tests"],
                  "mean_active_bumps_per_eval": work["bump_evals"] / max(1, work["acc_evals"]),

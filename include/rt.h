@@ -326,6 +326,9 @@ typedef struct rt_stats {
     uint64_t adj_recomputed; /* rt_trace_bwd: full RK4 steps recomputed from the checkpoints */
     uint64_t batch_windows; /* BATCH_SEGMENTS: culling windows marched (one per wave and window) */
     uint64_t batch_replays; /* BATCH_SEGMENTS: windows marched again because a lane's box met an object */
+    uint64_t refine_evals;      /* COUNT_WORK: FP64 acceleration evaluations of the hit refinement */
+    uint64_t refine_bump_terms; /* COUNT_WORK: bumps inside their cut at those evaluations (graph metric) */
+    uint64_t refine_steps;      /* COUNT_WORK: FP64 integrator steps of the refinement (full and partial) */
 } rt_stats;
 
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
@@ -483,7 +486,9 @@ rt_status rt_adamw_step(rt_ctx *ctx, float *params, uint16_t *w_bf16, float *m, 
  * mode 0: sin^2 th uniform in [0, 1) from a counter-based generator of
  * (seed, shape, sample), i.e. entry points uniform over the disc of impact
  * parameters; mode 1: cos th = i / (n_per_shape - 1); mode 2: sin th
- * uniform in [0, 1) (impact parameters uniform).  kappa and scale
+ * uniform in [0, 1) (impact parameters uniform); mode 4 or 6: as 0 or 2
+ * with stratified draws, sample i in stratum i of n_per_shape equal strata
+ * of the uniform variable (the training loop's draws).  kappa and scale
  * are host arrays [n_shapes]; outputs are device arrays:
  *   x   [n_shapes][n_per_shape][6]  network input (1, 0, 0, -cos th, sin th, 0)
  *   y   [n_shapes][n_per_shape][6]  target: (exit point / 3 - (-cos 2th, sin 2th, 0),
@@ -499,7 +504,10 @@ rt_status rt_surrogate_gen(rt_ctx *ctx, int n_shapes, const float *kappa, const 
  * rt_adamw_step, n_steps times, enqueued from the host without
  * synchronising).  Every step uses batch fresh crossings per shape (mode 0
  * or 2 of rt_surrogate_gen, step h), drawn 16 steps at a time with seed
- * seed + 1000003 (c + 1) for the c-th group of 16 steps; step s (1-based) uses the
+ * seed + 1000003 (c + 1) for the c-th group of 16 steps, stratified: the
+ * 16 batch draws of a group split [0, 1) into 16 batch equal strata of the
+ * uniform variable, one draw in each, and step j of the group takes the
+ * strata congruent to j modulo 16; step s (1-based) uses the
  * learning rate lr s / warmup for s <= warmup, then a cosine decay from lr
  * to lr_min.  kappa, scale: host [n_nets].  params (FP32 master), w_bf16,
  * adam_m, adam_v: device [n_nets][RT_MLP_PARAMS], updated in place.

@@ -1305,8 +1305,8 @@ rt_status rt_surrogate_gen(rt_ctx *c, int n_shapes, const float *kappa, const fl
     if (n_shapes < 1 || n_shapes > 4096 || n_per < 1 || (int64_t)n_shapes * n_per > (1LL << 31) - 1)
         return fail(c, RT_EINVAL, "rt_surrogate_gen: bad sizes");
     if (!kappa || !scale || !x || !y || !aux) return fail(c, RT_EINVAL, "rt_surrogate_gen: NULL argument");
-    if (!(h >= 1e-3f && h <= 0.5f) || mode < 0 || mode > 2)
-        return fail(c, RT_EINVAL, "rt_surrogate_gen: need 1e-3 <= h <= 0.5 and mode in {0, 1, 2}");
+    if (!(h >= 1e-3f && h <= 0.5f) || !(mode == 0 || mode == 1 || mode == 2 || mode == 4 || mode == 6))
+        return fail(c, RT_EINVAL, "rt_surrogate_gen: need 1e-3 <= h <= 0.5 and mode in {0, 1, 2, 4, 6}");
     for (int i = 0; i < n_shapes; ++i)
         if (!finite(kappa[i]) || std::fabs(kappa[i]) > 100.f || !(scale[i] > 0.f) || !finite(scale[i]))
             return fail(c, RT_EINVAL, "rt_surrogate_gen: bad kappa or scale");
@@ -1549,6 +1549,9 @@ rt_status rt_get_stats(rt_ctx *c, rt_stats *out) {
     out->adj_recomputed = v[rti::ST_ADJ_RECOMP];
     out->batch_windows = v[rti::ST_BATCH_WIN];
     out->batch_replays = v[rti::ST_BATCH_REPLAY];
+    out->refine_evals = v[rti::ST_REF_EVALS];
+    out->refine_bump_terms = v[rti::ST_REF_BUMPS];
+    out->refine_steps = v[rti::ST_REF_STEPS];
     out->eligible = c->last_surr_flag ? c->surr_eligible : 0;
     if (c->last_timed) {
         // events: 0 before reset, 1 after reset, 2+p after pass p, 2+np after

@@ -269,8 +269,9 @@ template <class T> __device__ __forceinline__ V3<T> graph_quad_accel(V3<T> q, V3
 }
 
 // Double precision version over a (per-lane) mask, same regrouping.
+// n_in (optional): adds the number of bumps inside their cut at p.
 __device__ __forceinline__ V3<double> graph_accel_f64(const double *__restrict__ B, uint64_t mask, V3<double> p,
-                                                      V3<double> y) {
+                                                      V3<double> y, unsigned *n_in = nullptr) {
     double gx = 0, gy = 0, gz = 0, q = 0;
     double yy = dot(y, y);
     while (mask) {
@@ -281,6 +282,7 @@ __device__ __forceinline__ V3<double> graph_accel_f64(const double *__restrict__
         double dx = p.x - pb[1], dy = p.y - pb[2], dz = p.z - pb[3];
         double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 > pb[5]) continue;
+        if (n_in) ++*n_in;
         double w = pb[7] * exp(-0.5 * r2 * s);
         gx -= w * dx;
         gy -= w * dy;

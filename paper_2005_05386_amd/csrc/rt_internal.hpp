@@ -70,6 +70,9 @@ enum Stat {
     ST_ADJ_RECOMP, // adjoint: full RK4 steps recomputed from the checkpoints
     ST_BATCH_WIN,     // batched segments: windows marched
     ST_BATCH_REPLAY,  // batched segments: windows marched again with per-step tests
+    ST_REF_EVALS,     // COUNT: FP64 refinement acceleration evaluations
+    ST_REF_BUMPS,     // COUNT: bumps inside their cut at those evaluations
+    ST_REF_STEPS,     // COUNT: FP64 refinement integrator steps
     ST_N
 };
 

@@ -64,6 +64,9 @@ __global__ __launch_bounds__(256) void k_cross_gen(const float *__restrict__ kap
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_per) return;
     const float k = fabsf(kappa[sh]);
+    // stratified draws: the training loop's (step_batch > 0), or on request
+    const bool strat = step_batch > 0 || (mode & 4) != 0;
+    mode &= 3;
     // one bump at the origin with sigma = 1, no cut: (cx, cy, cz, -log2(e)/2), (kappa, 1, cut^2, 1)
     __shared__ float4 bump[2];
     if (threadIdx.x == 0) {
@@ -77,7 +80,12 @@ __global__ __launch_bounds__(256) void k_cross_gen(const float *__restrict__ kap
         st = sqrtf(fmaxf(0.f, 1.f - ct * ct));
     } else {
         const uint64_t r = splitmix64(seed ^ splitmix64(((uint64_t)sh << 40) ^ (uint64_t)i));
-        const float u = (float)((r >> 11) * (1.0 / 9007199254740992.0));
+        float u = (float)((r >> 11) * (1.0 / 9007199254740992.0));
+        // training draws are stratified: sample i lies in stratum i of n_per,
+        // so the lanes of a wave take neighbouring strata (chords of nearly
+        // equal length, little divergence) and each step's batch takes every
+        // (n_per / step_batch)-th stratum (see the output index below)
+        if (strat) u = (float)(((double)i + (double)u) / (double)n_per);
         // mode 0: sin^2 th uniform (area-uniform impact parameters); mode 2: sin th uniform
         const float s2 = mode == 2 ? u * u : u;
         st = sqrtf(s2);
@@ -128,8 +136,10 @@ __global__ __launch_bounds__(256) void k_cross_gen(const float *__restrict__ kap
     const V3<float> uo = (1.0f / 3.0f) * ue;
     const V3<float> vo = rsqrt_(dot(ye, ye)) * ye;
     const float inv = 1.0f / scale[sh];
-    // layout [shape][sample], or step-major [i / step_batch][shape][i % step_batch]
-    const int64_t o = step_batch > 0 ? ((int64_t)(i / step_batch) * gridDim.y + sh) * step_batch + i % step_batch
+    // layout [shape][sample], or step-major [step][shape][position] with
+    // step i % (n_per / step_batch) and position i / (n_per / step_batch)
+    const int nst = step_batch > 0 ? n_per / step_batch : 1;
+    const int64_t o = step_batch > 0 ? ((int64_t)(i % nst) * gridDim.y + sh) * step_batch + i / nst
                                      : (int64_t)sh * n_per + i;
     float *x = X + 6 * o, *yv = Y + 6 * o, *aux = AUX + 4 * o;
     x[0] = 1.f;

@@ -787,12 +787,15 @@ __device__ __forceinline__ double obj_F64(int id, V3<double> x, int ns, int np, 
     return torus_sdf<double>(TOD + 8 * (id - np), x);
 }
 
-template <int KIND, int STEP>
+// COUNT: also counts the acceleration evaluations, the bumps inside their
+// cut at them (graph metric) and the integrator steps (work statistics).
+template <int KIND, int STEP, bool COUNT = false>
 __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__restrict__ BD,
                                                 const double *__restrict__ SPD, const double *__restrict__ PLD,
                                                 const double *__restrict__ TOD) {
     const int n = A.ctr[rti::CTR_REFINE];
     const int HW = A.width * A.height;
+    unsigned c_eval = 0, c_bump = 0, c_step = 0;  // COUNT only
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         float4 r0, r1, r2, r3, r4;
         double tk_hi, tk_lo, h, sc;
@@ -821,8 +824,9 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
         const double *Bs = BD + (int64_t)set * A.n_bumps * (is_deform(KIND) ? DEFORM_D : 8);
         double amp = A.twist_amp, th0 = A.twist_theta0;
         auto acc = [&](V3<double> p, V3<double> v, V3<double> &a) -> bool {
+            if constexpr (COUNT) c_eval++;
             if constexpr (KIND == KIND_GRAPH) {
-                a = graph_accel_f64(Bs, mask, p, v);
+                a = graph_accel_f64(Bs, mask, p, v, COUNT ? &c_bump : nullptr);
                 return true;
             } else if constexpr (KIND == KIND_TWIST) {
                 return twist_accel<double>(amp, th0, p, v, a);
@@ -847,6 +851,7 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
         V3<double> a0;
         acc(x, y, a0);
         auto step = [&](double hs, V3<double> &xo, V3<double> &yo) {
+            if constexpr (COUNT) c_step++;
             V3<double> dx, dv;
             if constexpr (STEP == STEP_RK45) {
                 V3<double> A1 = a0, ex, ev;
@@ -906,6 +911,18 @@ __global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__res
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(A.stats + rti::ST_REFINED, (unsigned long long)n);
+    if constexpr (COUNT) {
+        unsigned v[3] = {c_eval, c_bump, c_step};
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v[q] += __shfl_xor(v[q], o);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(A.stats + rti::ST_REF_EVALS, (unsigned long long)v[0]);
+            atomicAdd(A.stats + rti::ST_REF_BUMPS, (unsigned long long)v[1]);
+            atomicAdd(A.stats + rti::ST_REF_STEPS, (unsigned long long)v[2]);
+        }
+    }
 }
 
 // ====================================================== ordered compaction
@@ -1045,7 +1062,12 @@ hipError_t launch_kind_step(const TraceArgs &a, const rti::DeviceData &d, int n_
         if (e != hipSuccess) return e;
         if (ev) (void)hipEventRecord(ev[2 + p], s);
     }
-    hipLaunchKernelGGL((k_refine<KIND, STEP>), dim3(rgrid), dim3(256), 0, s, a, d.bump_d, d.sph_d, d.pln_d, d.tor_d);
+    if (a.count)
+        hipLaunchKernelGGL((k_refine<KIND, STEP, true>), dim3(rgrid), dim3(256), 0, s, a, d.bump_d, d.sph_d, d.pln_d,
+                           d.tor_d);
+    else
+        hipLaunchKernelGGL((k_refine<KIND, STEP>), dim3(rgrid), dim3(256), 0, s, a, d.bump_d, d.sph_d, d.pln_d,
+                           d.tor_d);
     hipError_t e = hipGetLastError();
     if (ev) (void)hipEventRecord(ev[2 + n_passes], s);
     return e;

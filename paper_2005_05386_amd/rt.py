@@ -90,7 +90,8 @@ class rt_stats(C.Structure):
                 ("crossings", C.c_uint64), ("accepted", C.c_uint64), ("surr_ms", C.c_float),
                 ("eligible", C.c_int), ("adj_steps", C.c_uint64), ("adj_bump_terms", C.c_uint64),
                 ("adj_recomputed", C.c_uint64),
-                ("batch_windows", C.c_uint64), ("batch_replays", C.c_uint64)]
+                ("batch_windows", C.c_uint64), ("batch_replays", C.c_uint64),
+                ("refine_evals", C.c_uint64), ("refine_bump_terms", C.c_uint64), ("refine_steps", C.c_uint64)]
 
 
 _P = C.c_void_p
@@ -436,7 +437,8 @@ class Tracer:
 
     def surrogate_gen(self, kappa, scale, n_per, h, grid=False, seed=0, mode=None):
         """Crossing data for each shape kappa (mode 0: sin^2 th uniform,
-        1: cos-theta grid, 2: sin th uniform; grid=True selects mode 1):
+        1: cos-theta grid, 2: sin th uniform, 4 / 6: 0 / 2 with stratified
+        draws; grid=True selects mode 1):
         returns x, y [n,n_per,6], aux [n,n_per,4]."""
         import torch
         k = np.ascontiguousarray(kappa, np.float32)

@@ -69,6 +69,29 @@ def test_crossing_data_random_mode(env):
     assert np.all(aux[..., 1] >= 0)                        # every ray left the sphere
 
 
+@pytest.mark.parametrize("mode", [4, 6])
+def test_crossing_data_stratified_mode(env, mode):
+    """Stratified draws (the training loop's): sample i of n takes its
+    uniform variable in stratum [i / n, (i + 1) / n), sin^2 th for mode 4 and
+    sin th for mode 6; labels of a few samples against the exact crossing."""
+    rt, surrogate, torch, tr = env
+    say("crossing data stratified mode %d" % mode)
+    n, kappa = 4096, 1.2
+    x, y, aux = tr.surrogate_gen([kappa], [1.0], n, 0.01, seed=7, mode=mode)
+    x, y, aux = (a.cpu().numpy()[0].astype(np.float64) for a in (x, y, aux))
+    s = x[:, 4]
+    u = s * s if mode == 4 else s
+    lo = np.arange(n) / n
+    assert np.all(u >= lo - 1e-6) and np.all(u < lo + 1.0 / n + 1e-6), np.abs(u - lo - 0.5 / n).max()
+    assert np.all(aux[:, 1] >= 0)
+    for i in (100, 1500, 3000, 4000):
+        c = -x[i, 3]
+        dphi, arc = exact.crossing_exact(kappa, c)
+        ex = np.array([-(c * c - s[i] * s[i]), 2 * s[i] * c, 0.0]) + y[i, :3]
+        assert abs(np.arctan2(ex[1], ex[0]) % (2 * np.pi) - dphi) < 2e-5, (i, c)
+        assert abs(aux[i, 1] - arc) < 2e-4, (i, aux[i, 1], arc)
+
+
 def _nets(torch, n, seed=10):
     p = np.stack([mlp.init_params(seed + i) for i in range(n)])
     rng = np.random.default_rng(seed)
