@@ -117,10 +117,17 @@ __device__ __forceinline__ void stage_store(__bf16 (*S)[40], int tid, const bf16
     }
 }
 
-template <int LA, int LB>
+// VEC: every tile is whole and the outputs (and Z) are 16-byte aligned with
+// row strides a multiple of 8 elements; the epilogue then goes through LDS
+// and every thread stores 16 consecutive values of one row with 16-byte
+// stores (EPI_NONE and EPI_DSILU).
+template <int LA, int LB, bool VEC = false>
 __global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G, int ntx, int nty, int ntz) {
-    __shared__ __attribute__((aligned(16))) __bf16 As[64][32 + 8];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[64][32 + 8];  // transposed: Bs[n][k]
+    // one LDS block: the two staging arrays, reused for the output tile
+    __shared__ __attribute__((aligned(16))) float smem[VEC ? 64 * 68 : 64 * 40];
+    static_assert(sizeof(smem) >= 2 * 64 * 40 * sizeof(__bf16), "staging exceeds the LDS block");
+    __bf16(*As)[40] = reinterpret_cast<__bf16(*)[40]>(&smem[0]);
+    __bf16(*Bs)[40] = reinterpret_cast<__bf16(*)[40]>(&smem[0]) + 64;  // transposed: Bs[n][k]
     int tx, ty, g;
     if (!xcd_tile(ntx, nty, ntz, tx, ty, g)) return;
     int M = G.M;
@@ -166,6 +173,53 @@ __global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G, int ntx, int nty,
             for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
+    if constexpr (VEC) {
+        // the staging arrays are free after the loop's last barrier
+        float(*Zs)[68] = reinterpret_cast<float(*)[68]>(&smem[0]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    Zs[wm + 16 * i + (lane >> 4) * 4 + e][wn + 16 * j + (lane & 15)] = acc[i][j][e];
+        __syncthreads();
+        const int rr = tid >> 2, c0 = (tid & 3) * 16;
+        const int64_t gm = row0 + m0 + rr;
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 t = *reinterpret_cast<const float4 *>(&Zs[rr][c0 + 4 * q]);
+            v[4 * q] = t.x;
+            v[4 * q + 1] = t.y;
+            v[4 * q + 2] = t.z;
+            v[4 * q + 3] = t.w;
+        }
+        if (G.epi == rti::EPI_DSILU) {
+            const float *zp = G.Z + g * G.z_g + gm * G.ldz + n0 + c0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 z = *reinterpret_cast<const float4 *>(zp + 4 * q);
+                v[4 * q] *= dsilu(z.x);
+                v[4 * q + 1] *= dsilu(z.y);
+                v[4 * q + 2] *= dsilu(z.z);
+                v[4 * q + 3] *= dsilu(z.w);
+            }
+            __bf16 *cb = G.Cb + g * G.cb_g + gm * G.ldcb + n0 + c0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                bf16x8 b;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) b[e] = (__bf16)v[8 * q + e];
+                *reinterpret_cast<bf16x8 *>(cb + 8 * q) = b;
+            }
+        }
+        float *cf = G.Cf + g * G.cf_g + gm * G.ldcf + n0 + c0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<float4 *>(cf + 4 * q) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        return;
+    }
     // epilogue
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -198,6 +252,106 @@ __global__ __launch_bounds__(256) void k_gemm(rti::GemmArgs G, int ntx, int nty,
                     G.Cf[g * G.cf_g + gm * G.ldcf + n] = v;
                     break;
                 }
+            }
+}
+
+// Weight-gradient product: both operands have unit stride along m (or n)
+// and the long K (the batch) strided, C = sum_k A(m, k) B(k, n) with
+// A(m, k) = A[k sak + m], B(k, n) = B[k sbk + n], EPI_NONE.  A 64x64 tile
+// per block; the four waves split K in four contiguous quarters, each wave
+// accumulating the whole tile for its quarter (4x4 16x16x32 MFMA tiles)
+// with its own LDS staging, so the K loop has no block barrier.  A lane
+// loads four k rows of eight consecutive m and writes each m's four k values
+// as one 8-byte LDS store ([m][k] rows of 40).  The partial tiles are added
+// in a fixed order, (w0 + w2) + (w1 + w3), through LDS.  Needs K % 128 == 0,
+// M % 64 == 0, N % 64 == 0, 8 | the strides and 16-byte aligned bases.
+__global__ __launch_bounds__(256) void k_gemm_wgrad(rti::GemmArgs G, int ntx, int nty, int ntz) {
+    __shared__ __attribute__((aligned(16))) float smem[4 * 2 * 64 * 40 / 2];
+    static_assert(sizeof(smem) >= 2 * 64 * 64 * sizeof(float), "reduction exceeds the LDS block");
+    int tx, ty, g;
+    if (!xcd_tile(ntx, nty, ntz, tx, ty, g)) return;
+    const int m0 = ty * 64, n0 = tx * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __bf16(*As)[40] = reinterpret_cast<__bf16(*)[40]>(&smem[0]) + wave * 128;  // this wave's [m][k]
+    __bf16(*Bs)[40] = As + 64;                                                  // and [n][k]
+    const __bf16 *__restrict__ A = G.A + g * G.a_g;
+    const __bf16 *__restrict__ B = G.B + g * G.b_g;
+    const int kq4 = G.K / 4;
+    const int kb = wave * kq4;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // lane: k rows kr .. kr + 3 of the 32-wide slice, m (or n) columns c0 .. c0 + 7
+    const int kr = (lane >> 3) * 4, c0 = (lane & 7) * 8;
+    const int kq = (lane >> 4) * 8;
+    for (int k0 = kb; k0 < kb + kq4; k0 += 32) {
+        bf16x8 va[4], vb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            va[t] = *(const bf16x8 *)(A + (int64_t)(k0 + kr + t) * G.sak + m0 + c0);
+            vb[t] = *(const bf16x8 *)(B + (int64_t)(k0 + kr + t) * G.sbk + n0 + c0);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            const bf16x4 a4 = {va[0][e], va[1][e], va[2][e], va[3][e]};
+            const bf16x4 b4 = {vb[0][e], vb[1][e], vb[2][e], vb[3][e]};
+            *(bf16x4 *)&As[c0 + e][kr] = a4;
+            *(bf16x4 *)&Bs[c0 + e][kr] = b4;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bf16x8 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8 *)&As[16 * i + (lane & 15)][kq];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bf16x8 b = *(const bf16x8 *)&Bs[16 * j + (lane & 15)][kq];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // fixed-order sum of the four partial tiles: (w0 + w2) + (w1 + w3)
+    float(*R)[64][64] = reinterpret_cast<float(*)[64][64]>(&smem[0]);
+    auto put = [&](int slot) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) R[slot][16 * i + (lane >> 4) * 4 + e][16 * j + (lane & 15)] = acc[i][j][e];
+    };
+    auto add = [&](int slot) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[i][j][e] += R[slot][16 * i + (lane >> 4) * 4 + e][16 * j + (lane & 15)];
+    };
+    __syncthreads();
+    if (wave >= 2) put(wave - 2);
+    __syncthreads();
+    if (wave < 2) add(wave);
+    __syncthreads();
+    if (wave == 1) put(0);
+    __syncthreads();
+    if (wave != 0) return;
+    add(0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 16 * i + (lane >> 4) * 4 + e, n = n0 + 16 * j + (lane & 15);
+                G.Cf[g * G.cf_g + (int64_t)m * G.ldcf + n] = acc[i][j][e];
             }
 }
 
@@ -234,13 +388,17 @@ __global__ __launch_bounds__(256) void k_l1_fwd(const float *__restrict__ params
     }
 }
 
+// Rows per partial of the FP32 layers' weight gradients: short serial
+// chunks, many blocks.
+constexpr int GRAD_ROWS = 32;
+
 // First-layer gradients in FP32: dW1[o][i] = sum_m dz1[m][o] x[m][i] and
-// db1[o] = sum_m dz1[m][o]; per block of 256 rows a sequential partial,
-// then the partials summed in order.
+// db1[o] = sum_m dz1[m][o]; per block of GRAD_ROWS rows a sequential
+// partial, then the partials summed in order.
 __global__ __launch_bounds__(256) void k_l1_grad_part(const float *__restrict__ DZ, const float *__restrict__ X, int B,
                                                       float *__restrict__ part) {
     const int g = blockIdx.y, c = blockIdx.x, o = threadIdx.x;
-    const int r0 = c * 256, r1 = min(B, r0 + 256);
+    const int r0 = c * GRAD_ROWS, r1 = min(B, r0 + GRAD_ROWS);
     float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int m = r0; m < r1; ++m) {
         const int64_t r = (int64_t)g * B + m;
@@ -269,29 +427,57 @@ __global__ __launch_bounds__(256) void k_l1_grad_final(const float *__restrict__
     G[rti::OFF_B1 + o] = a[6];
 }
 
-// Output layer in FP32: y[m][o] = b4[o] + sum_k W4[o][k] silu(z3[m][k]),
-// one thread per (row, output), k in order.
+// Output layer in FP32: y[m][o] = b4[o] + sum_k W4[o][k] silu(z3[m][k]).
+// One wave per row (the rows of a 64-row chunk of network blockIdx.y dealt
+// to the block's four waves), lane l taking k = l + 64 q in order of q, then
+// a butterfly sum over the lanes in a fixed pattern; W4 stays in registers.
 __global__ __launch_bounds__(256) void k_l4_fwd(const float *__restrict__ params, const float *__restrict__ Z3, int B,
                                                 float *__restrict__ Y) {
-    const int g = blockIdx.y;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= B * 6) return;
-    const int m = idx / 6, o = idx - m * 6;
-    const float *__restrict__ W = params + g * rti::MLP_P + rti::OFF_W4 + o * rti::MLP_H;
-    const float *__restrict__ z = Z3 + ((int64_t)g * B + m) * rti::MLP_H;
-    float acc = params[g * rti::MLP_P + rti::OFF_B4 + o];
-    for (int k = 0; k < rti::MLP_H; ++k) acc = fmaf(W[k], silu(z[k]), acc);
-    Y[((int64_t)g * B + m) * 6 + o] = acc;
+    const int g = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * 64;
+    if (m0 >= B) return;
+    const float *__restrict__ W = params + g * rti::MLP_P + rti::OFF_W4;
+    float w[6][4];
+#pragma unroll
+    for (int o = 0; o < 6; ++o)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[o][q] = W[o * rti::MLP_H + lane + 64 * q];
+    const float *__restrict__ b4 = params + g * rti::MLP_P + rti::OFF_B4;
+    const int m1 = min(B, m0 + 64);
+    for (int m = m0 + wave; m < m1; m += 4) {
+        const float *__restrict__ z = Z3 + ((int64_t)g * B + m) * rti::MLP_H;
+        float h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = silu(z[lane + 64 * q]);
+        float a[6];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            float t = w[o][0] * h[0];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) t = fmaf(w[o][q], h[q], t);
+            a[o] = t;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+            for (int o = 0; o < 6; ++o) a[o] += __shfl_xor(a[o], off);
+        if (lane < 6) {
+            float v = a[0];
+#pragma unroll
+            for (int o = 1; o < 6; ++o) v = lane == o ? a[o] : v;
+            Y[((int64_t)g * B + m) * 6 + lane] = b4[lane] + v;
+        }
+    }
 }
 
 // Output-layer gradients in FP32: dW4[o][k] = sum_m dy[m][o] silu(z3[m][k]),
-// db4[o] = sum_m dy[m][o]; per block of 256 rows a sequential partial
+// db4[o] = sum_m dy[m][o]; per block of GRAD_ROWS rows a sequential partial
 // (thread k: six dW4 partials, and db4[k] for k < 6), then the partials in
 // order.
 __global__ __launch_bounds__(256) void k_l4_grad_part(const float *__restrict__ DY, const float *__restrict__ Z3, int B,
                                                       float *__restrict__ part) {
     const int g = blockIdx.y, c = blockIdx.x, k = threadIdx.x;
-    const int r0 = c * 256, r1 = min(B, r0 + 256);
+    const int r0 = c * GRAD_ROWS, r1 = min(B, r0 + GRAD_ROWS);
     float a[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int m = r0; m < r1; ++m) {
         const int64_t r = (int64_t)g * B + m;
@@ -554,7 +740,19 @@ hipError_t launch_gemm(const GemmArgs &G, int groups, int max_rows, hipStream_t 
     const bool a_kc = dims && G.sak == 1 && al(G.A, G.a_g, G.sam);
     const bool b_nc = dims && G.sbn == 1 && al(G.B, G.b_g, G.sbk);
     const bool b_nc4 = dims && G.sbn == 1 && (uintptr_t)G.B % 4 == 0 && G.b_g % 2 == 0 && G.sbk % 8 == 0;
-    if (a_mc && b_nc)
+    // whole tiles and 16-byte aligned outputs: the LDS-staged epilogue
+    auto al16 = [](const void *p, int64_t a, int64_t b) { return ((uintptr_t)p % 16 == 0) && a % 4 == 0 && b % 4 == 0; };
+    const bool vec = dims && G.M % 64 == 0 && G.N % 64 == 0 &&
+                     (G.epi == EPI_NONE || (G.epi == EPI_DSILU && al16(G.Z, G.z_g, G.ldz) &&
+                                            (uintptr_t)G.Cb % 16 == 0 && G.cb_g % 8 == 0 && G.ldcb % 8 == 0)) &&
+                     al16(G.Cf, G.cf_g, G.ldcf);
+    if (a_mc && b_nc && G.epi == EPI_NONE && G.K % 128 == 0 && G.M % 64 == 0 && G.N % 64 == 0)
+        hipLaunchKernelGGL(k_gemm_wgrad, grid, dim3(256), 0, s, G, ntx, nty, groups);
+    else if (a_kc && b_nc4 && vec)
+        hipLaunchKernelGGL((k_gemm<L_KC, L_MC4, true>), grid, dim3(256), 0, s, G, ntx, nty, groups);
+    else if (a_kc && b_nc && vec)
+        hipLaunchKernelGGL((k_gemm<L_KC, L_MC, true>), grid, dim3(256), 0, s, G, ntx, nty, groups);
+    else if (a_mc && b_nc)
         hipLaunchKernelGGL((k_gemm<L_MC, L_MC>), grid, dim3(256), 0, s, G, ntx, nty, groups);
     else if (a_kc && b_nc)
         hipLaunchKernelGGL((k_gemm<L_KC, L_MC>), grid, dim3(256), 0, s, G, ntx, nty, groups);
@@ -601,14 +799,14 @@ namespace rti {
 
 size_t mlp_work_bytes(int n_nets, int batch) {
     size_t nb = (size_t)n_nets * batch;
-    size_t nch = ((size_t)batch + 255) / 256;
+    size_t nch = ((size_t)batch + GRAD_ROWS - 1) / GRAD_ROWS;
     return nb * MLP_IN * 4 + nb * MLP_OUT * 2 + nb * MLP_H * (3 * 4 + 6 * 2 + 2 * 4 + 2 * 2) +
            (size_t)n_nets * nch * MLP_H * 7 * 4 + 16 * 256;
 }
 
 void mlp_work_carve(void *base, int n_nets, int batch, MlpWork &w) {
     size_t nb = (size_t)n_nets * batch;
-    size_t nch = ((size_t)batch + 255) / 256;
+    size_t nch = ((size_t)batch + GRAD_ROWS - 1) / GRAD_ROWS;
     char *p = (char *)base;
     auto take = [&](size_t bytes) {
         char *r = p;
@@ -623,7 +821,7 @@ void mlp_work_carve(void *base, int n_nets, int batch, MlpWork &w) {
     for (int i = 0; i < 2; ++i) w.dzf[i] = (float *)take(nb * MLP_H * 4);
     for (int i = 0; i < 2; ++i) w.dzb[i] = (__bf16 *)take(nb * MLP_H * 2);
     // partials: nch x 7 x 256 per network for the FP32 layers, and
-    // ceil(batch / 64) x 256 <= 4 nch x 256 for the column sums
+    // ceil(batch / COLSUM_ROWS) x 256 <= 7 nch x 256 for the column sums
     w.part = (float *)take((size_t)n_nets * nch * MLP_H * 7 * 4);
 }
 
@@ -647,7 +845,7 @@ hipError_t mlp_forward(int n, int B, const __bf16 *wb, const float *params, cons
                        w.hl[1], n);
     hipLaunchKernelGGL(k_gemm_x3, grid, dim3(256), 0, s, w.h[1], w.hl[1], params, OFF_W3, OFF_B3, B, w.z[2], w.h[2],
                        w.hl[2], n);
-    hipLaunchKernelGGL(k_l4_fwd, dim3((B * 6 + 255) / 256, n), dim3(256), 0, s, params, w.z[2], B, y);
+    hipLaunchKernelGGL(k_l4_fwd, dim3((B + 63) / 64, n), dim3(256), 0, s, params, w.z[2], B, y);
     return hipGetLastError();
 }
 
@@ -703,7 +901,7 @@ hipError_t mlp_backward(int n, int B, const __bf16 *wb, const float *params, con
     };
     // output layer (FP32): weight and bias gradients, then dz3 into buffer 0
     {
-        const int nch4 = (B + 255) / 256;
+        const int nch4 = (B + GRAD_ROWS - 1) / GRAD_ROWS;
         hipLaunchKernelGGL(k_l4_grad_part, dim3(nch4, n), dim3(256), 0, s, dy, w.z[2], B, w.part);
         hipLaunchKernelGGL(k_l4_grad_final, dim3(n), dim3(256), 0, s, w.part, nch4, grad);
         hipLaunchKernelGGL(k_l4_bwd, dim3((B + 63) / 64, n), dim3(256), 0, s, params, dy, w.z[2], B, w.dzf[0],
@@ -723,7 +921,7 @@ hipError_t mlp_backward(int n, int B, const __bf16 *wb, const float *params, con
         return e;
     if ((e = bprop(w.dzb[1], MLP_H, OFF_W2, w.z[0], w.dzf[0], w.dzb[0])) != hipSuccess) return e;
     // layer 1 (FP32): dz in buffer 0, input x
-    const int nch = (B + 255) / 256;
+    const int nch = (B + GRAD_ROWS - 1) / GRAD_ROWS;
     hipLaunchKernelGGL(k_l1_grad_part, dim3(nch, n), dim3(256), 0, s, w.dzf[0], w.xf, B, w.part);
     hipLaunchKernelGGL(k_l1_grad_final, dim3(n), dim3(256), 0, s, w.part, nch, grad);
     return hipGetLastError();

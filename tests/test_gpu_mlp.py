@@ -31,9 +31,10 @@ def _params(torch, n, scale=1.0):
     return p, pt, pt.to(torch.bfloat16)
 
 
-# batches that are multiples of 8 take the vector-staged backward products
+# batches that are multiples of 8 take the vector-staged backward products,
+# multiples of 128 the split-K weight gradient and the LDS-staged epilogue
 # (264: a ragged last tile of 8 rows), the others the element-wise ones
-@pytest.mark.parametrize("n,batch", [(3, 37), (2, 300), (1, 1), (2, 264), (1, 1024)])
+@pytest.mark.parametrize("n,batch", [(3, 37), (2, 300), (1, 1), (2, 264), (1, 1024), (3, 512)])
 def test_mlp_forward_backward_match_oracle(env, n, batch):
     rt, torch, tr = env
     say("mlp fwd/bwd n_nets=%d batch=%d" % (n, batch))
