@@ -371,14 +371,34 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const int *__restrict__ ctl, 
                 }
             __syncthreads();
         }
-        // output layer, FP32: one thread per (row, output), k in order
-        for (int idx = tid; idx < 64 * 6; idx += 256) {
-            const int m = idx / 6, o = idx - m * 6;
-            if (m < M) {
-                const float *__restrict__ W = Pg + rti::OFF_W4 + o * 256;
-                float acc = Pg[rti::OFF_B4 + o];
-                for (int k = 0; k < 256; ++k) acc = fmaf(W[k], Hf[m][k], acc);
-                S.xout[6 * (int64_t)(m0 + m) + o] = acc;
+        // output layer, FP32, in the training forward's order: one wave per
+        // row, lane l taking k = l + 64 q in order of q, then a butterfly sum
+        // over the lanes, then the bias
+        {
+            float w4[6][4];
+#pragma unroll
+            for (int o = 0; o < 6; ++o)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w4[o][q] = Pg[rti::OFF_W4 + o * 256 + lane + 64 * q];
+            for (int m = wave; m < M; m += 4) {
+                float a[6];
+#pragma unroll
+                for (int o = 0; o < 6; ++o) {
+                    float t = w4[o][0] * Hf[m][lane];
+#pragma unroll
+                    for (int q = 1; q < 4; ++q) t = fmaf(w4[o][q], Hf[m][lane + 64 * q], t);
+                    a[o] = t;
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+                    for (int o = 0; o < 6; ++o) a[o] += __shfl_xor(a[o], off);
+                if (lane < 6) {
+                    float v = a[0];
+#pragma unroll
+                    for (int o = 1; o < 6; ++o) v = lane == o ? a[o] : v;
+                    S.xout[6 * (int64_t)(m0 + m) + lane] = Pg[rti::OFF_B4 + lane] + v;
+                }
             }
         }
         __syncthreads();

@@ -789,8 +789,11 @@ __device__ __forceinline__ double obj_F64(int id, V3<double> x, int ns, int np, 
 
 // COUNT: also counts the acceleration evaluations, the bumps inside their
 // cut at them (graph metric) and the integrator steps (work statistics).
+// Occupancy: the graph-metric RK4 refine is compiled for 4 waves per SIMD
+// (128 VGPRs, 36 B of spills; 3.5% faster than 3 waves at 156 VGPRs); the
+// other kinds need 144-204 VGPRs and would spill 50-300 B.
 template <int KIND, int STEP, bool COUNT = false>
-__global__ __launch_bounds__(256) void k_refine(TraceArgs A, const double *__restrict__ BD,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == KIND_GRAPH && STEP == STEP_RK4 ? 4 : 1, 8))) void k_refine(TraceArgs A, const double *__restrict__ BD,
                                                 const double *__restrict__ SPD, const double *__restrict__ PLD,
                                                 const double *__restrict__ TOD) {
     const int n = A.ctr[rti::CTR_REFINE];
