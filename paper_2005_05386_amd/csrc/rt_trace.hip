@@ -81,8 +81,9 @@ __device__ __forceinline__ float4 *batch_save() {
 
 // ================================================================ the pass
 // Occupancy: 7 waves per SIMD (at most 72 VGPRs) measured fastest for the
-// RK4 graph and twist kernels, 6 for DP5(4), although long-lived values
-// spill (the spills are a small share of the instructions).
+// RK4 graph and twist kernels, 6 for DP5(4) and for rotating deformations
+// (77.5 -> 72.2 ms per 1080p frame), although long-lived values spill (the
+// spills are a small share of the instructions).
 // SURR: learned crossings (graph metric, RK4, one parameter set): a ray whose
 // step chord enters the support sphere of an eligible bump stops on the
 // sphere (the partial step is committed, its fraction of h added to t) and
@@ -107,7 +108,7 @@ __device__ __forceinline__ float4 *batch_save() {
 // only once its box is cleared.  Windows and object lists only bound the
 // work, so the outputs equal the plain kernel's bit for bit.
 template <int KIND, int STEP, bool COUNT, bool SURR = false, bool TAPE = false, bool BATCH = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 ? 6 : (BATCH ? RT_BATCH_WAVES : RT_PASS_WAVES), 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 || KIND == KIND_DEFORM_ROT ? 6 : (BATCH ? RT_BATCH_WAVES : RT_PASS_WAVES), 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
                                                     const float *__restrict__ TOR) {
@@ -791,7 +792,7 @@ __device__ __forceinline__ double obj_F64(int id, V3<double> x, int ns, int np, 
 // cut at them (graph metric) and the integrator steps (work statistics).
 // Occupancy: the graph-metric RK4 refine is compiled for 4 waves per SIMD
 // (128 VGPRs, 36 B of spills; 3.5% faster than 3 waves at 156 VGPRs); the
-// other kinds need 144-204 VGPRs and would spill 50-300 B.
+// other kinds need 144-204 VGPRs, and 3 or 4 waves measured no faster.
 template <int KIND, int STEP, bool COUNT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == KIND_GRAPH && STEP == STEP_RK4 ? 4 : 1, 8))) void k_refine(TraceArgs A, const double *__restrict__ BD,
                                                 const double *__restrict__ SPD, const double *__restrict__ PLD,
