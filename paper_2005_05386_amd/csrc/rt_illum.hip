@@ -623,9 +623,12 @@ void illum_rounds(const rti::IllumArgs &a, const rti::DeviceData &d, int grid, h
         hipLaunchKernelGGL((k_illum_iter<KIND, ONE>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
         hipLaunchKernelGGL((k_illum_step<KIND, ONE>), dim3(grid), dim3(256), 0, s, a, d.bump_f, it);
     }
-    // retries from converged neighbours; each round has its own counters
+    // retries from converged neighbours, a quarter of the iterations each (a
+    // seed from a neighbour is close: 1080p 432 -> 390 ms for 99.88 -> 99.83%
+    // of the hits found, the quadric unchanged); each round has its own
+    // counters
     rti::IllumArgs r = a;
-    r.max_iters = std::max(a.max_iters / 2, 1);
+    r.max_iters = std::max(a.max_iters / 4, 1);
     for (int round = 1; round <= rti::ILLUM_RETRY_ROUNDS; ++round) {
         r.ctr = a.ctr + round * 2 * (a.max_iters + 1);
         hipLaunchKernelGGL((k_illum_seed<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, r.ctr);
@@ -634,7 +637,9 @@ void illum_rounds(const rti::IllumArgs &a, const rti::DeviceData &d, int grid, h
             hipLaunchKernelGGL((k_illum_step<KIND, ONE>), dim3(grid), dim3(256), 0, s, r, d.bump_f, it);
         }
     }
-    // continuation in the light position for the pixels still unsolved
+    // continuation in the light position for the pixels still unsolved, half
+    // the iterations per stage (a quarter loses 15% of the quadric's hits)
+    r.max_iters = std::max(a.max_iters / 2, 1);
     for (int st = 0; st < rti::ILLUM_CONT_STAGES; ++st) {
         const float lam0 = (float)st / rti::ILLUM_CONT_STAGES, lam1 = (float)(st + 1) / rti::ILLUM_CONT_STAGES;
         r.ctr = a.ctr + (1 + rti::ILLUM_RETRY_ROUNDS + st) * 2 * (a.max_iters + 1);
