@@ -68,6 +68,25 @@ def test_mlp_forward_backward_match_oracle(env, n, batch):
     say("worst relative error: forward %.2e, backward %.2e" % (worst_f, worst_b))
 
 
+@pytest.mark.parametrize("n,batch", [(2, 1024), (3, 264)])
+def test_mlp_backward_is_deterministic(env, n, batch):
+    """The weight gradients split K over the waves of a block and sum the
+    partial tiles in a fixed order, the FP32 layers sum fixed row chunks in
+    order: two backward passes give the same bits."""
+    rt, torch, tr = env
+    say("mlp backward determinism n_nets=%d batch=%d" % (n, batch))
+    p, pt, pb = _params(torch, n)
+    rng = np.random.default_rng(5)
+    x = torch.tensor(rng.normal(size=(n, batch, 6)).astype(np.float32), device="cuda")
+    dy = torch.tensor(rng.normal(size=(n, batch, 6)).astype(np.float32), device="cuda")
+    out = []
+    for _ in range(2):
+        work = tr.mlp_work(n, batch)
+        tr.mlp_fwd(pb, pt, x, work)
+        out.append(tr.mlp_bwd(pb, pt, dy, work).cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
 def test_adamw_step(env):
     rt, torch, tr = env
     say("adamw")
