@@ -52,7 +52,7 @@ def test_mlp_forward_backward_match_oracle(env, n, batch):
         ef = np.abs(y[i] - yr).max() / max(1.0, np.abs(yr).max())
         worst_f = max(worst_f, ef)
         # the oracle rounds at the same bf16 points; what remains is FP32
-        # accumulation order (measured worst 3.6e-6)
+        # accumulation order (measured worst 4.1e-6)
         assert ef <= 2e-5, (i, ef)
         gr = mlp.backward(p32[i], x[i].astype(np.float64), dy[i].astype(np.float64), bf16=True)
         for blk, (a, b) in enumerate(zip(mlp.split(g[i].astype(np.float64)), mlp.split(gr))):
