@@ -222,7 +222,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
             V3<float> bmin = mk(0.f, 0.f, 0.f), bmax = bmin;
 
             for (;;) {
-                bool act = alive && (STEP == STEP_RK45 ? acc_pass < A.S : (BATCH ? it_m : it) < A.S) && !(SURR && parked);
+                bool act = alive && (STEP == STEP_RK45 ? acc_pass < A.S : it < A.S) && !(SURR && parked);
+                // batched: the pass length counts first marches only
                 if constexpr (BATCH) act = alive && (replay ? (!hold && wi < wlen) : it_m < A.S);
                 uint64_t am = ballot(act);
                 if (am == 0) {
