@@ -36,8 +36,13 @@ static_assert(rtd::KIND_DEFORM_ROT == rti::KERNEL_KIND_DEFORM_ROT, "rotating def
 
 namespace {
 
+// The output index is made opaque where it is used: otherwise the compiler
+// hoists the nine per-lane output addresses (18 registers, loop invariant)
+// out of the step loop, where they stay live through every step for a
+// store that happens once per ray.
 __device__ __forceinline__ void write_out(const TraceArgs &A, unsigned oi, V3<float> x, float t, V3<float> y, int id,
                                           int steps) {
+    __asm__ volatile("" : "+v"(oi));
     A.out_hit[3 * oi + 0] = x.x;
     A.out_hit[3 * oi + 1] = x.y;
     A.out_hit[3 * oi + 2] = x.z;
@@ -94,6 +99,9 @@ __device__ __forceinline__ float4 *batch_save() {
 #ifndef RT_PASS_WAVES
 #define RT_PASS_WAVES 7  // waves per SIMD the RK4 and Euler pass kernels are compiled for
 #endif
+#ifndef RT_GRAPH_WAVES
+#define RT_GRAPH_WAVES 8  // the same for the plain isotropic graph metric (64 registers, no spill in the step loop)
+#endif
 #ifndef RT_BATCH_WAVES
 #define RT_BATCH_WAVES 6  // the same for the batched-segment variant
 #endif
@@ -108,12 +116,16 @@ __device__ __forceinline__ float4 *batch_save() {
 // only once its box is cleared.  Windows and object lists only bound the
 // work, so the outputs equal the plain kernel's bit for bit.
 template <int KIND, int STEP, bool COUNT, bool SURR = false, bool TAPE = false, bool BATCH = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 || KIND == KIND_DEFORM_ROT ? 6 : (BATCH ? RT_BATCH_WAVES : RT_PASS_WAVES), 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 || KIND == KIND_DEFORM_ROT ? 6 : (BATCH ? RT_BATCH_WAVES : (KIND == KIND_GRAPH && !SURR && !TAPE ? RT_GRAPH_WAVES : RT_PASS_WAVES)), 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
                                                     const float *__restrict__ TOR) {
     static_assert(!BATCH || (STEP != STEP_RK45 && !COUNT && !SURR && !TAPE),
                   "batched segments: fixed-step integrators, plain trace");
+    // t as two floats, the trial step and the attempt count change only
+    // under DP5(4) and learned crossings; fixed-step traces derive t from the
+    // step count and neither read nor keep them
+    constexpr bool CARRY_T = STEP == STEP_RK45 || SURR;
     const int lane = lane_id();
     const int xcd0 = blockIdx.x % N_XCD;
     int *pass_ctr = A.ctr + rti::CTR_PASS0 + pass * rti::CTR_PASS_WORDS;
@@ -194,11 +206,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                 xh = mk(F(rti::Q_XH), F(rti::Q_XH + 1), F(rti::Q_XH + 2));
                 xl = mk(F(rti::Q_XL), F(rti::Q_XL + 1), F(rti::Q_XL + 2));
                 y = mk(F(rti::Q_Y), F(rti::Q_Y + 1), F(rti::Q_Y + 2));
-                th = F(rti::Q_TH);
-                tl = F(rti::Q_TL);
-                hc = F(rti::Q_H);
+                if constexpr (CARRY_T) {
+                    th = F(rti::Q_TH);
+                    tl = F(rti::Q_TL);
+                    hc = F(rti::Q_H);
+                    att = __float_as_int(F(rti::Q_ATT));
+                }
                 steps = __float_as_int(F(rti::Q_STEPS));
-                att = __float_as_int(F(rti::Q_ATT));
                 if constexpr (SURR) skip = __float_as_int(F(rti::Q_SKIP));
             } else {
                 xh = xl = y = mk(0.f, 0.f, 0.f);
@@ -241,6 +255,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
 
                 // ---- per-wave culling window
                 if (BATCH ? (!replay && wi == 0) : it % A.K == 0) {
+                    // the lane id taken afresh: the table offsets derived from it
+                    // are then formed in this block, once per window, instead of
+                    // being hoisted out of the step loop and spilled (not in the
+                    // batched variant, whose twist kernel then spilled inside its
+                    // step loop and ran 1.6x slower)
+                    int lane = lane_id();
+                    if constexpr (!BATCH) __asm__ volatile("" : "+v"(lane));
                     V3<float> p = xh + xl;
                     if (A.cull_margin < 0.f) {
                         bmask = n_bumps >= 64 ? ~0ull : ((1ull << n_bumps) - 1ull);
@@ -725,11 +746,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STE
                     P(rti::Q_Y, y.x);
                     P(rti::Q_Y + 1, y.y);
                     P(rti::Q_Y + 2, y.z);
-                    P(rti::Q_TH, th);
-                    P(rti::Q_TL, tl);
-                    P(rti::Q_H, hc);
+                    if constexpr (CARRY_T) {
+                        P(rti::Q_TH, th);
+                        P(rti::Q_TL, tl);
+                        P(rti::Q_H, hc);
+                        P(rti::Q_ATT, __int_as_float(att));
+                    }
                     P(rti::Q_STEPS, __int_as_float(steps));
-                    P(rti::Q_ATT, __int_as_float(att));
                     if constexpr (SURR) P(rti::Q_SKIP, __int_as_float(skip));
                 }
             }
