@@ -209,11 +209,15 @@ typedef struct rt_camera {
  *                clipped to t_max; a step below h_min fails the ray (id -2).
  * RT_STEP_EULER  the paper's explicit Euler march (Eq. 4.1), step h.
  * A ray stops at the first accepted step whose segment meets the scene; the
- * hit is then refined in double precision by bisection of the step fraction
- * s on the sign of the object's implicit function along the partial step of
- * the same integrator (bisect_iters halvings; a grazing sphere segment with
- * no sign change keeps the segment's root).  Otherwise it stops after
- * max_steps accepted steps or when t reaches t_max (miss). */
+ * hit is then refined in double precision: the step fraction s where the
+ * object's implicit function changes sign along the partial step of the same
+ * integrator is bracketed to a width of 2^-bisect_iters (the precision of
+ * that many bisection halvings), by regula falsi with the Illinois
+ * modification started at the segment's root and a halving whenever two
+ * probes have not halved the bracket; s is the bracket's midpoint.  A
+ * grazing sphere segment with no sign change keeps the segment's root.
+ * Otherwise it stops after max_steps accepted steps or when t reaches t_max
+ * (miss). */
 typedef enum rt_step_kind { RT_STEP_RK4 = 0, RT_STEP_RK45 = 1, RT_STEP_EULER = 2 } rt_step_kind;
 
 typedef struct rt_step_rule {
@@ -224,7 +228,8 @@ typedef struct rt_step_rule {
     float t_max;       /* > 0; RK4/Euler rays also stop at max_steps */
     int cull_every;    /* K: steps between per-wave re-culls of bumps/objects, 1..256 (16) */
     int pass_steps;    /* S: steps per launch before surviving rays are compacted, >= 16 (256) */
-    int bisect_iters;  /* FP64 bisection halvings for the hit, 0..60 (24: h 2^-24 is below the float spacing of the hit) */
+    int bisect_iters;  /* hit refinement: bracket the step fraction to 2^-bisect_iters, 0..60 (24: h 2^-24 is below the
+                          float spacing of the hit; 0: no refinement, s = 1/2 when the sign changes) */
     int flags;         /* RT_FLAG_* bits, 0 for a plain trace */
 } rt_step_rule;
 

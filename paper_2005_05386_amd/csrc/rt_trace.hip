@@ -898,13 +898,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == KIN
         double F1 = obj_F64(obj, x1, A.n_spheres, A.n_planes, SPD, PLD, TOD);
         double s = sc;
         if ((F0 > 0.0) != (F1 > 0.0)) {
-            double lo = 0.0, hi = 1.0;
-            for (int i = 0; i < A.bisect_iters; ++i) {
-                double mid = 0.5 * (lo + hi);
+            // The bracket [lo, hi] of the sign change is narrowed to a width
+            // of 2^-bisect_iters, as bisection would, but by regula falsi with
+            // the Illinois modification (the value at an end kept twice in a
+            // row is halved), the first probe at the segment's FP32 root: a
+            // handful of probes instead of one per halving, since the implicit
+            // function is nearly linear across one step.  When two probes
+            // have not halved the bracket the next one is a plain halving, so
+            // the bracket halves at least every third probe.
+            const bool pos0 = F0 > 0.0;
+            const double tol = ldexp(1.0, -A.bisect_iters);
+            double lo = 0.0, hi = 1.0, flo = F0, fhi = F1;
+            double w_ref = 1.0;
+            int kept = 0, since = 0;  // end kept by the last probe (-1 lo, +1 hi); probes since the last check
+            bool halve = false;
+            for (int i = 0; i < 3 * A.bisect_iters + 2 && hi - lo > tol; ++i) {
+                double m = i == 0 ? sc : (halve ? 0.5 * (lo + hi) : lo + (hi - lo) * (flo / (flo - fhi)));
+                if (!(m > lo && m < hi)) m = 0.5 * (lo + hi);
                 V3<double> xm, ym;
-                step(mid * h, xm, ym);
-                if ((obj_F64(obj, xm, A.n_spheres, A.n_planes, SPD, PLD, TOD) > 0.0) == (F0 > 0.0)) lo = mid;
-                else hi = mid;
+                step(m * h, xm, ym);
+                const double fm = obj_F64(obj, xm, A.n_spheres, A.n_planes, SPD, PLD, TOD);
+                if (fm == 0.0) {
+                    lo = hi = m;
+                    break;
+                }
+                if ((fm > 0.0) == pos0) {
+                    lo = m;
+                    flo = fm;
+                    if (kept == 1) fhi *= 0.5;
+                    kept = 1;
+                } else {
+                    hi = m;
+                    fhi = fm;
+                    if (kept == -1) flo *= 0.5;
+                    kept = -1;
+                }
+                halve = false;
+                if (++since == 2) {
+                    halve = hi - lo > 0.5 * w_ref;
+                    w_ref = hi - lo;
+                    since = 0;
+                }
             }
             s = 0.5 * (lo + hi);
         }

@@ -198,6 +198,34 @@ def test_twist_rays_near_its_centre(rt):
     assert abs(g["hit"][c, 0]) < 1e-6 and abs(g["hit"][c, 1]) < 1e-6
 
 
+def test_refinement_brackets_the_root(rt):
+    """The hit refinement brackets the step fraction s of the sign change to
+    a width of 2^-bisect_iters and returns the bracket's midpoint: within
+    h 2^-(n+1) of the root in s, so t within that and the hit point within
+    that times the Euclidean speed (<= 1 for the graph metric, plus the
+    step's own curvature), up to the
+    FP32 rounding of the outputs.  Checked against a 40-iteration trace of
+    the same frame; object ids do not depend on the refinement."""
+    say("refinement precision: bumps16 160x90, bisect_iters 8 / 16 / 24 against 40")
+    wl = W.with_size(W.get("bumps16_1080p"), 160, 90)
+    h = wl["rule"]["h"]
+    ref = gpu_trace(rt, wl, rule=dict(wl["rule"], bisect_iters=40))
+    hit = ref["id"] >= 0
+    assert hit.sum() > 2000
+    for n in (8, 16, 24):
+        g = gpu_trace(rt, wl, rule=dict(wl["rule"], bisect_iters=n))
+        assert np.array_equal(g["id"], ref["id"])
+        bound = h * 2.0 ** -(n + 1) * 1.001
+        ulp_t = np.spacing(np.abs(ref["t"][hit])).astype(np.float64)
+        dt = np.abs(g["t"][hit].astype(np.float64) - ref["t"][hit])
+        assert np.all(dt <= bound + 2 * ulp_t), (n, dt.max())
+        ulp_x = np.spacing(np.abs(ref["hit"][hit])).max(axis=1).astype(np.float64)
+        dx = np.linalg.norm(g["hit"][hit].astype(np.float64) - ref["hit"][hit], axis=1)
+        # the partial step's end moves at h (|y| + O(h |a|)) per unit of s
+        assert np.all(dx <= 1.1 * bound + 4 * ulp_x), (n, dx.max())
+        say("  bisect_iters=%d: max |dt| %.3g, max |dx| %.3g, bound %.3g" % (n, dt.max(), dx.max(), bound))
+
+
 def test_euler_single_bump(rt):
     say("single_bump Euler h=0.01")
     wl = W.get("single_bump_64")
