@@ -53,14 +53,15 @@ FLOPS = {
     # quadratic: grad f 6, y^T H y 9, 1 + |grad f|^2 6, reciprocal and scale 5
     "gquad_eval": 26,
     # RK4: step 74 (3 stage states 36, stage sums 30, h/2 and h/6 scaling 8), x_hi + x_lo 3,
-    # chord length 5, two-float position update 21 (7 per coordinate), velocity update 3
-    "rk4_step": 106,
-    # Euler: h y and h a 6, x_hi + x_lo 3, chord length 5, two-float update 21, velocity update 3
-    "euler_step": 38,
+    # chord length 5, two-float position update 12 (Fast2Sum and the low part, 4 per
+    # coordinate), velocity update 3
+    "rk4_step": 97,
+    # Euler: h y and h a 6, x_hi + x_lo 3, chord length 5, two-float update 12, velocity update 3
+    "euler_step": 29,
     # DP5(4): stage states 280 (6 positions with their h^2 terms, 6 velocities), 5th-order
     # increments 66, embedded error 77, h^2 1; error norm and step control 58; x_hi + x_lo,
-    # chord length, two-float position and time updates, velocity update 39
-    "dp5_attempt": 521,
+    # chord length, two-float position and time updates (12 + 4), velocity update 27
+    "dp5_attempt": 509,
     "obj_test": 20,          # one segment-object test
     # adjoint (RK4, graph metric), per full step reversed: the stage sums
     # recomputed 4 x 16, the stage VJP overheads 4 x 32 (|y|^2 5, 1/(1 + |g|^2) 7,
@@ -70,11 +71,11 @@ FLOPS = {
     "adj_rev_step": 408,
     "adj_term": 114,
     # per step recomputed from a checkpoint: one RK4 step with its 4 evaluations
-    # (106 + 4 x 16) plus 27 per bump term inside its cut
-    "adj_recomp_step": 170,
+    # (97 + 4 x 16) plus 27 per bump term inside its cut
+    "adj_recomp_step": 161,
     # crossing generator (training data): one RK4 step in the canonical frame
-    # with its single bump always inside the cut, 4 x (16 + 27) + 106
-    "cross_step": 278,
+    # with its single bump always inside the cut, 4 x (16 + 27) + 97
+    "cross_step": 269,
     # FP64 hit refinement (graph metric): per evaluation and per bump inside
     # its cut as in FP32 (the exponential counted once, although FP64 exp is
     # a software routine); per RK4 step 80 (stage states 36, stage sums 30,
