@@ -100,7 +100,7 @@ __device__ __forceinline__ float4 *batch_save() {
 #define RT_PASS_WAVES 7  // waves per SIMD the RK4 and Euler pass kernels are compiled for
 #endif
 #ifndef RT_GRAPH_WAVES
-#define RT_GRAPH_WAVES 8  // the same for the plain isotropic graph metric (64 registers, no spill in the step loop)
+#define RT_GRAPH_WAVES 8  // the same for the isotropic graph metric, plain and taped (64 registers, no spill in the step loop)
 #endif
 #ifndef RT_BATCH_WAVES
 #define RT_BATCH_WAVES 6  // the same for the batched-segment variant
@@ -116,7 +116,7 @@ __device__ __forceinline__ float4 *batch_save() {
 // only once its box is cleared.  Windows and object lists only bound the
 // work, so the outputs equal the plain kernel's bit for bit.
 template <int KIND, int STEP, bool COUNT, bool SURR = false, bool TAPE = false, bool BATCH = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 || KIND == KIND_DEFORM_ROT ? 6 : (BATCH ? RT_BATCH_WAVES : (KIND == KIND_GRAPH && !SURR && !TAPE ? RT_GRAPH_WAVES : RT_PASS_WAVES)), 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP == STEP_RK45 || KIND == KIND_DEFORM_ROT ? 6 : (BATCH ? RT_BATCH_WAVES : (KIND == KIND_GRAPH && !SURR ? RT_GRAPH_WAVES : RT_PASS_WAVES)), 8))) void k_trace_pass(TraceArgs A, int pass, const float4 *__restrict__ BF,
                                                     const float4 *__restrict__ SPH,
                                                     const float4 *__restrict__ PLN,
                                                     const float *__restrict__ TOR) {
