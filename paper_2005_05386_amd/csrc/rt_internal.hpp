@@ -199,7 +199,7 @@ struct IllumArgs {
     float *w_al, *w_be, *w_T, *w_F;  // angles, length, last residual
     float *w_X, *w_Y;                // base shot's end point and velocity [3 per pixel]
     int *list[3];
-    int *ctr;  // per round 2 (max_iters + 1) words: list sizes, then step-list sizes
+    int *ctr;  // 2 (max_iters + 1) words for each shooting attempt: list sizes, then step-list sizes
     // continuation rounds: the shots aim at q + cont (L - q) instead of L,
     // and a pixel that converges there is marked conv_code
     float cont;
