@@ -2,14 +2,19 @@
 
 One step = one full trace of the workload frame: every pixel, every
 integration pass and the FP64 hit refinement, with the metric, scene and
-output buffers already resident in HBM.  `value` is rays per second.
+output buffers already resident in HBM.  `value` is rays per second with
+--frames-in-flight frames (default 2) traced concurrently, each on its own
+stream with its own context and outputs, K frames in all between two device
+synchronisations; `frame_latency_ms` is one frame traced alone (a separate
+serial loop of K frames, which also gives the kernel times).
 
 The JSON line also carries
   roofline      the integration-pass kernel against the FP32 vector peak:
                 algorithmic FLOPs (counted per lane by the instrumented
                 kernel variant, priced with the per-unit figures below)
-                divided by the pass kernels' HIP-event time inside the
-                timed region;
+                divided by the pass kernels' HIP-event time in the serial
+                loop (launches that do not overlap); frame_rate_tflops is
+                the same FLOPs over the throughput's time per frame;
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded,
                 seeded pixel sample of the same workload.
 """
@@ -594,6 +599,8 @@ def main():
     ap.add_argument("--surr-samples", type=int, default=10_000_000, help="training crossings per bump shape")
     ap.add_argument("--surr-tol", type=float, default=1e-3, help="probe tolerance on the hit error")
     ap.add_argument("--surr-pass-steps", type=int, default=1024, help="steps per pass in surrogate traces")
+    ap.add_argument("--frames-in-flight", type=int, default=2,
+                    help="frames traced concurrently on as many streams for the throughput figure")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run plain copies of this many bytes")
     args = ap.parse_args()
     if args.copy_probe:
@@ -654,8 +661,33 @@ def main():
         n_pass_launches += st["passes"]
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms_serial = ev0.elapsed_time(ev1) / args.steps
     n_rays = tr.n_sets * cam["width"] * cam["height"]
+
+    # Throughput: frames in flight on as many streams, each with a context
+    # (workspace) and outputs of its own, so that the next frame's waves take
+    # the SIMDs an ending pass leaves idle.  The serial loop above gives the
+    # kernel times (no overlap) and one frame's latency.
+    nf = max(1, args.frames_in_flight)
+    ms = ms_serial
+    if nf > 1:
+        trs, outs, streams = [tr], [out], [stream]
+        for _ in range(nf - 1):
+            t2 = rt.Tracer(0)
+            t2.set_metric(wl["metric"])
+            t2.set_scene(wl["scene"])
+            trs.append(t2)
+            outs.append(t2.alloc_outputs(cam))
+            streams.append(torch.cuda.Stream())
+        for i in range(2 * nf):
+            trs[i % nf].trace_into(cam, rule, ms_steps, outs[i % nf], stream=streams[i % nf])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            trs[i % nf].trace_into(cam, rule, ms_steps, outs[i % nf], stream=streams[i % nf])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        print("[bench] %d frames in flight: %.3f ms per frame (serial %.3f)" % (nf, ms, ms_serial), flush=True)
 
     import numpy as np
     dfm = wl["metric"].get("deforms")
@@ -689,10 +721,12 @@ def main():
                    "anisotropic_bumps": int(wl["metric"]["abumps"].shape[1]) if "abumps" in wl["metric"] else 0,
                    "spheres": int(len(wl["scene"]["spheres"]))},
         "ray_steps_per_s": work["ray_steps"] / (ms / 1e3),
+        "frames_in_flight": nf, "frame_latency_ms": ms_serial,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, rule["pass_steps"]),
                      "kernel": "k_trace_pass", "flops_per_trace": flops,
                      "kernel_ms_per_launch": pass_ms / max(1, n_pass_launches),
+                     "frame_rate_tflops": flops / (ms / 1e3) / 1e12,
                      },
         "kernel_ms": {"passes": pass_ms / args.steps, "refine": refine_ms / args.steps,
                       "compaction": compact_ms / args.steps},

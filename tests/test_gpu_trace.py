@@ -247,6 +247,31 @@ def test_sign_invariance_bitwise(rt):
         assert np.array_equal(g1[k], g2[k]), k
 
 
+def test_concurrent_contexts_bitwise(rt):
+    """Frames in flight on two streams, each with its own context, equal a
+    frame traced alone bit for bit (the throughput figure traces this way)."""
+    import torch
+    say("two contexts on two streams, bumps16 320x180, 3 frames each")
+    wl = W.with_size(W.get("bumps16_1080p"), 320, 180)
+    ref = gpu_trace(rt, wl)
+    cam, rule = wl["camera"], wl["rule"]
+    trs, outs, streams = [], [], []
+    for _ in range(2):
+        tr = rt.Tracer(0)
+        tr.set_metric(wl["metric"])
+        tr.set_scene(wl["scene"])
+        trs.append(tr)
+        outs.append(tr.alloc_outputs(cam))
+        streams.append(torch.cuda.Stream())
+    for i in range(6):
+        trs[i % 2].trace_into(cam, rule, rule["max_steps"], outs[i % 2], stream=streams[i % 2])
+    torch.cuda.synchronize()
+    for o in outs:
+        g = {k: v.cpu().numpy() for k, v in o.items() if hasattr(v, "cpu")}
+        for k in ("hit", "t", "id", "dir", "steps"):
+            assert np.array_equal(g[k].reshape(ref[k].shape), ref[k]), k
+
+
 @pytest.mark.parametrize("grid,K,S", [("1", 16, 256), ("7", 4, 64), ("", 64, 16)])
 def test_deterministic_across_launch_shapes(rt, grid, K, S):
     """Per-lane 6-sigma selection and ordered bump walks make every ray's
